@@ -1,0 +1,601 @@
+/*
+ * lbaxi_oracle.c -- plain FP64 CPU oracle of the improved axisymmetric
+ * lattice Boltzmann scheme (Li, He, Tang, Tao, "Improved axisymmetric lattice
+ * Boltzmann scheme", arXiv:1003.0282).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file exists so that the GPU path can be
+ * checked against something slow and obviously correct.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or helper with the HIP library: every
+ * constant below is written out here from the paper.
+ *
+ * Conventions (all lattice units, dt = dx = c = 1, cs^2 = 1/3):
+ *   node (i, j): i = 0..nz-1 along z (axial), j = 0..nr-1 along r (radial),
+ *   r_j = r0 + j.  Array index of population a at node (i, j):
+ *   (a*nr + j)*nz + i.  The state held between steps is the pre-collision
+ *   population f^ (the paper's f-hat of Eq. 13) plus g (Eq. 53) and h.
+ *   tau, tau_g, tau_h are the paper's relaxation parameters (nu = tau/3,
+ *   omega0 = 1/(tau + 1/2), Sec. III A); callers holding the usual BGK
+ *   relaxation time tau_s convert with tau = tau_s - 1/2.
+ *
+ * What each function follows:
+ *   feq9         Eq. (6)                      D2Q9 equilibrium
+ *   geq4         Eq. (54)                     D2Q4 swirl equilibrium, rho -> rho0
+ *   heq4         temperature analogue of Eq. (54) (the paper defines no
+ *                temperature equation; this reading is an assumption)
+ *   node_macros  Eqs. (14)-(17) with mu -> mu0, body force added to F_i
+ *   node_source  Eq. (12) (+ centrifugal force rho0 u_th^2 / r, Sec. III C)
+ *   node_collide Eq. (13) for f, Eq. (53) for g, its analogue for h
+ *   stream       the left-hand side of Eq. (13) / (53): pull streaming, with
+ *                periodic ends, specular reflection on the axis (Sec. IV A),
+ *                halfway bounce-back / moving walls, free slip
+ *   residual     Eq. (57)
+ * At r = 0 every term carrying 1/r is taken as zero (Sec. IV A).
+ *
+ * Parity of the temperature row is unpinned by the paper (it defines no
+ * temperature scheme); its pins are closed-form conduction solutions.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- lattice (Eq. 6 and the D2Q4 set of Sec. III C) -------------------- */
+/* D2Q9 velocities, components (e_z, e_r). */
+static const int EZ9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int ER9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double W9[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
+                             1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+/* D2Q4 velocities: (1,0), (0,1), (-1,0), (0,-1); weights 1/4. */
+static const int EZ4[4] = {1, 0, -1, 0};
+static const int ER4[4] = {0, 1, 0, -1};
+
+/* Direction that has e reversed, e_r flipped, e_z flipped: found by search so
+ * that no hand-typed permutation table can hide a mistake. */
+static int find9(int ez, int er) {
+  for (int a = 0; a < 9; ++a)
+    if (EZ9[a] == ez && ER9[a] == er) return a;
+  return -1;
+}
+static int find4(int ez, int er) {
+  for (int a = 0; a < 4; ++a)
+    if (EZ4[a] == ez && ER4[a] == er) return a;
+  return -1;
+}
+static int opp9(int a) { return find9(-EZ9[a], -ER9[a]); }
+static int mirr9(int a) { return find9(EZ9[a], -ER9[a]); }
+static int mirz9(int a) { return find9(-EZ9[a], ER9[a]); }
+static int opp4(int a) { return find4(-EZ4[a], -ER4[a]); }
+static int mirr4(int a) { return find4(EZ4[a], -ER4[a]); }
+
+/* ---- parameters -------------------------------------------------------- */
+enum { ORC_AXIS = 0, ORC_WALL = 1, ORC_PERIODIC = 2, ORC_FREESLIP = 3 };
+
+typedef struct {
+  int kind;           /* ORC_AXIS / ORC_WALL / ORC_PERIODIC / ORC_FREESLIP */
+  double uz, ur;      /* wall velocity in the meridian plane */
+  double omega;       /* wall angular speed: u_theta at the wall = omega*r */
+  int thermal;        /* 0 adiabatic, 1 fixed temperature T */
+  double T;
+  double r_split;     /* z-walls only: second segment where r_j > r_split */
+  int kind2;          /* (r_split < 0 disables the second segment) */
+  double omega2;
+  int thermal2;
+  double T2;
+} orc_side;
+
+typedef struct {
+  int nz, nr;
+  double r0;          /* r_j = r0 + j; r0 = 0 puts the axis on node row 0 */
+  int swirl, thermal, cartesian;
+  double tau, tau_g, tau_h; /* paper convention */
+  double rho0;
+  double a0, period, phase; /* axial force density a(t) */
+  double gbeta, T_ref;      /* Boussinesq buoyancy rho0*g*beta*(T - T_ref) */
+  orc_side side[4];         /* 0 south (r = r0 - 1/2 or axis), 1 north,
+                               2 west (z = -1/2), 3 east (z = nz - 1/2) */
+} orc_params;
+
+typedef struct {
+  orc_params p;
+  double *f, *g, *h;    /* state f^(t), g(t), h(t) */
+  double *fs, *gs, *hs; /* post-collision f*, g*, h* (step scratch) */
+  double *spd;          /* |u| at the previous time level */
+  int have_spd;
+  int64_t t;
+} orc_state;
+
+/* ---- small helpers ------------------------------------------------------ */
+static double r_of(const orc_params* p, int j) { return p->r0 + (double)j; }
+/* 1/r, taken as zero on the axis and in the planar (Cartesian) test mode. */
+static double inv_r(const orc_params* p, int j) {
+  double r = r_of(p, j);
+  if (p->cartesian || r <= 0.0) return 0.0;
+  return 1.0 / r;
+}
+/* Thread the row loops only when the lattice is big enough to pay for it. */
+static int par_ok(const orc_params* p) {
+  return (long)p->nz * (long)p->nr >= 16384;
+}
+static int is_axis_row(const orc_params* p, int j) {
+  return j == 0 && p->side[0].kind == ORC_AXIS;
+}
+static size_t IDX(const orc_params* p, int a, int j, int i) {
+  return ((size_t)a * (size_t)p->nr + (size_t)j) * (size_t)p->nz + (size_t)i;
+}
+
+/* Axial force density at integer time t (periodic when period > 0). */
+double orc_force_a(const orc_params* p, int64_t t) {
+  if (p->period > 0.0)
+    return p->a0 * cos(2.0 * M_PI * (double)t / p->period + p->phase);
+  return p->a0;
+}
+
+/* ---- equilibria ----------------------------------------------------------- */
+/* Eq. (6): f_eq = w rho [1 + e.u/cs^2 + (e.u)^2/(2 cs^4) - u^2/(2 cs^2)]. */
+void orc_feq9(double rho, double uz, double ur, double* out) {
+  const double cs2 = 1.0 / 3.0;
+  double uu = uz * uz + ur * ur;
+  for (int a = 0; a < 9; ++a) {
+    double eu = EZ9[a] * uz + ER9[a] * ur;
+    out[a] = W9[a] * rho *
+             (1.0 + eu / cs2 + eu * eu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+  }
+}
+
+/* Eq. (54): g_eq = (rho u_th / 4)[1 + 2 e.u / c^2]; rho -> rho0 (Sec. III C). */
+void orc_geq4(double rho0, double uth, double uz, double ur, double* out) {
+  for (int a = 0; a < 4; ++a) {
+    double eu = EZ4[a] * uz + ER4[a] * ur;
+    out[a] = rho0 * uth / 4.0 * (1.0 + 2.0 * eu);
+  }
+}
+
+/* Temperature equilibrium built like Eq. (54) with T in place of rho0*u_th. */
+void orc_heq4(double T, double uz, double ur, double* out) {
+  for (int a = 0; a < 4; ++a) {
+    double eu = EZ4[a] * uz + ER4[a] * ur;
+    out[a] = T / 4.0 * (1.0 + 2.0 * eu);
+  }
+}
+
+/* ---- macroscopic variables (Eqs. 14-17) ----------------------------------
+ * Eq. (15) with the force split as F_i = G_i - 2 mu0 u_i delta_ir / r^2, where
+ * G = (a(t) + rho0 g beta (T - T_ref), rho0 u_th^2 / r) holds every part of
+ * the force that does not depend on (u_z, u_r).  Multiplying Eq. (14) by u_i
+ * and subtracting it from Eq. (15) gives
+ *     u_i (sum f + mu0 delta_ir / r^2) = sum e_i f + G_i / 2,
+ * which is Eq. (16) with the body force added; Eq. (17) is unchanged.
+ * out = {rho, u_z, u_r, u_th, T}.  g_in must already carry the axis
+ * substitution (see node_axis_g) when j is the axis row.                    */
+void orc_node_macros(const orc_params* p, int j, int64_t t, const double* fh,
+                     const double* g, const double* h, double* out) {
+  double ir = inv_r(p, j);
+  double mu0 = p->rho0 * p->tau / 3.0; /* mu = tau rho cs^2 dt, Eq. (36) */
+  double s0 = 0, sz = 0, sr = 0;
+  for (int a = 0; a < 9; ++a) {
+    s0 += fh[a];
+    sz += EZ9[a] * fh[a];
+    sr += ER9[a] * fh[a];
+  }
+  double uth = 0.0, T = p->T_ref;
+  if (p->swirl) {
+    double sg = 0;
+    for (int a = 0; a < 4; ++a) sg += g[a];
+    uth = is_axis_row(p, j) ? 0.0 : sg / p->rho0; /* u_th = sum g / rho0 */
+  }
+  if (p->thermal) {
+    T = 0;
+    for (int a = 0; a < 4; ++a) T += h[a];
+  }
+  double Gz = orc_force_a(p, t);
+  if (p->thermal) Gz += p->rho0 * p->gbeta * (T - p->T_ref);
+  double Gr = p->swirl ? p->rho0 * uth * uth * ir : 0.0;
+  double ur = (sr + 0.5 * Gr) / (s0 + mu0 * ir * ir); /* Eq. (16), i = r */
+  double rho = s0 / (1.0 + 0.5 * ur * ir);           /* Eq. (17) */
+  double uz = (sz + 0.5 * Gz) / s0;                   /* Eq. (16), i = z */
+  out[0] = rho;
+  out[1] = uz;
+  out[2] = ur;
+  out[3] = uth;
+  out[4] = T;
+}
+
+/* Eq. (12): S_a = [(e_ai - u_i) F_i / (rho cs^2) - u_r / r] f_eq_a with
+ * F_r = -2 mu0 u_r / r^2 + rho0 u_th^2 / r and F_z = a(t) (+ buoyancy). */
+void orc_node_source(const orc_params* p, int j, int64_t t, const double* m,
+                     const double* feq, double* S) {
+  double ir = inv_r(p, j);
+  double mu0 = p->rho0 * p->tau / 3.0;
+  const double cs2 = 1.0 / 3.0;
+  double rho = m[0], uz = m[1], ur = m[2], uth = m[3], T = m[4];
+  double Fz = orc_force_a(p, t);
+  if (p->thermal) Fz += p->rho0 * p->gbeta * (T - p->T_ref);
+  double Fr = -2.0 * mu0 * ur * ir * ir;
+  if (p->swirl) Fr += p->rho0 * uth * uth * ir;
+  for (int a = 0; a < 9; ++a) {
+    double eF = (EZ9[a] - uz) * Fz + (ER9[a] - ur) * Fr;
+    S[a] = (eF / (rho * cs2) - ur * ir) * feq[a];
+  }
+}
+
+/* Axis treatment of g (non-equilibrium extrapolation, Sec. IV B): the swirl
+ * population on the axis node becomes the non-equilibrium part of its radial
+ * neighbour, g(i,0) = g(i,1) - g_eq(i,1), with row-1 macros at the same time
+ * level; u_th vanishes on the axis. */
+static void node_axis_g(const orc_params* p, int64_t t, const double* f1,
+                        const double* g1, const double* h1, double* g0) {
+  double m1[5], geq1[4];
+  orc_node_macros(p, 1, t, f1, g1, h1, m1);
+  orc_geq4(p->rho0, m1[3], m1[1], m1[2], geq1);
+  for (int a = 0; a < 4; ++a) g0[a] = g1[a] - geq1[a];
+}
+
+/* Eq. (13) for f, Eq. (53) for g and the analogous rule for h, at one node.
+ * Inputs are the pre-collision populations (g already axis-substituted);
+ * outputs are the post-collision populations and the macros m[5].          */
+void orc_node_collide(const orc_params* p, int j, int64_t t, const double* fh,
+                      const double* g, const double* h, double* fo, double* go,
+                      double* ho, double* m) {
+  double ir = inv_r(p, j);
+  orc_node_macros(p, j, t, fh, g, h, m);
+  double rho = m[0], uz = m[1], ur = m[2], uth = m[3], T = m[4];
+  double feq[9], S[9];
+  orc_feq9(rho, uz, ur, feq);
+  orc_node_source(p, j, t, m, feq, S);
+  for (int a = 0; a < 9; ++a) {
+    /* omega_f = [1 + tau e_ar / r] / (tau + 0.5), after Eq. (13) */
+    double w = (1.0 + p->tau * ER9[a] * ir) / (p->tau + 0.5);
+    fo[a] = fh[a] - w * (fh[a] - feq[a]) + (1.0 - 0.5 * w) * S[a];
+  }
+  if (p->swirl) {
+    double geq[4];
+    orc_geq4(p->rho0, uth, uz, ur, geq);
+    double nu = p->tau_g / 2.0; /* nu = tau_g c^2 / 2 */
+    for (int a = 0; a < 4; ++a) {
+      double w = (1.0 + p->tau_g * ER4[a] * ir) / (p->tau_g + 0.5);
+      double Sg = -ir * (2.0 * ur + nu * ir) * geq[a]; /* Eq. (54) */
+      go[a] = g[a] - w * (g[a] - geq[a]) + Sg;
+    }
+  }
+  if (p->thermal) {
+    double heq[4];
+    orc_heq4(T, uz, ur, heq);
+    for (int a = 0; a < 4; ++a) {
+      double w = (1.0 + p->tau_h * ER4[a] * ir) / (p->tau_h + 0.5);
+      double Sh = -ur * ir * heq[a];
+      ho[a] = h[a] - w * (h[a] - heq[a]) + Sh;
+    }
+  }
+}
+
+/* ---- boundaries ------------------------------------------------------------
+ * A wall lies half a lattice spacing outside the last fluid node.  A
+ * population whose upstream node lies outside the domain takes the rule of the
+ * boundary it crossed; a z-end is checked before the radial sides. */
+typedef struct { int kind; double omega; int thermal; double T; } seg_t;
+
+static seg_t zwall_segment(const orc_params* p, const orc_side* s, int j) {
+  seg_t sg;
+  if (s->r_split >= 0.0 && r_of(p, j) > s->r_split) {
+    sg.kind = s->kind2; sg.omega = s->omega2; sg.thermal = s->thermal2;
+    sg.T = s->T2;
+  } else {
+    sg.kind = s->kind; sg.omega = s->omega; sg.thermal = s->thermal;
+    sg.T = s->T;
+  }
+  return sg;
+}
+
+/* Moving-wall bounce-back term 6 w_a rho0 (e_a . u_w). */
+static double wall_term9(const orc_params* p, const orc_side* s, int a) {
+  return 6.0 * W9[a] * p->rho0 * (EZ9[a] * s->uz + ER9[a] * s->ur);
+}
+
+static double pull_f(const orc_params* p, const double* fs, int i, int j,
+                     int a) {
+  int iz = i - EZ9[a], jr = j - ER9[a];
+  if (iz < 0 || iz >= p->nz) {
+    const orc_side* s = &p->side[iz < 0 ? 2 : 3];
+    if (s->kind == ORC_PERIODIC) {
+      iz = (iz + p->nz) % p->nz;
+    } else {
+      seg_t sg = zwall_segment(p, s, j);
+      if (sg.kind == ORC_FREESLIP) {
+        /* specular reflection on the z-end: arrives from (i, j - e_r) with
+         * e_z reversed */
+        int j2 = j - ER9[a], b = mirz9(a);
+        if (j2 >= 0 && j2 < p->nr) return fs[IDX(p, b, j2, i)];
+        if (j2 < 0 && p->side[0].kind == ORC_AXIS)
+          return fs[IDX(p, mirr9(b), 1, i)];
+        return fs[IDX(p, opp9(a), j, i)];
+      }
+      return fs[IDX(p, opp9(a), j, i)] + wall_term9(p, s, a);
+    }
+  }
+  if (jr < 0) {
+    const orc_side* s = &p->side[0];
+    if (s->kind == ORC_AXIS) /* ghost (iz,-1) is the mirror image of (iz,1) */
+      return fs[IDX(p, mirr9(a), 1, iz)];
+    return fs[IDX(p, opp9(a), j, i)] + wall_term9(p, s, a);
+  }
+  if (jr >= p->nr) {
+    const orc_side* s = &p->side[1];
+    return fs[IDX(p, opp9(a), j, i)] + wall_term9(p, s, a);
+  }
+  return fs[IDX(p, a, jr, iz)];
+}
+
+static double pull_g(const orc_params* p, const double* gs, int i, int j,
+                     int a) {
+  int iz = i - EZ4[a], jr = j - ER4[a];
+  if (iz < 0 || iz >= p->nz) {
+    const orc_side* s = &p->side[iz < 0 ? 2 : 3];
+    if (s->kind == ORC_PERIODIC) {
+      iz = (iz + p->nz) % p->nz;
+    } else {
+      seg_t sg = zwall_segment(p, s, j);
+      if (sg.kind == ORC_FREESLIP) return gs[IDX(p, opp4(a), j, i)];
+      /* anti-bounce-back, rho0 u_th = rho0 omega r at the wall */
+      return -gs[IDX(p, opp4(a), j, i)] + 0.5 * p->rho0 * sg.omega * r_of(p, j);
+    }
+  }
+  if (jr < 0) {
+    const orc_side* s = &p->side[0];
+    if (s->kind == ORC_AXIS) return 0.0; /* replaced on the axis, see above */
+    double rw = p->r0 - 0.5;
+    return -gs[IDX(p, opp4(a), j, i)] + 0.5 * p->rho0 * s->omega * rw;
+  }
+  if (jr >= p->nr) {
+    const orc_side* s = &p->side[1];
+    double rw = p->r0 + (double)p->nr - 0.5;
+    return -gs[IDX(p, opp4(a), j, i)] + 0.5 * p->rho0 * s->omega * rw;
+  }
+  return gs[IDX(p, a, jr, iz)];
+}
+
+static double pull_h(const orc_params* p, const double* hs, int i, int j,
+                     int a) {
+  int iz = i - EZ4[a], jr = j - ER4[a];
+  if (iz < 0 || iz >= p->nz) {
+    const orc_side* s = &p->side[iz < 0 ? 2 : 3];
+    if (s->kind == ORC_PERIODIC) {
+      iz = (iz + p->nz) % p->nz;
+    } else {
+      seg_t sg = zwall_segment(p, s, j);
+      if (sg.kind == ORC_WALL && sg.thermal)
+        return -hs[IDX(p, opp4(a), j, i)] + 0.5 * sg.T;
+      return hs[IDX(p, opp4(a), j, i)]; /* adiabatic */
+    }
+  }
+  if (jr < 0) {
+    const orc_side* s = &p->side[0];
+    if (s->kind == ORC_AXIS) return hs[IDX(p, mirr4(a), 1, iz)];
+    if (s->thermal) return -hs[IDX(p, opp4(a), j, i)] + 0.5 * s->T;
+    return hs[IDX(p, opp4(a), j, i)];
+  }
+  if (jr >= p->nr) {
+    const orc_side* s = &p->side[1];
+    if (s->thermal) return -hs[IDX(p, opp4(a), j, i)] + 0.5 * s->T;
+    return hs[IDX(p, opp4(a), j, i)];
+  }
+  return hs[IDX(p, a, jr, iz)];
+}
+
+/* ---- state management ------------------------------------------------------ */
+static size_t nodes(const orc_params* p) {
+  return (size_t)p->nz * (size_t)p->nr;
+}
+
+orc_state* orc_create(const orc_params* p) {
+  orc_state* s = (orc_state*)calloc(1, sizeof(orc_state));
+  if (!s) return NULL;
+  s->p = *p;
+  size_t n = nodes(p);
+  s->f = (double*)calloc(9 * n, sizeof(double));
+  s->fs = (double*)calloc(9 * n, sizeof(double));
+  s->g = (double*)calloc(4 * n, sizeof(double));
+  s->gs = (double*)calloc(4 * n, sizeof(double));
+  s->h = (double*)calloc(4 * n, sizeof(double));
+  s->hs = (double*)calloc(4 * n, sizeof(double));
+  s->spd = (double*)calloc(n, sizeof(double));
+  if (!s->f || !s->fs || !s->g || !s->gs || !s->h || !s->hs || !s->spd) {
+    free(s->f); free(s->fs); free(s->g); free(s->gs); free(s->h);
+    free(s->hs); free(s->spd); free(s);
+    return NULL;
+  }
+  return s;
+}
+
+void orc_destroy(orc_state* s) {
+  if (!s) return;
+  free(s->f); free(s->fs); free(s->g); free(s->gs); free(s->h);
+  free(s->hs); free(s->spd); free(s);
+}
+
+int64_t orc_time(const orc_state* s) { return s->t; }
+
+/* Gather the populations of node (i, j) from the state arrays. */
+static void gather(const orc_state* s, int i, int j, double* f, double* g,
+                   double* h) {
+  const orc_params* p = &s->p;
+  for (int a = 0; a < 9; ++a) f[a] = s->f[IDX(p, a, j, i)];
+  for (int a = 0; a < 4; ++a) {
+    g[a] = p->swirl ? s->g[IDX(p, a, j, i)] : 0.0;
+    h[a] = p->thermal ? s->h[IDX(p, a, j, i)] : 0.0;
+  }
+}
+
+/* Populations at (i, j) ready for the macros: on the axis row the swirl
+ * populations are replaced by the extrapolated ones. */
+static void node_inputs(const orc_state* s, int i, int j, double* f, double* g,
+                        double* h) {
+  gather(s, i, j, f, g, h);
+  if (s->p.swirl && is_axis_row(&s->p, j)) {
+    double f1[9], g1[4], h1[4];
+    gather(s, i, 1, f1, g1, h1);
+    node_axis_g(&s->p, s->t, f1, g1, h1, g);
+  }
+}
+
+/* Equilibrium seeding: f^ = f_eq(rho0, u) - S(rho0, u)/2 (the paper's
+ * f^ = f - Omega/2 - S/2 with Omega = 0), g = g_eq, h = h_eq.  NULL fields
+ * mean zero velocity / T_ref.  On the axis row u_r and u_th are forced to 0. */
+void orc_seed(orc_state* s, const double* uz, const double* ur,
+              const double* uth, const double* T) {
+  const orc_params* p = &s->p;
+  s->t = 0;
+  s->have_spd = 0;
+  for (int j = 0; j < p->nr; ++j)
+    for (int i = 0; i < p->nz; ++i) {
+      size_t n = (size_t)j * p->nz + i;
+      double m[5];
+      m[0] = p->rho0;
+      m[1] = uz ? uz[n] : 0.0;
+      m[2] = ur ? ur[n] : 0.0;
+      m[3] = (uth && p->swirl) ? uth[n] : 0.0;
+      m[4] = (T && p->thermal) ? T[n] : p->T_ref;
+      if (is_axis_row(p, j)) { m[2] = 0.0; m[3] = 0.0; }
+      double feq[9], S[9], geq[4], heq[4];
+      orc_feq9(m[0], m[1], m[2], feq);
+      orc_node_source(p, j, 0, m, feq, S);
+      for (int a = 0; a < 9; ++a) s->f[IDX(p, a, j, i)] = feq[a] - 0.5 * S[a];
+      if (p->swirl) {
+        orc_geq4(p->rho0, m[3], m[1], m[2], geq);
+        for (int a = 0; a < 4; ++a) s->g[IDX(p, a, j, i)] = geq[a];
+      }
+      if (p->thermal) {
+        orc_heq4(m[4], m[1], m[2], heq);
+        for (int a = 0; a < 4; ++a) s->h[IDX(p, a, j, i)] = heq[a];
+      }
+    }
+}
+
+/* Macroscopic fields of the current state; any output may be NULL. */
+void orc_macros(const orc_state* s, double* rho, double* uz, double* ur,
+                double* uth, double* T) {
+  const orc_params* p = &s->p;
+#pragma omp parallel for schedule(static) if (par_ok(p))
+  for (int j = 0; j < p->nr; ++j)
+    for (int i = 0; i < p->nz; ++i) {
+      double f[9], g[4], h[4], m[5];
+      size_t n = (size_t)j * p->nz + i;
+      node_inputs(s, i, j, f, g, h);
+      orc_node_macros(p, j, s->t, f, g, h, m);
+      if (rho) rho[n] = m[0];
+      if (uz) uz[n] = m[1];
+      if (ur) ur[n] = m[2];
+      if (uth) uth[n] = m[3];
+      if (T) T[n] = m[4];
+    }
+}
+
+/* Streaming of the post-collision arrays into the state arrays. */
+static void stream_all(orc_state* s) {
+  const orc_params* p = &s->p;
+#pragma omp parallel for schedule(static) if (par_ok(p))
+  for (int j = 0; j < p->nr; ++j)
+    for (int i = 0; i < p->nz; ++i) {
+      for (int a = 0; a < 9; ++a) s->f[IDX(p, a, j, i)] = pull_f(p, s->fs, i, j, a);
+      if (p->swirl)
+        for (int a = 0; a < 4; ++a) s->g[IDX(p, a, j, i)] = pull_g(p, s->gs, i, j, a);
+      if (p->thermal)
+        for (int a = 0; a < 4; ++a) s->h[IDX(p, a, j, i)] = pull_h(p, s->hs, i, j, a);
+    }
+}
+
+/* n time steps t -> t + n: collide every node (Eqs. 12-17, 53-54), then
+ * stream.  The speed |u| of each collided level is kept for Eq. (57). */
+void orc_step(orc_state* s, int64_t n) {
+  const orc_params* p = &s->p;
+  for (int64_t k = 0; k < n; ++k) {
+#pragma omp parallel for schedule(static) if (par_ok(p))
+    for (int j = 0; j < p->nr; ++j)
+      for (int i = 0; i < p->nz; ++i) {
+        double f[9], g[4], h[4], fo[9], go[4], ho[4], m[5];
+        node_inputs(s, i, j, f, g, h);
+        orc_node_collide(p, j, s->t, f, g, h, fo, go, ho, m);
+        for (int a = 0; a < 9; ++a) s->fs[IDX(p, a, j, i)] = fo[a];
+        if (p->swirl)
+          for (int a = 0; a < 4; ++a) s->gs[IDX(p, a, j, i)] = go[a];
+        if (p->thermal)
+          for (int a = 0; a < 4; ++a) s->hs[IDX(p, a, j, i)] = ho[a];
+        s->spd[(size_t)j * p->nz + i] = sqrt(m[1] * m[1] + m[2] * m[2]);
+      }
+    s->have_spd = 1;
+    stream_all(s);
+    s->t += 1;
+  }
+}
+
+/* Eq. (57): max over nodes of | |u|(t) - |u|(t-1) |, t the current level.
+ * Returns NaN when any node holds a NaN, and -1 when no previous level is
+ * known (no step taken since seeding or loading). */
+double orc_residual(const orc_state* s) {
+  const orc_params* p = &s->p;
+  if (!s->have_spd) return -1.0;
+  double res = 0.0;
+  int bad = 0;
+  for (int j = 0; j < p->nr; ++j)
+    for (int i = 0; i < p->nz; ++i) {
+      double f[9], g[4], h[4], m[5];
+      node_inputs(s, i, j, f, g, h);
+      orc_node_macros(p, j, s->t, f, g, h, m);
+      double d = fabs(sqrt(m[1] * m[1] + m[2] * m[2]) -
+                      s->spd[(size_t)j * p->nz + i]);
+      if (d != d) bad = 1;
+      else if (d > res) res = d;
+    }
+  return bad ? NAN : res;
+}
+
+/* Raw state access for the tests (pre-collision f^, g, h at time t). */
+void orc_get_state(const orc_state* s, double* f, double* g, double* h) {
+  size_t n = nodes(&s->p);
+  if (f) memcpy(f, s->f, 9 * n * sizeof(double));
+  if (g) memcpy(g, s->g, 4 * n * sizeof(double));
+  if (h) memcpy(h, s->h, 4 * n * sizeof(double));
+}
+
+void orc_set_state(orc_state* s, const double* f, const double* g,
+                   const double* h, int64_t t) {
+  size_t n = nodes(&s->p);
+  if (f) memcpy(s->f, f, 9 * n * sizeof(double));
+  if (g) memcpy(s->g, g, 4 * n * sizeof(double));
+  if (h) memcpy(s->h, h, 4 * n * sizeof(double));
+  s->t = t;
+  s->have_spd = 0;
+}
+
+/* Streaming alone, exposed for the permutation tests: state <- stream(in). */
+void orc_stream_only(orc_state* s, const double* fs, const double* gs,
+                     const double* hs) {
+  size_t n = nodes(&s->p);
+  memcpy(s->fs, fs, 9 * n * sizeof(double));
+  if (gs) memcpy(s->gs, gs, 4 * n * sizeof(double));
+  if (hs) memcpy(s->hs, hs, 4 * n * sizeof(double));
+  stream_all(s);
+}
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int orc_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* Layout probe for the ctypes mirror of orc_params. */
+size_t orc_sizeof_params(void) { return sizeof(orc_params); }
