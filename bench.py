@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the improved axisymmetric LB hot path on one GPU.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME]
+
+A step is one time step of every lattice of the workload (pull streaming with
+the boundary rules, macros, collision of f, g and h as the workload has
+them), run through the C-ABI library.  The timed region is exactly K steps
+between two device synchronisations, inputs resident in HBM.  Prints one JSON
+line with MLUPS, the HBM-roofline fraction of the step kernel and the CPU
+oracle timed on a bounded sample of the same workload.
+
+Workloads (synthetic, seeded):
+  batch256   256 rotating-lid cavities, Nr ~ U{64..512}, H/R ~ U[1,3],
+             Re ~ U[500,2500], FP32 f + g, one launch per step (default)
+  pipe_fp32 / pipe_fp64   16384 x 2048 body-force pipe, f only
+  womersley  64 x 128 Womersley pipe, FP32
+  cavity     256 x 384 rotating-lid cavity at Re 990, FP32 f + g
+  melt512    512 crystal/crucible melts 128 x 256, FP32 f + g + h
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def workload(name: str):
+    from paper_1003_0282_amd import workloads as W
+    if name == "batch256":
+        return W.batch_cavities(256, seed=0), 1, "256 rotating-lid cavities (seed 0), FP32 f+g"
+    if name == "pipe_fp32":
+        return [W.roofline_pipe()], 1, "16384x2048 body-force pipe, FP32 f"
+    if name == "pipe_fp64":
+        return [W.roofline_pipe()], 0, "16384x2048 body-force pipe, FP64 f"
+    if name == "womersley":
+        return [W.womersley()], 1, "Womersley pipe 64x128, FP32 f"
+    if name == "cavity":
+        return [W.cavity(256, 384, 990.0)], 1, "rotating-lid cavity 256x384 Re 990, FP32 f+g"
+    if name == "melt512":
+        return W.melt_set(512, seed=1), 1, "512 crystal/crucible melts 128x256, FP32 f+g+h"
+    raise SystemExit("unknown workload %r" % name)
+
+
+def bytes_per_update(case, prec):
+    es = 8 if prec == 0 else 4
+    q = 9 + (4 if case.get("swirl") else 0) + (4 if case.get("thermal") else 0)
+    return 2 * q * es  # every population read once and written once
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_1003_0282_amd", "csrc")
+    for f in sorted(os.listdir(src)):
+        if f.startswith("lbaxi"):
+            h.update(open(os.path.join(src, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_entry(name: str, per_launch_algo: float):
+    """HBM bytes per launch from committed rocprofv3 counter summaries of this
+    exact kernel source, or None."""
+    p = os.path.join(ROOT, "profiles", "traffic_%s.json" % name)
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return float(d["hbm_bytes_per_launch"])
+
+
+def cpu_baseline(cases, seconds: float):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    from oracle import oracle as O
+    O.build()
+    done = 0
+    used = []
+    t0 = time.perf_counter()
+    k = 0
+    while time.perf_counter() - t0 < seconds and k < len(cases):
+        c = cases[k]
+        o = O.Oracle(c)
+        o.seed()
+        steps = 0
+        t1 = time.perf_counter()
+        while steps < 200 and time.perf_counter() - t0 < seconds:
+            o.step(5)
+            steps += 5
+        done += steps * c["nz"] * c["nr"]
+        used.append("%s x%d steps" % (c.get("name", "case"), steps))
+        del o
+        k += 1
+    el = time.perf_counter() - t0
+    return {"value": done / el / 1e6, "unit": "MLUPS", "cores": O.get_threads(),
+            "kind": "oracle",
+            "sample": "%d of %d lattices, %d node updates in %.1f s (%s)" % (
+                k, len(cases), done, el, "; ".join(used[:4]) + (" ..." if len(used) > 4 else ""))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="batch256")
+    ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--launch", default="", help="tile_z,tile_r,grid,xcd,nt (skips autotune)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the workload is a single-GPU batch and no "
+              "multi-GPU path is built (asked for --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1003_0282_amd import lbaxi as L
+
+    cases, prec, label = workload(args.workload)
+    torch.cuda.set_device(0)
+    lat = L.Lattices(cases, prec)
+    lat.seed()
+    tuned = None
+    if args.launch:
+        cfg = [int(x) for x in args.launch.split(",")]
+        lat.set_launch(*cfg)
+    elif args.autotune:
+        tuned = lat.autotune(steps_per_trial=max(4, min(50, args.warmup // 8)))
+    launch = lat.get_launch()
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    stream = lat.stream
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    lat.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    ms_step = ms / args.steps
+    nodes = lat.nodes
+    mlups = nodes * args.steps / (ms / 1e3) / 1e6
+    bpu = bytes_per_update(cases[0], prec)
+    algo = bpu * nodes  # bytes per launch of the step kernel
+    achieved = algo / (ms_step / 1e3) / 1e9
+    tr = traffic_entry(args.workload, algo)
+    res = lat.residual()
+    finite = bool(all(r == r and r < 1e30 for r in res))
+    out = {
+        "metric": "MLUPS (lattice node updates per second) and fraction of HBM peak",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 0 else "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": label, "lattices": len(cases),
+                   "nodes": nodes, "bytes_per_update": bpu,
+                   "bytes_per_update_f_only_convention": 144 if prec == 0 else 72,
+                   "launch": {"tile_z": launch[0], "tile_r": launch[1], "grid": launch[2],
+                              "xcd_aware": launch[3], "nt_store": launch[4],
+                              "autotuned": tuned is not None}},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": tr, "kernel": "k_step (fused stream+collide)",
+                     "algorithmic_bytes_per_launch": algo},
+        "state_finite": finite,
+    }
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(cases, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,1195 @@
+// lbaxi.hip -- kernels and host runtime behind include/lbaxi.h.
+//
+// One fused kernel advances every lattice of a handle by one time step:
+// each thread owns one node, pulls its 9 (+4 +4) populations from the
+// post-collision buffer of the previous step applying the boundary rules,
+// computes the macros of Eqs. (16)-(17), collides with Eqs. (12)-(13) and
+// (53)-(54), and writes its populations to the other buffer at its own
+// address.  Work is described by a tile table {instance, z0, r0, interior}
+// so that hundreds of uneven lattices share one (optionally persistent)
+// launch; runs are replayed from HIP graphs of K steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lbaxi.h"
+#include "lbaxi_device.hpp"
+
+using namespace lbx;
+
+// ============================================================================
+// kernels
+// ============================================================================
+
+struct Tile {
+  int inst, z0, r0, interior;
+};
+
+struct TileRange {
+  int start, end, stride;
+};
+
+// Tiles handled by this workgroup.  With xcd_aware the grid is split into 8
+// interleaved groups (workgroup b runs on XCD b % 8), each walking its own
+// contiguous band of tiles so that neighbouring tiles share one L2.
+__device__ inline TileRange tile_range(int ntiles, int xcd) {
+  TileRange t;
+  const int G = gridDim.x, b = blockIdx.x;
+  if (xcd && G >= 8 && (G & 7) == 0) {
+    const int x = b & 7, q = G >> 3;
+    t.start = (int)((long long)ntiles * x / 8) + (b >> 3);
+    t.end = (int)((long long)ntiles * (x + 1) / 8);
+    t.stride = q;
+  } else {
+    t.start = b;
+    t.end = ntiles;
+    t.stride = G;
+  }
+  return t;
+}
+
+template <typename R>
+struct StepArgs {
+  const InstP* ip;
+  const Tile* tiles;
+  const int* ntiles;
+  const R* src;
+  R* dst;
+  R* spd;
+  const long long* tdev;  // time base in device memory (graph replays) or NULL
+  long long t0;           // time level when tdev is NULL
+  int k;                  // step index inside a graph
+  int mode;               // MODE_PRE | MODE_SPEED
+  int tzlog;              // log2 of tile_z
+  int tr;
+  int xcd;
+  int nt_store;
+};
+
+template <typename R>
+__device__ inline void st(R* p, R v, int nt) {
+  if (nt)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+template <typename R, int F>
+__global__ void __launch_bounds__(1024) k_step(StepArgs<R> A) {
+  const long long t = A.tdev ? (*A.tdev + A.k) : A.t0;
+  const int ntiles = *A.ntiles;
+  const TileRange tr = tile_range(ntiles, A.xcd);
+  const int tz = 1 << A.tzlog;
+  const int li = threadIdx.x & (tz - 1), lj = threadIdx.x >> A.tzlog;
+  const bool pre = A.mode & MODE_PRE;
+  for (int ti = tr.start; ti < tr.end; ti += tr.stride) {
+    const Tile T = A.tiles[ti];
+    const InstP& P = A.ip[T.inst];
+    const int i = T.z0 + li, j = T.r0 + lj;
+    if (i >= P.nz || j >= P.nr) continue;
+    const PR<R> p = make_pr<R>(P, t);
+    const R* s = A.src + P.off;
+    R f[9], g[4], h[4];
+    load_node<R, F>(P, s, i, j, T.interior != 0, pre, f, g, h);
+    const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
+    if ((F & F_SWIRL) && axis_row) {
+      // non-equilibrium extrapolation of g from row 1 (Sec. IV B)
+      R f1[9], g1[4], h1[4];
+      load_node<R, F>(P, s, i, 1, false, pre, f1, g1, h1);
+      const Mac<R> m1 = macros<R, F>(p, 1, false, f1, g1, h1);
+      const R q = (R)0.25 * p.rho0 * m1.uth;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        g[a] = g1[a] - q * ((R)1 + (R)2 * ((R)ez4(a) * m1.uz + (R)er4(a) * m1.ur));
+    }
+    const Mac<R> m = macros<R, F>(p, j, axis_row, f, g, h);
+    collide<R, F>(p, m, f, g, h);
+    R* d = A.dst + P.off;
+    const int pl = P.plane, o = j * P.nz + i;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) st(d + a * pl + o, f[a], A.nt_store);
+    if (F & F_SWIRL) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) st(d + (9 + a) * pl + o, g[a], A.nt_store);
+    }
+    if (F & F_THERMAL) {
+      const int hb = (F & F_SWIRL) ? 13 : 9;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) st(d + (hb + a) * pl + o, h[a], A.nt_store);
+    }
+    if (A.mode & MODE_SPEED) A.spd[P.off_fld + o] = sqrt(m.uz * m.uz + m.ur * m.ur);
+  }
+}
+
+// Equilibrium seeding: f^ = f_eq - S/2 at rho = rho0, g = g_eq, h = h_eq.
+template <typename R, int F>
+__global__ void __launch_bounds__(1024) k_seed(const InstP* ip, const Tile* tiles,
+                                               const int* ntiles, R* buf, const R* uz_in,
+                                               const R* ur_in, const R* uth_in, const R* T_in,
+                                               int tzlog) {
+  const int ti = blockIdx.x;
+  if (ti >= *ntiles) return;
+  const Tile T = tiles[ti];
+  const InstP& P = ip[T.inst];
+  const int tz = 1 << tzlog;
+  const int i = T.z0 + (threadIdx.x & (tz - 1)), j = T.r0 + (threadIdx.x >> tzlog);
+  if (i >= P.nz || j >= P.nr) return;
+  const PR<R> p = make_pr<R>(P, 0);
+  const long long fo = P.off_fld + (long long)j * P.nz + i;
+  const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
+  const R uz = uz_in ? uz_in[fo] : (R)0;
+  const R ur = (ur_in && !axis_row) ? ur_in[fo] : (R)0;
+  const R uth = ((F & F_SWIRL) && uth_in && !axis_row) ? uth_in[fo] : (R)0;
+  const R dT = ((F & F_THERMAL) && T_in) ? T_in[fo] - p.T_ref : (R)0;
+  const R ir = inv_radius(p, j);
+  R Fz = p.a_t;
+  if (F & F_THERMAL) Fz += p.rho0 * p.gbeta * dT;
+  R Fr = -(R)2 * p.mu0 * ur * ir * ir;
+  if (F & F_SWIRL) Fr += p.rho0 * uth * uth * ir;
+  const R usq = uz * uz + ur * ur;
+  R* d = buf + P.off;
+  const int pl = P.plane, o = j * P.nz + i;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    const R ez = (R)ez9(a), er = (R)er9(a), w = (R)w9(a);
+    const R eu = ez * uz + er * ur;
+    const R Pa = (R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * usq;
+    const R S = w * ((R)1 + Pa) * ((R)3 * ((ez - uz) * Fz + (er - ur) * Fr) - p.rho0 * ur * ir);
+    d[a * pl + o] = w * p.rho0 * Pa - (R)0.5 * S;
+  }
+  if (F & F_SWIRL) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      d[(9 + a) * pl + o] =
+          (R)0.25 * p.rho0 * uth * ((R)1 + (R)2 * ((R)ez4(a) * uz + (R)er4(a) * ur));
+  }
+  if (F & F_THERMAL) {
+    const int hb = (F & F_SWIRL) ? 13 : 9;
+    const R Tv = p.T_ref + dT;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      d[(hb + a) * pl + o] =
+          (R)0.25 * (dT + Tv * (R)2 * ((R)ez4(a) * uz + (R)er4(a) * ur));
+  }
+}
+
+// Macros at the current level of each lattice (own buffer parity and time).
+template <typename R, int F>
+__device__ inline Mac<R> node_macros(const InstP& P, const InstDyn& D, const R* bufA,
+                                     const R* bufB, int i, int j, bool interior) {
+  const PR<R> p = make_pr<R>(P, D.t);
+  const R* s = (D.cur ? bufB : bufA) + P.off;
+  R f[9], g[4], h[4];
+  load_node<R, F>(P, s, i, j, interior, D.pre != 0, f, g, h);
+  const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
+  // on the axis u_th = 0 and g does not enter the macros of Eqs. (16)-(17)
+  return macros<R, F>(p, j, axis_row, f, g, h);
+}
+
+template <typename R, int F>
+__global__ void __launch_bounds__(1024) k_macros(const InstP* ip, const InstDyn* dyn,
+                                                 const Tile* tiles, const int* ntiles,
+                                                 const R* bufA, const R* bufB, R* rho, R* uz,
+                                                 R* ur, R* uth, R* T, int tzlog) {
+  const int ti = blockIdx.x;
+  if (ti >= *ntiles) return;
+  const Tile Tl = tiles[ti];
+  const InstP& P = ip[Tl.inst];
+  const int tz = 1 << tzlog;
+  const int i = Tl.z0 + (threadIdx.x & (tz - 1)), j = Tl.r0 + (threadIdx.x >> tzlog);
+  if (i >= P.nz || j >= P.nr) return;
+  const Mac<R> m = node_macros<R, F>(P, dyn[Tl.inst], bufA, bufB, i, j, Tl.interior != 0);
+  const long long o = P.off_fld + (long long)j * P.nz + i;
+  if (rho) rho[o] = m.rho;
+  if (uz) uz[o] = m.uz;
+  if (ur) ur[o] = m.ur;
+  if (uth) uth[o] = m.uth;
+  if (T) T[o] = (R)P.T_ref + m.dT;
+}
+
+// Bit pattern of a non-negative double: monotone in the value, and every NaN
+// compares above +Inf, so an unsigned max both reduces and flags NaN.
+__device__ inline unsigned long long key(double v) {
+  return (unsigned long long)__double_as_longlong(fabs(v));
+}
+
+// Eq. (57) per lattice: max | |u|(t) - |u|(t-1) | with |u|(t-1) in spd.
+template <typename R, int F>
+__global__ void __launch_bounds__(1024) k_residual(const InstP* ip, const InstDyn* dyn,
+                                                   const Tile* tiles, const int* ntiles,
+                                                   const R* bufA, const R* bufB, const R* spd,
+                                                   unsigned long long* res, int tzlog) {
+  __shared__ unsigned long long red[16];
+  const int ti = blockIdx.x;
+  if (ti >= *ntiles) return;  // uniform per workgroup
+  const Tile Tl = tiles[ti];
+  const InstP& P = ip[Tl.inst];
+  const int tz = 1 << tzlog;
+  const int i = Tl.z0 + (threadIdx.x & (tz - 1)), j = Tl.r0 + (threadIdx.x >> tzlog);
+  unsigned long long v = 0;
+  if (i < P.nz && j < P.nr) {
+    const Mac<R> m = node_macros<R, F>(P, dyn[Tl.inst], bufA, bufB, i, j, Tl.interior != 0);
+    const double sp = (double)sqrt(m.uz * m.uz + m.ur * m.ur);
+    v = key(sp - (double)spd[P.off_fld + (long long)j * P.nz + i]);
+  }
+  // wave-level max, then across the waves of the workgroup
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    unsigned long long b = red[0];
+    for (int w = 1; w < nw; ++w) b = red[w] > b ? red[w] : b;
+    atomicMax(res + Tl.inst, b);
+  }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+__global__ void k_set_time(long long* t, long long v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *t = v;
+}
+
+__global__ void k_add_time(long long* t, long long dv) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *t += dv;
+}
+
+// ============================================================================
+// host runtime
+// ============================================================================
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+lbaxi_status fail(lbaxi_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(LBAXI_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int n_planes(unsigned fields) {
+  return 9 + ((fields & LBAXI_SWIRL) ? 4 : 0) + ((fields & LBAXI_THERMAL) ? 4 : 0);
+}
+
+// Worst-case tile count over the shapes the runtime accepts (tile_z >= 64).
+long long max_tiles(const std::vector<lbaxi_desc>& d) {
+  long long n = 0;
+  for (const auto& x : d) n += (long long)((x.nz + 63) / 64) * x.nr;
+  return n;
+}
+
+struct Layout {
+  size_t ip, dyn, tiles, ntiles, res, tdev, bufA, bufB, spd, total;
+  std::vector<long long> off, off_fld;
+  long long buf_elems, fld_elems;
+};
+
+Layout layout(const std::vector<lbaxi_desc>& d) {
+  Layout L;
+  const int n = (int)d.size();
+  const size_t es = d[0].prec == LBAXI_FP64 ? 8 : 4;
+  const int np = n_planes(d[0].fields);
+  size_t o = 0;
+  L.ip = o; o = align_up(o + sizeof(InstP) * n, 256);
+  L.dyn = o; o = align_up(o + sizeof(InstDyn) * n, 256);
+  L.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)max_tiles(d), 256);
+  L.ntiles = o; o = align_up(o + sizeof(int), 256);
+  L.res = o; o = align_up(o + sizeof(unsigned long long) * n, 256);
+  L.tdev = o; o = align_up(o + sizeof(long long), 256);
+  long long e = 0, fe = 0;
+  for (const auto& x : d) {
+    L.off.push_back(e);
+    L.off_fld.push_back(fe);
+    e += align_up((size_t)np * x.nz * x.nr, 64);
+    fe += (long long)x.nz * x.nr;
+  }
+  L.buf_elems = e;
+  L.fld_elems = fe;
+  L.bufA = o; o = align_up(o + es * (size_t)e, 256);
+  L.bufB = o; o = align_up(o + es * (size_t)e, 256);
+  L.spd = o; o = align_up(o + es * (size_t)align_up(fe, 64), 256);
+  L.total = o;
+  return L;
+}
+
+// Paper-convention relaxation parameters of a descriptor.
+void taus(const lbaxi_desc& d, double& tau, double& tau_g, double& tau_h) {
+  tau = d.tau - 0.5;
+  tau_g = d.tau_g > 0 ? d.tau_g - 0.5 : 2.0 * tau / 3.0;  // tau_g = 2 tau / 3 (Sec. III C)
+  tau_h = d.tau_h > 0 ? d.tau_h - 0.5 : tau;
+}
+
+lbaxi_status validate(const lbaxi_desc& d, int k) {
+  char b[256];
+  auto bad = [&](lbaxi_status s, const char* what) {
+    snprintf(b, sizeof b, "descriptor %d: %s", k, what);
+    return fail(s, b);
+  };
+  if (d.nz < 2 || d.nr < 2) return bad(LBAXI_EINVAL, "nz and nr must be >= 2");
+  if ((long long)n_planes(d.fields) * d.nz * d.nr >= (1LL << 31))
+    return bad(LBAXI_EINVAL, "lattice too large for 32-bit in-lattice offsets");
+  if (d.prec != LBAXI_FP64 && d.prec != LBAXI_FP32) return bad(LBAXI_EINVAL, "bad prec");
+  if (d.fields & ~7u) return bad(LBAXI_EINVAL, "unknown field bits");
+  if (!(d.rho0 > 0)) return bad(LBAXI_EINVAL, "rho0 must be positive");
+  if (!(d.r0 >= 0)) return bad(LBAXI_EINVAL, "r0 must be >= 0");
+  const lbaxi_side* sd[4] = {&d.south, &d.north, &d.west, &d.east};
+  for (int s = 0; s < 4; ++s) {
+    const int kd = sd[s]->kind;
+    if (kd < 0 || kd > 3) return bad(LBAXI_EINVAL, "bad side kind");
+    if (kd == LBAXI_SIDE_AXIS && s != 0) return bad(LBAXI_EINVAL, "axis only as south side");
+    if (kd == LBAXI_SIDE_PERIODIC && s < 2) return bad(LBAXI_EINVAL, "periodic only on z-ends");
+    if (kd == LBAXI_SIDE_FREESLIP && s < 2) return bad(LBAXI_EINVAL, "free slip only on z-ends");
+    if (s >= 2 && sd[s]->r_split >= 0) {
+      const int k2 = sd[s]->kind2;
+      if (kd == LBAXI_SIDE_PERIODIC || (k2 != LBAXI_SIDE_WALL && k2 != LBAXI_SIDE_FREESLIP))
+        return bad(LBAXI_EINVAL, "bad second segment");
+    }
+  }
+  if ((d.west.kind == LBAXI_SIDE_PERIODIC) != (d.east.kind == LBAXI_SIDE_PERIODIC))
+    return bad(LBAXI_EINVAL, "periodic must be set on both z-ends");
+  if (d.south.kind == LBAXI_SIDE_AXIS && d.r0 != 0.0)
+    return bad(LBAXI_EINVAL, "an axis south side needs r0 = 0");
+  if (d.south.kind != LBAXI_SIDE_AXIS && !(d.fields & LBAXI_CARTESIAN) && !(d.r0 >= 1.0))
+    return bad(LBAXI_EINVAL, "an annulus needs r0 >= 1");
+  double tau, tg, th;
+  taus(d, tau, tg, th);
+  const double tt[3] = {tau, tg, th};
+  const bool used[3] = {true, (d.fields & LBAXI_SWIRL) != 0, (d.fields & LBAXI_THERMAL) != 0};
+  for (int q = 0; q < 3; ++q) {
+    if (!used[q]) continue;
+    if (!(tt[q] > 0)) return bad(LBAXI_ERANGE, "relaxation time must exceed 1/2");
+    for (int j = 0; j < d.nr; ++j) {
+      const double r = d.r0 + j;
+      const double ir = ((d.fields & LBAXI_CARTESIAN) || r <= 0) ? 0.0 : 1.0 / r;
+      for (int e = -1; e <= 1; ++e) {
+        const double w = (1.0 + tt[q] * e * ir) / (tt[q] + 0.5);
+        if (!(w > 0.0 && w < 2.0))
+          return bad(LBAXI_ERANGE, "a relaxation rate leaves (0, 2) on some row");
+      }
+    }
+  }
+  return LBAXI_OK;
+}
+
+InstP make_inst(const lbaxi_desc& d, long long off, long long off_fld) {
+  InstP P;
+  memset(&P, 0, sizeof P);
+  P.nz = d.nz;
+  P.nr = d.nr;
+  P.plane = d.nz * d.nr;
+  P.cart = (d.fields & LBAXI_CARTESIAN) ? 1 : 0;
+  P.r0 = d.r0;
+  taus(d, P.tau, P.tau_g, P.tau_h);
+  P.rho0 = d.rho0;
+  P.mu0 = d.rho0 * P.tau / 3.0;  // mu = tau rho cs^2 (Eq. 36), rho -> rho0
+  P.nu_g = P.tau_g / 2.0;        // nu = tau_g c^2 / 2 (Eq. 54)
+  P.om0 = 1.0 / (P.tau + 0.5);
+  P.omg0 = 1.0 / (P.tau_g + 0.5);
+  P.omh0 = 1.0 / (P.tau_h + 0.5);
+  P.a0 = d.a0;
+  P.period = d.period;
+  P.phase = d.phase;
+  P.gbeta = d.gbeta;
+  P.T_ref = d.T_ref;
+  P.off = off;
+  P.off_fld = off_fld;
+  const lbaxi_side* sd[4] = {&d.south, &d.north, &d.west, &d.east};
+  for (int s = 0; s < 4; ++s) {
+    SideP& S = P.side[s];
+    S.kind = sd[s]->kind;
+    S.thermal = sd[s]->thermal;
+    S.kind2 = sd[s]->kind2;
+    S.thermal2 = sd[s]->thermal2;
+    S.uz = sd[s]->u_z;
+    S.ur = sd[s]->u_r;
+    S.omega = sd[s]->omega;
+    S.T = sd[s]->T;
+    S.r_split = (s >= 2) ? sd[s]->r_split : -1.0;
+    S.omega2 = sd[s]->omega2;
+    S.T2 = sd[s]->T2;
+  }
+  return P;
+}
+
+int ilog2(int x) {
+  int l = 0;
+  while ((1 << l) < x) ++l;
+  return l;
+}
+
+}  // namespace
+
+struct lbaxi_s {
+  int n = 0, prec = 0;
+  unsigned fields = 0;
+  std::vector<lbaxi_desc> desc;
+  std::vector<InstP> ip;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char* ws = nullptr;
+  Layout L;
+  InstP* d_ip = nullptr;
+  InstDyn* d_dyn = nullptr;
+  Tile* d_tiles = nullptr;
+  int* d_ntiles = nullptr;
+  unsigned long long* d_res = nullptr;
+  long long* d_t = nullptr;
+  void* bufA = nullptr;
+  void* bufB = nullptr;
+  void* spd = nullptr;
+  // state of the running lattices (all share parity and time)
+  int cur = 0;
+  bool pre = true;
+  long long t = 0;
+  bool have_spd = false;
+  // per lattice
+  std::vector<int> status;
+  std::vector<InstDyn> dyn;
+  std::vector<char> inst_spd;
+  bool dyn_dirty = true;
+  // launch shape
+  int tz = 64, tr = 4, grid = 0, xcd = 0, nt = 1;
+  int K = 64;
+  std::vector<Tile> tiles_all;  // every lattice, current shape (seed/macros/residual)
+  std::vector<Tile> tiles_run;  // RUNNING lattices only (step)
+  int ntiles_all = 0, ntiles_run = 0;
+  // which tile list the device table holds: 0 none, 1 all, 2 run
+  int dev_tiles = 0;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+void build_tiles(lbaxi_t* h) {
+  h->tiles_all.clear();
+  h->tiles_run.clear();
+  for (int k = 0; k < h->n; ++k) {
+    const lbaxi_desc& d = h->desc[k];
+    for (int j0 = 0; j0 < d.nr; j0 += h->tr)
+      for (int i0 = 0; i0 < d.nz; i0 += h->tz) {
+        Tile T;
+        T.inst = k;
+        T.z0 = i0;
+        T.r0 = j0;
+        T.interior = (i0 >= 1 && i0 + h->tz <= d.nz - 1 && j0 >= 1 && j0 + h->tr <= d.nr - 1);
+        h->tiles_all.push_back(T);
+        if (h->status[k] == LBAXI_RUNNING) h->tiles_run.push_back(T);
+      }
+  }
+  h->ntiles_all = (int)h->tiles_all.size();
+  h->ntiles_run = (int)h->tiles_run.size();
+  h->dev_tiles = 0;
+}
+
+lbaxi_status upload_tiles(lbaxi_t* h, int which) {
+  if (which == 2 && h->ntiles_run == h->ntiles_all) which = 1;  // same list
+  if (h->dev_tiles == which) return LBAXI_OK;
+  const std::vector<Tile>& v = which == 1 ? h->tiles_all : h->tiles_run;
+  const int n = (int)v.size();
+  if (n) HIPCHK(hipMemcpyAsync(h->d_tiles, v.data(), sizeof(Tile) * n, hipMemcpyHostToDevice,
+                               h->stream));
+  HIPCHK(hipMemcpyAsync(h->d_ntiles, &n, sizeof(int), hipMemcpyHostToDevice, h->stream));
+  // the host vectors must outlive the copies: synchronise (tables change rarely)
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->dev_tiles = which;
+  return LBAXI_OK;
+}
+
+lbaxi_status upload_dyn(lbaxi_t* h) {
+  if (!h->dyn_dirty) return LBAXI_OK;
+  for (int k = 0; k < h->n; ++k)
+    if (h->status[k] == LBAXI_RUNNING) {
+      h->dyn[k].cur = h->cur;
+      h->dyn[k].pre = h->pre ? 1 : 0;
+      h->dyn[k].t = h->t;
+    }
+  HIPCHK(hipMemcpyAsync(h->d_dyn, h->dyn.data(), sizeof(InstDyn) * h->n, hipMemcpyHostToDevice,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->dyn_dirty = false;
+  return LBAXI_OK;
+}
+
+void drop_graphs(lbaxi_t* h) {
+  for (int q = 0; q < 2; ++q)
+    if (h->gexec[q]) {
+      (void)hipGraphExecDestroy(h->gexec[q]);
+      h->gexec[q] = nullptr;
+    }
+}
+
+template <typename R, int F>
+void* step_fn() {
+  return reinterpret_cast<void*>(&k_step<R, F>);
+}
+
+void* pick_step(int prec, unsigned fields) {
+  const int F = fields & 3;
+  if (prec == LBAXI_FP64) {
+    switch (F) {
+      case 0: return step_fn<double, 0>();
+      case 1: return step_fn<double, 1>();
+      case 2: return step_fn<double, 2>();
+      default: return step_fn<double, 3>();
+    }
+  }
+  switch (F) {
+    case 0: return step_fn<float, 0>();
+    case 1: return step_fn<float, 1>();
+    case 2: return step_fn<float, 2>();
+    default: return step_fn<float, 3>();
+  }
+}
+
+// StepArgs is laid out identically for float and double (pointers only).
+StepArgs<double> step_args(lbaxi_t* h, int from, long long t0, bool use_tdev, int k, int mode) {
+  StepArgs<double> a;
+  a.ip = h->d_ip;
+  a.tiles = h->d_tiles;
+  a.ntiles = h->d_ntiles;
+  a.src = (const double*)(from ? h->bufB : h->bufA);
+  a.dst = (double*)(from ? h->bufA : h->bufB);
+  a.spd = (double*)h->spd;
+  a.tdev = use_tdev ? h->d_t : nullptr;
+  a.t0 = t0;
+  a.k = k;
+  a.mode = mode;
+  a.tzlog = ilog2(h->tz);
+  a.tr = h->tr;
+  a.xcd = h->xcd;
+  a.nt_store = h->nt;
+  return a;
+}
+
+int step_grid(const lbaxi_t* h) {
+  return h->grid > 0 ? h->grid : std::max(1, h->ntiles_all);
+}
+
+lbaxi_status launch_step(lbaxi_t* h, int mode) {
+  StepArgs<double> a = step_args(h, h->cur, h->t, false, 0, mode);
+  void* args[] = {&a};
+  HIPCHK(hipLaunchKernel(pick_step(h->prec, h->fields), dim3(step_grid(h)),
+                         dim3(h->tz * h->tr), args, 0, h->stream));
+  h->cur ^= 1;
+  h->t += 1;
+  h->pre = false;
+  return LBAXI_OK;
+}
+
+lbaxi_status make_graph(lbaxi_t* h, int from) {
+  hipGraph_t g;
+  HIPCHK(hipGraphCreate(&g, 0));
+  hipGraphNode_t prev = nullptr;
+  void* fn = pick_step(h->prec, h->fields);
+  lbaxi_status st = LBAXI_OK;
+  for (int k = 0; k < h->K && st == LBAXI_OK; ++k) {
+    StepArgs<double> a = step_args(h, from ^ (k & 1), 0, true, k, 0);
+    void* args[] = {&a};
+    hipKernelNodeParams p;
+    memset(&p, 0, sizeof p);
+    p.func = fn;
+    p.gridDim = dim3(step_grid(h));
+    p.blockDim = dim3(h->tz * h->tr);
+    p.sharedMemBytes = 0;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    hipGraphNode_t node;
+    hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+    if (e != hipSuccess) st = fail(LBAXI_EDEVICE, std::string("hipGraphAddKernelNode: ") +
+                                                      hipGetErrorString(e));
+    prev = node;
+  }
+  if (st == LBAXI_OK) {
+    long long* tp = h->d_t;
+    long long dv = h->K;
+    void* args[] = {&tp, &dv};
+    hipKernelNodeParams p;
+    memset(&p, 0, sizeof p);
+    p.func = reinterpret_cast<void*>(&k_add_time);
+    p.gridDim = dim3(1);
+    p.blockDim = dim3(64);
+    p.kernelParams = args;
+    hipGraphNode_t node;
+    hipError_t e = hipGraphAddKernelNode(&node, g, &prev, 1, &p);
+    if (e != hipSuccess)
+      st = fail(LBAXI_EDEVICE, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
+  }
+  if (st == LBAXI_OK) {
+    hipError_t e = hipGraphInstantiate(&h->gexec[from], g, nullptr, nullptr, 0);
+    if (e != hipSuccess)
+      st = fail(LBAXI_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  (void)hipGraphDestroy(g);
+  return st;
+}
+
+lbaxi_status check_handle(const lbaxi_t* h) {
+  if (!h) return fail(LBAXI_EINVAL, "NULL handle");
+  return LBAXI_OK;
+}
+
+template <typename R, int F>
+void* seed_fn() { return reinterpret_cast<void*>(&k_seed<R, F>); }
+template <typename R, int F>
+void* macros_fn() { return reinterpret_cast<void*>(&k_macros<R, F>); }
+template <typename R, int F>
+void* resid_fn() { return reinterpret_cast<void*>(&k_residual<R, F>); }
+
+#define PICK(name, prec, fields)                                            \
+  ((prec) == LBAXI_FP64                                                     \
+       ? ((fields & 3) == 0   ? name<double, 0>()                           \
+          : (fields & 3) == 1 ? name<double, 1>()                           \
+          : (fields & 3) == 2 ? name<double, 2>()                           \
+                              : name<double, 3>())                          \
+       : ((fields & 3) == 0   ? name<float, 0>()                            \
+          : (fields & 3) == 1 ? name<float, 1>()                            \
+          : (fields & 3) == 2 ? name<float, 2>()                            \
+                              : name<float, 3>()))
+
+lbaxi_status run_steps(lbaxi_t* h, long long n) {
+  if (n <= 0) return LBAXI_OK;
+  lbaxi_status st;
+  if (h->ntiles_run == 0) return LBAXI_OK;
+  if ((st = upload_tiles(h, 2)) != LBAXI_OK) return st;
+  long long left = n;
+  if (h->pre) {
+    if ((st = launch_step(h, MODE_PRE | (left == 1 ? MODE_SPEED : 0))) != LBAXI_OK) return st;
+    --left;
+  }
+  // the last step of the call records |u| for Eq. (57); graphs cover the rest
+  if (h->K > 0 && left - 1 >= h->K) {
+    const long long reps = (left - 1) / h->K;
+    if (!h->gexec[h->cur] && (st = make_graph(h, h->cur)) != LBAXI_OK) return st;
+    hipLaunchKernelGGL(k_set_time, dim3(1), dim3(64), 0, h->stream, h->d_t, h->t);
+    HIPCHK(hipGetLastError());
+    for (long long q = 0; q < reps; ++q) HIPCHK(hipGraphLaunch(h->gexec[h->cur], h->stream));
+    h->t += reps * h->K;
+    left -= reps * h->K;
+  }
+  while (left > 0) {
+    if ((st = launch_step(h, left == 1 ? MODE_SPEED : 0)) != LBAXI_OK) return st;
+    --left;
+  }
+  h->have_spd = true;
+  h->dyn_dirty = true;
+  return LBAXI_OK;
+}
+
+lbaxi_status residuals(lbaxi_t* h, std::vector<double>& out) {
+  lbaxi_status st;
+  if ((st = upload_dyn(h)) != LBAXI_OK) return st;
+  if ((st = upload_tiles(h, 1)) != LBAXI_OK) return st;
+  hipLaunchKernelGGL(k_fill_u64, dim3((h->n + 255) / 256), dim3(256), 0, h->stream, h->d_res,
+                     h->n, 0ULL);
+  HIPCHK(hipGetLastError());
+  void* fn = PICK(resid_fn, h->prec, h->fields);
+  const void* A = h->bufA;
+  const void* B = h->bufB;
+  const void* S = h->spd;
+  unsigned long long* r = h->d_res;
+  const InstP* ip = h->d_ip;
+  const InstDyn* dy = h->d_dyn;
+  const Tile* tl = h->d_tiles;
+  const int* nt = h->d_ntiles;
+  int tzlog = ilog2(h->tz);
+  void* args[] = {&ip, &dy, &tl, &nt, &A, &B, &S, &r, &tzlog};
+  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->ntiles_all)), dim3(h->tz * h->tr), args, 0,
+                         h->stream));
+  std::vector<unsigned long long> bits(h->n);
+  HIPCHK(hipMemcpyAsync(bits.data(), h->d_res, sizeof(unsigned long long) * h->n,
+                        hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  out.resize(h->n);
+  for (int k = 0; k < h->n; ++k) {
+    double v;
+    memcpy(&v, &bits[k], sizeof v);
+    out[k] = v;
+  }
+  return LBAXI_OK;
+}
+
+struct SaveHeader {
+  char magic[8];
+  int32_t version, n, prec;
+  uint32_t fields;
+  int64_t t;
+  int32_t cur, pre, have_spd, pad;
+  uint64_t desc_hash, buf_bytes;
+};
+
+uint64_t desc_hash(const std::vector<lbaxi_desc>& d) {
+  // FNV-1a over the descriptor bytes (layout-identical handles hash equal)
+  uint64_t hsh = 1469598103934665603ULL;
+  const unsigned char* p = reinterpret_cast<const unsigned char*>(d.data());
+  for (size_t i = 0; i < d.size() * sizeof(lbaxi_desc); ++i) {
+    hsh ^= p[i];
+    hsh *= 1099511628211ULL;
+  }
+  return hsh;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+extern "C" {
+
+const char* lbaxi_last_error(void) { return g_err.c_str(); }
+
+const char* lbaxi_strerror(lbaxi_status s) {
+  switch (s) {
+    case LBAXI_OK: return "ok";
+    case LBAXI_EINVAL: return "invalid argument";
+    case LBAXI_ERANGE: return "relaxation rate out of (0, 2)";
+    case LBAXI_ENOMEM: return "workspace too small";
+    case LBAXI_EDEVICE: return "HIP error";
+    case LBAXI_EDIVERGED: return "diverged (NaN/Inf)";
+    case LBAXI_ESTATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+lbaxi_status lbaxi_workspace_bytes(int32_t n, const lbaxi_desc* descs, size_t* bytes) {
+  if (n < 1 || !descs || !bytes) return fail(LBAXI_EINVAL, "bad arguments");
+  std::vector<lbaxi_desc> d(descs, descs + n);
+  for (int k = 0; k < n; ++k) {
+    lbaxi_status s = validate(d[k], k);
+    if (s != LBAXI_OK) return s;
+    if (d[k].prec != d[0].prec || (d[k].fields & 3) != (d[0].fields & 3))
+      return fail(LBAXI_EINVAL, "all lattices of a batch need the same prec and field set");
+  }
+  *bytes = layout(d).total;
+  return LBAXI_OK;
+}
+
+lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace, size_t bytes,
+                          void* hip_stream, lbaxi_t** out) {
+  if (!out) return fail(LBAXI_EINVAL, "NULL out");
+  *out = nullptr;
+  size_t need = 0;
+  lbaxi_status st = lbaxi_workspace_bytes(n, descs, &need);
+  if (st != LBAXI_OK) return st;
+  if (!d_workspace) return fail(LBAXI_EINVAL, "NULL workspace");
+  if (reinterpret_cast<uintptr_t>(d_workspace) % 256) return fail(LBAXI_EINVAL, "workspace not 256-byte aligned");
+  if (bytes < need) return fail(LBAXI_ENOMEM, "workspace smaller than lbaxi_workspace_bytes");
+  lbaxi_t* h = new (std::nothrow) lbaxi_s();
+  if (!h) return fail(LBAXI_ENOMEM, "host allocation failed");
+  h->n = n;
+  h->desc.assign(descs, descs + n);
+  h->prec = descs[0].prec;
+  h->fields = descs[0].fields;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  h->ws = static_cast<char*>(d_workspace);
+  h->L = layout(h->desc);
+  h->d_ip = reinterpret_cast<InstP*>(h->ws + h->L.ip);
+  h->d_dyn = reinterpret_cast<InstDyn*>(h->ws + h->L.dyn);
+  h->d_tiles = reinterpret_cast<Tile*>(h->ws + h->L.tiles);
+  h->d_ntiles = reinterpret_cast<int*>(h->ws + h->L.ntiles);
+  h->d_res = reinterpret_cast<unsigned long long*>(h->ws + h->L.res);
+  h->d_t = reinterpret_cast<long long*>(h->ws + h->L.tdev);
+  h->bufA = h->ws + h->L.bufA;
+  h->bufB = h->ws + h->L.bufB;
+  h->spd = h->ws + h->L.spd;
+  for (int k = 0; k < n; ++k) h->ip.push_back(make_inst(h->desc[k], h->L.off[k], h->L.off_fld[k]));
+  h->status.assign(n, LBAXI_RUNNING);
+  h->dyn.assign(n, InstDyn{0, 1, 0});
+  h->inst_spd.assign(n, 0);
+  // default launch shape: one wave along z, 4 rows, one workgroup per tile
+  h->tz = 64;
+  h->tr = 4;
+  h->grid = 0;
+  h->xcd = 0;
+  h->nt = 1;
+  build_tiles(h);
+  hipError_t e = hipGetDevice(&h->device);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->d_ip, h->ip.data(), sizeof(InstP) * n, hipMemcpyHostToDevice,
+                       h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(LBAXI_EDEVICE, std::string("create: ") + hipGetErrorString(e));
+  }
+  st = lbaxi_seed(h, nullptr, nullptr, nullptr, nullptr);
+  if (st != LBAXI_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return LBAXI_OK;
+}
+
+void lbaxi_destroy(lbaxi_t* h) {
+  if (!h) return;
+  drop_graphs(h);
+  delete h;
+}
+
+lbaxi_status lbaxi_seed(lbaxi_t* h, const void* d_uz, const void* d_ur, const void* d_uth,
+                        const void* d_T) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  for (int k = 0; k < h->n; ++k) h->status[k] = LBAXI_RUNNING;
+  build_tiles(h);
+  if ((st = upload_tiles(h, 1)) != LBAXI_OK) return st;
+  void* fn = PICK(seed_fn, h->prec, h->fields);
+  const InstP* ip = h->d_ip;
+  const Tile* tl = h->d_tiles;
+  const int* nt = h->d_ntiles;
+  void* buf = h->bufA;
+  int tzlog = ilog2(h->tz);
+  void* args[] = {&ip, &tl, &nt, &buf, &d_uz, &d_ur, &d_uth, &d_T, &tzlog};
+  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->ntiles_all)), dim3(h->tz * h->tr), args, 0,
+                         h->stream));
+  h->cur = 0;
+  h->pre = true;
+  h->t = 0;
+  h->have_spd = false;
+  for (int k = 0; k < h->n; ++k) {
+    h->dyn[k] = InstDyn{0, 1, 0};
+    h->inst_spd[k] = 0;
+  }
+  h->dyn_dirty = true;
+  return LBAXI_OK;
+}
+
+lbaxi_status lbaxi_step(lbaxi_t* h, int64_t n) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  if (n < 0) return fail(LBAXI_EINVAL, "negative step count");
+  st = run_steps(h, n);
+  if (st == LBAXI_OK && n > 0)
+    for (int k = 0; k < h->n; ++k)
+      if (h->status[k] == LBAXI_RUNNING) h->inst_spd[k] = 1;
+  return st;
+}
+
+lbaxi_status lbaxi_macros(lbaxi_t* h, void* d_rho, void* d_uz, void* d_ur, void* d_uth,
+                          void* d_T) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  if ((st = upload_dyn(h)) != LBAXI_OK) return st;
+  if ((st = upload_tiles(h, 1)) != LBAXI_OK) return st;
+  void* fn = PICK(macros_fn, h->prec, h->fields);
+  const InstP* ip = h->d_ip;
+  const InstDyn* dy = h->d_dyn;
+  const Tile* tl = h->d_tiles;
+  const int* nt = h->d_ntiles;
+  const void* A = h->bufA;
+  const void* B = h->bufB;
+  int tzlog = ilog2(h->tz);
+  void* args[] = {&ip, &dy, &tl, &nt, &A, &B, &d_rho, &d_uz, &d_ur, &d_uth, &d_T, &tzlog};
+  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->ntiles_all)), dim3(h->tz * h->tr), args, 0,
+                         h->stream));
+  return LBAXI_OK;
+}
+
+lbaxi_status lbaxi_residual(lbaxi_t* h, double* host_res) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  if (!host_res) return fail(LBAXI_EINVAL, "NULL host_res");
+  for (int k = 0; k < h->n; ++k)
+    if (!h->inst_spd[k]) return fail(LBAXI_ESTATE, "no step since seeding or loading");
+  std::vector<double> r;
+  if ((st = residuals(h, r)) != LBAXI_OK) return st;
+  bool bad = false;
+  for (int k = 0; k < h->n; ++k) {
+    host_res[k] = r[k];
+    if (!std::isfinite(r[k])) bad = true;
+  }
+  return bad ? fail(LBAXI_EDIVERGED, "NaN or Inf in some lattice") : LBAXI_OK;
+}
+
+lbaxi_status lbaxi_time(const lbaxi_t* h, int32_t k, int64_t* t) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  if (k < 0 || k >= h->n || !t) return fail(LBAXI_EINVAL, "bad lattice index");
+  *t = h->status[k] == LBAXI_RUNNING ? h->t : h->dyn[k].t;
+  return LBAXI_OK;
+}
+
+lbaxi_status lbaxi_batch_run(lbaxi_t* h, double tol, int64_t max_steps, int64_t check_every,
+                             int32_t* host_status, int64_t* host_steps, double* host_res) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  if (check_every < 2 || max_steps < 0 || !(tol >= 0) || !host_status || !host_steps)
+    return fail(LBAXI_EINVAL, "bad batch_run arguments");
+  std::vector<double> last(h->n, -1.0);
+  const long long t_start = h->t;
+  long long done = 0;
+  while (done < max_steps && h->ntiles_run > 0) {
+    const long long n = std::min<long long>(check_every, max_steps - done);
+    if ((st = run_steps(h, n)) != LBAXI_OK) return st;
+    for (int k = 0; k < h->n; ++k)
+      if (h->status[k] == LBAXI_RUNNING) h->inst_spd[k] = 1;
+    done += n;
+    std::vector<double> r;
+    if ((st = residuals(h, r)) != LBAXI_OK) return st;
+    bool changed = false;
+    for (int k = 0; k < h->n; ++k) {
+      if (h->status[k] != LBAXI_RUNNING) continue;
+      last[k] = r[k];
+      int ns = LBAXI_RUNNING;
+      if (!std::isfinite(r[k])) ns = LBAXI_DIVERGED;
+      else if (r[k] <= tol) ns = LBAXI_CONVERGED;
+      if (ns != LBAXI_RUNNING) {
+        h->status[k] = ns;
+        h->dyn[k].cur = h->cur;
+        h->dyn[k].pre = 0;
+        h->dyn[k].t = h->t;
+        changed = true;
+      }
+    }
+    if (changed) {
+      build_tiles(h);
+      h->dyn_dirty = true;
+    }
+  }
+  for (int k = 0; k < h->n; ++k) {
+    if (h->status[k] == LBAXI_RUNNING && done >= max_steps) {
+      h->status[k] = LBAXI_CAPPED;
+      h->dyn[k].cur = h->cur;
+      h->dyn[k].pre = h->pre ? 1 : 0;
+      h->dyn[k].t = h->t;
+    }
+    host_status[k] = h->status[k];
+    host_steps[k] = (h->status[k] == LBAXI_RUNNING ? h->t : h->dyn[k].t) - t_start;
+    if (host_res) host_res[k] = last[k];
+  }
+  build_tiles(h);
+  h->dyn_dirty = true;
+  return LBAXI_OK;
+}
+
+lbaxi_status lbaxi_set_launch(lbaxi_t* h, int32_t tile_z, int32_t tile_r, int32_t grid_blocks,
+                              int32_t xcd_aware, int32_t nt_store) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  if (tile_z < 64 || (tile_z & (tile_z - 1)) || tile_r < 1 || tile_z * tile_r > 1024 ||
+      grid_blocks < 0)
+    return fail(LBAXI_EINVAL, "tile_z must be a power of two >= 64, tile_z*tile_r <= 1024");
+  const bool shape = tile_z != h->tz || tile_r != h->tr;
+  h->tz = tile_z;
+  h->tr = tile_r;
+  h->grid = grid_blocks;
+  h->xcd = xcd_aware ? 1 : 0;
+  h->nt = nt_store ? 1 : 0;
+  if (shape) build_tiles(h);
+  drop_graphs(h);
+  return LBAXI_OK;
+}
+
+lbaxi_status lbaxi_get_launch(const lbaxi_t* h, int32_t* cfg5) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  if (!cfg5) return fail(LBAXI_EINVAL, "NULL cfg5");
+  cfg5[0] = h->tz;
+  cfg5[1] = h->tr;
+  cfg5[2] = h->grid;
+  cfg5[3] = h->xcd;
+  cfg5[4] = h->nt;
+  return LBAXI_OK;
+}
+
+lbaxi_status lbaxi_set_graph_steps(lbaxi_t* h, int32_t k) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  if (k < 0 || (k & 1)) return fail(LBAXI_EINVAL, "graph length must be even and >= 0");
+  h->K = k;
+  drop_graphs(h);
+  return LBAXI_OK;
+}
+
+lbaxi_status lbaxi_autotune(lbaxi_t* h, int32_t steps_per_trial, int32_t* cfg5_out) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  if (steps_per_trial < 2) return fail(LBAXI_EINVAL, "steps_per_trial must be >= 2");
+  static const int shapes[][2] = {{64, 1}, {64, 2}, {64, 4}, {64, 8}, {128, 1},
+                                  {128, 2}, {128, 4}, {256, 1}, {256, 2}};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int dev_cu = 256;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) dev_cu = prop.multiProcessorCount;
+  }
+  auto trial = [&](int tz, int tr, int grid, int xcd, int nt, float& ms) -> lbaxi_status {
+    lbaxi_status s = lbaxi_set_launch(h, tz, tr, grid, xcd, nt);
+    if (s != LBAXI_OK) return s;
+    if ((s = run_steps(h, 2)) != LBAXI_OK) return s;  // warm-up + graph build
+    HIPCHK(hipEventRecord(e0, h->stream));
+    if ((s = run_steps(h, steps_per_trial)) != LBAXI_OK) return s;
+    HIPCHK(hipEventRecord(e1, h->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    return LBAXI_OK;
+  };
+  float best = 1e30f;
+  int b[5] = {h->tz, h->tr, h->grid, h->xcd, h->nt};
+  for (const auto& sh : shapes) {
+    float ms;
+    if ((st = trial(sh[0], sh[1], 0, 0, 1, ms)) != LBAXI_OK) break;
+    if (ms < best) {
+      best = ms;
+      b[0] = sh[0]; b[1] = sh[1]; b[2] = 0; b[3] = 0; b[4] = 1;
+    }
+  }
+  if (st == LBAXI_OK) {
+    const int wg = b[0] * b[1];
+    const int per_cu = std::max(1, 2048 / wg);
+    const int grids[] = {dev_cu * per_cu, dev_cu * per_cu * 2, dev_cu * per_cu / 2};
+    const int base[3] = {b[0], b[1], 0};
+    for (int gi = 0; gi < 3 && st == LBAXI_OK; ++gi)
+      for (int xcd = 0; xcd < 2 && st == LBAXI_OK; ++xcd) {
+        float ms;
+        if ((st = trial(base[0], base[1], grids[gi], xcd, 1, ms)) != LBAXI_OK) break;
+        if (ms < best) {
+          best = ms;
+          b[2] = grids[gi]; b[3] = xcd; b[4] = 1;
+        }
+      }
+    float ms;
+    if (st == LBAXI_OK && (st = trial(b[0], b[1], b[2], b[3], 0, ms)) == LBAXI_OK && ms < best) {
+      best = ms;
+      b[4] = 0;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != LBAXI_OK) return st;
+  h->dyn_dirty = true;
+  for (int k = 0; k < h->n; ++k)
+    if (h->status[k] == LBAXI_RUNNING) h->inst_spd[k] = 1;
+  if ((st = lbaxi_set_launch(h, b[0], b[1], b[2], b[3], b[4])) != LBAXI_OK) return st;
+  if (cfg5_out) memcpy(cfg5_out, b, sizeof b);
+  return LBAXI_OK;
+}
+
+lbaxi_status lbaxi_state_bytes(const lbaxi_t* h, size_t* bytes) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  if (!bytes) return fail(LBAXI_EINVAL, "NULL bytes");
+  const size_t es = h->prec == LBAXI_FP64 ? 8 : 4;
+  *bytes = sizeof(SaveHeader) + sizeof(InstDyn) * h->n + sizeof(int32_t) * h->n +
+           es * (size_t)h->L.buf_elems + es * (size_t)h->L.fld_elems;
+  return LBAXI_OK;
+}
+
+lbaxi_status lbaxi_save(lbaxi_t* h, void* host_buf, size_t bytes) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  size_t need;
+  if ((st = lbaxi_state_bytes(h, &need)) != LBAXI_OK) return st;
+  if (!host_buf || bytes < need) return fail(LBAXI_EINVAL, "save buffer too small");
+  for (int k = 0; k < h->n; ++k)
+    if (h->status[k] == LBAXI_RUNNING) {
+      h->dyn[k].cur = h->cur; h->dyn[k].pre = h->pre; h->dyn[k].t = h->t;
+    }
+  const size_t es = h->prec == LBAXI_FP64 ? 8 : 4;
+  char* p = static_cast<char*>(host_buf);
+  SaveHeader H;
+  memset(&H, 0, sizeof H);
+  memcpy(H.magic, "LBAXISV1", 8);
+  H.version = 1;
+  H.n = h->n;
+  H.prec = h->prec;
+  H.fields = h->fields;
+  H.t = h->t;
+  H.cur = h->cur;
+  H.pre = h->pre;
+  H.have_spd = h->have_spd;
+  H.desc_hash = desc_hash(h->desc);
+  H.buf_bytes = es * (size_t)h->L.buf_elems;
+  memcpy(p, &H, sizeof H);
+  p += sizeof H;
+  memcpy(p, h->dyn.data(), sizeof(InstDyn) * h->n);
+  p += sizeof(InstDyn) * h->n;
+  memcpy(p, h->status.data(), sizeof(int32_t) * h->n);
+  p += sizeof(int32_t) * h->n;
+  // every lattice's own current buffer, instance by instance
+  const int np = n_planes(h->fields);
+  for (int k = 0; k < h->n; ++k) {
+    const char* src = static_cast<const char*>(h->dyn[k].cur ? h->bufB : h->bufA) + es * h->L.off[k];
+    const size_t nb = es * (size_t)np * h->desc[k].nz * h->desc[k].nr;
+    HIPCHK(hipMemcpyAsync(p + es * h->L.off[k], src, nb, hipMemcpyDeviceToHost, h->stream));
+  }
+  p += es * (size_t)h->L.buf_elems;
+  HIPCHK(hipMemcpyAsync(p, h->spd, es * (size_t)h->L.fld_elems, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBAXI_OK;
+}
+
+lbaxi_status lbaxi_load(lbaxi_t* h, const void* host_buf, size_t bytes) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  size_t need;
+  if ((st = lbaxi_state_bytes(h, &need)) != LBAXI_OK) return st;
+  if (!host_buf || bytes < need) return fail(LBAXI_EINVAL, "load buffer too small");
+  const char* p = static_cast<const char*>(host_buf);
+  SaveHeader H;
+  memcpy(&H, p, sizeof H);
+  if (memcmp(H.magic, "LBAXISV1", 8) || H.n != h->n || H.prec != h->prec ||
+      H.fields != h->fields || H.desc_hash != desc_hash(h->desc))
+    return fail(LBAXI_EINVAL, "checkpoint does not match this handle");
+  p += sizeof H;
+  memcpy(h->dyn.data(), p, sizeof(InstDyn) * h->n);
+  p += sizeof(InstDyn) * h->n;
+  memcpy(h->status.data(), p, sizeof(int32_t) * h->n);
+  p += sizeof(int32_t) * h->n;
+  const size_t es = h->prec == LBAXI_FP64 ? 8 : 4;
+  const int np = n_planes(h->fields);
+  for (int k = 0; k < h->n; ++k) {
+    char* dst = static_cast<char*>(h->dyn[k].cur ? h->bufB : h->bufA) + es * h->L.off[k];
+    const size_t nb = es * (size_t)np * h->desc[k].nz * h->desc[k].nr;
+    HIPCHK(hipMemcpyAsync(dst, p + es * h->L.off[k], nb, hipMemcpyHostToDevice, h->stream));
+  }
+  p += es * (size_t)h->L.buf_elems;
+  HIPCHK(hipMemcpyAsync(h->spd, p, es * (size_t)h->L.fld_elems, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->t = H.t;
+  h->cur = H.cur;
+  h->pre = H.pre != 0;
+  h->have_spd = H.have_spd != 0;
+  for (int k = 0; k < h->n; ++k) h->inst_spd[k] = h->have_spd ? 1 : 0;
+  build_tiles(h);
+  drop_graphs(h);
+  h->dyn_dirty = true;
+  return LBAXI_OK;
+}
+
+lbaxi_status lbaxi_node_count(const lbaxi_t* h, int64_t* nodes, int32_t* n) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  if (nodes) *nodes = h->L.fld_elems;
+  if (n) *n = h->n;
+  return LBAXI_OK;
+}
+
+size_t lbaxi_abi_desc_size(void) { return sizeof(lbaxi_desc); }
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Same seeded inputs on both sides, same step count, then every macroscopic
+field is compared element by element: max |u_gpu - u_oracle| / u_max must be
+<= 1e-10 for the FP64 path and <= 1e-5 for the FP32 path.  Sizes span several
+tiles with ragged tails; the boundary kinds (axis, walls with moving /
+rotating / thermal values, periodic ends, free slip, split z-ends, annulus,
+planar mode) all appear.  FP64 results must also be bitwise independent of
+the launch shape, of graph replay, of batching and of checkpointing.
+"""
+import numpy as np
+import pytest
+
+from paper_1003_0282_amd import workloads as W
+from _parity import assert_parity, gpu_run, oracle_run, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+
+
+def _fields(case, seed):
+    f = W.random_fields(case, seed)
+    if not case.get("swirl"):
+        f.pop("uth")
+    if not case.get("thermal"):
+        f.pop("T")
+    return f
+
+
+def _compare(case, steps, prec, fields=None, label="", **kw):
+    o = oracle_run(case, steps, fields)
+    lat = gpu_run([case], steps, prec, None if fields is None else [fields], **kw)
+    gm = to_np(lat.macros())
+    om = o.macros()
+    assert lat.time() == o.t == steps
+    return assert_parity(case, {k: v.reshape(case["nr"], case["nz"]) for k, v in gm.items()},
+                         om, prec, label), lat, o
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_hagen_poiseuille_c1(prec):
+    """4 x 32 pipe, a = 1e-6, tau 0.8, 20 000 steps from rest."""
+    case = W.hagen_poiseuille()
+    e, lat, o = _compare(case, 20000, prec, label="HP")
+    print("HP prec", prec, e)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_womersley_c2(prec):
+    """64 x 128 pipe, a0 cos(2 pi t / 4000), tau 0.6, two periods."""
+    case = W.womersley()
+    e, lat, o = _compare(case, 8000, prec, label="Womersley")
+    print("Womersley prec", prec, e)
+
+
+CASES = {
+    "cavity": lambda: W.cavity(37, 70, 400.0),
+    "melt": lambda: W.melt(-300.0, 500.0, 2e4, nr=29, nz=75),
+    "annulus_moving": lambda: W.base_case(67, 21, 0.7, r0=3.0, south=W.wall(uz=2e-3, omega=1e-3),
+                                          north=W.wall(omega=-5e-4), swirl=True, a0=1e-5),
+    "annulus_thermal": lambda: W.base_case(66, 19, 0.75, r0=5.0, south=W.wall(thermal=1, T=1.0),
+                                           north=W.wall(thermal=1, T=0.2), west=W.wall(),
+                                           east=W.freeslip(), thermal=True, tau_h=0.9,
+                                           gbeta=2e-4, T_ref=0.5, swirl=True),
+    "pipe_periodic_force": lambda: W.womersley(nz=130, nr=9, period=50.0, a0=3e-4),
+    "planar": lambda: W.base_case(65, 10, 0.7, cartesian=True, south=W.wall(), east=W.wall(),
+                                  west=W.wall(uz=0.0, ur=1e-3), a0=2e-5),
+    "split_top_axis": lambda: W.base_case(40, 17, 0.6, swirl=True, thermal=True, tau_h=0.7,
+                                          north=W.wall(omega=1e-3, thermal=1, T=1.0),
+                                          west=W.split_wall(W.wall(thermal=1, T=0.3),
+                                                            W.freeslip(), 6.0),
+                                          east=W.split_wall(W.wall(omega=-2e-3, thermal=1, T=0.0),
+                                                            W.freeslip(), 7.0),
+                                          gbeta=1e-4, T_ref=0.5),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("prec", [0, 1])
+def test_random_state_cases(name, prec):
+    """Seeded random fields (all components nonzero) then 300 steps."""
+    case = CASES[name]()
+    fields = _fields(case, 7)
+    e, lat, o = _compare(case, 300, prec, fields, label=name)
+    print(name, prec, e)
+
+
+def test_first_step_from_seed():
+    """One step from seeded random fields (own-slot read, then collision)."""
+    case = CASES["melt"]()
+    _compare(case, 1, 0, _fields(case, 3), label="one step")
+    _compare(case, 2, 0, _fields(case, 3), label="two steps")
+
+
+@pytest.mark.parametrize("launch", [(64, 1, 0, 0, 0), (128, 2, 0, 0, 1), (256, 4, 0, 0, 1),
+                                    (64, 8, 512, 1, 1), (64, 4, 64, 0, 0), (512, 2, 0, 0, 1)])
+def test_launch_shape_bitwise(launch):
+    """FP64 results do not depend on the tile shape or persistent grid."""
+    case = CASES["split_top_axis"]()
+    fields = _fields(case, 11)
+    ref = to_np(gpu_run([case], 257, 0, [fields]).macros())
+    got = to_np(gpu_run([case], 257, 0, [fields], launch=launch).macros())
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), k
+
+
+def test_graph_vs_direct_bitwise():
+    case = CASES["pipe_periodic_force"]()
+    fields = _fields(case, 12)
+    a = to_np(gpu_run([case], 300, 0, [fields], graph=0).macros())
+    b = to_np(gpu_run([case], 300, 0, [fields], graph=16).macros())
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_batch_equals_single_bitwise():
+    """Uneven lattices in one launch match separate handles exactly (FP64)."""
+    cases = [CASES["cavity"](), W.cavity(20, 133, 250.0), W.cavity(64, 65, 900.0)]
+    fields = [_fields(c, 20 + k) for k, c in enumerate(cases)]
+    lat = gpu_run(cases, 211, 0, fields)
+    ms = lat.macros_list()
+    for k, c in enumerate(cases):
+        single = to_np(gpu_run([c], 211, 0, [fields[k]]).macros())
+        for key in single:
+            assert np.array_equal(ms[k][key].double().cpu().numpy().reshape(-1), single[key]), (k, key)
+
+
+def test_batch_parity_vs_oracle_fp32():
+    cases = [W.cavity(24, 50, 300.0), W.cavity(33, 41, 500.0)]
+    fields = [_fields(c, 30 + k) for k, c in enumerate(cases)]
+    lat = gpu_run(cases, 400, 1, fields)
+    ms = lat.macros_list()
+    for k, c in enumerate(cases):
+        o = oracle_run(c, 400, fields[k])
+        assert_parity(c, to_np(ms[k]), o.macros(), 1, "batch %d" % k)
+
+
+def test_residual_matches_oracle():
+    """Eq. (57) on the GPU against the oracle's, after the same steps."""
+    case = CASES["cavity"]()
+    for prec, tol in ((0, 1e-12), (1, 1e-6)):
+        o = oracle_run(case, 500)
+        lat = gpu_run([case], 500, prec)
+        r_g = lat.residual()[0]
+        r_o = o.residual()
+        u_max = float(np.abs(o.macros()["uth"]).max())
+        assert abs(r_g - r_o) <= tol * u_max, (prec, r_g, r_o)
+
+
+def test_save_load_bitwise():
+    case = CASES["melt"]()
+    fields = _fields(case, 40)
+    a = gpu_run([case], 150, 0, [fields])
+    blob = a.save()
+    a.step(77)
+    ref = to_np(a.macros())
+    r_ref = a.residual()
+    b = gpu_run([case], 0, 0, [fields])
+    b.load(blob)
+    assert b.time() == 150
+    b.step(77)
+    got = to_np(b.macros())
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), k
+    assert np.array_equal(r_ref, b.residual())
+
+
+def test_batch_run_statuses():
+    """Converged lattices stop while the others continue; a NaN seed makes
+    one lattice DIVERGED without touching the rest; max_steps gives CAPPED."""
+    import torch
+    from paper_1003_0282_amd import lbaxi as L
+    cases = [W.hagen_poiseuille(nz=4, nr=8), W.hagen_poiseuille(nz=4, nr=16),
+             W.hagen_poiseuille(nz=4, nr=32)]
+    lat = L.Lattices(cases, L.FP64)
+    uz = torch.zeros(lat.nodes, dtype=torch.float64)
+    uz[lat.offsets[1] + 5] = float("nan")
+    lat.seed(uz=uz)
+    res = lat.run(tol=1e-13, max_steps=6000, check_every=500)
+    assert res.status[1] == L.DIVERGED
+    assert res.status[0] == L.CONVERGED
+    assert res.status[2] in (L.CAPPED, L.CONVERGED)
+    assert res.steps[0] < res.steps[2] or res.status[2] == L.CONVERGED
+    # the converged lattice stopped: its state equals a plain run of that length
+    single = gpu_run([cases[0]], int(res.steps[0]), 0)
+    m0 = lat.macros_list()[0]
+    assert np.array_equal(m0["uz"].cpu().numpy().reshape(-1), single.macros()["uz"].cpu().numpy())
+    lat2 = L.Lattices(cases[:1], L.FP64)
+    r2 = lat2.run(tol=0.0, max_steps=1000, check_every=250)
+    assert r2.status[0] == L.CAPPED and r2.steps[0] == 1000
+
+
+def test_autotune_keeps_results():
+    """Autotuning advances the real state; the result equals an untuned run."""
+    case = W.cavity(40, 150, 600.0)
+    fields = _fields(case, 50)
+    a = gpu_run([case], 0, 0, [fields])
+    cfg = a.autotune(steps_per_trial=4)
+    t = a.time()
+    assert t > 0 and len(cfg) == 5
+    ref = to_np(gpu_run([case], t, 0, [fields]).macros())
+    got = to_np(a.macros())
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), k
