@@ -105,6 +105,35 @@ def cpu_baseline(cases, seconds: float):
                 k, len(cases), done, el, "; ".join(used[:4]) + (" ..." if len(used) > 4 else ""))}
 
 
+def copy_probe(steps: int, warmup: int, nbytes: int = 4 << 30):
+    """Device-to-device streaming copy through the library's copy kernel: the
+    practical HBM ceiling the step kernel is compared with."""
+    import ctypes as C
+    import torch
+    from paper_1003_0282_amd import lbaxi as L
+    L._L.lbaxi_stream_copy.restype = C.c_int32
+    L._L.lbaxi_stream_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    call = lambda: L._check(L._L.lbaxi_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes,
+                                                   s.cuda_stream), "lbaxi_stream_copy")
+    for _ in range(max(1, warmup)):
+        call()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        call()
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    gbs = 2 * nbytes / (ms / 1e3) / 1e9
+    return {"metric": "copy bandwidth (read + write)", "value": round(gbs, 1), "unit": "GB/s",
+            "bytes_per_launch": 2 * nbytes, "ms_per_launch": round(ms, 4),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +143,8 @@ def main():
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--launch", default="", help="tile_z,tile_r,grid,xcd,nt (skips autotune)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--prec", default="", choices=["", "fp64", "fp32", "fp32fast"],
+                    help="override the workload's precision")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the workload is a single-GPU batch and no "
@@ -123,7 +154,13 @@ def main():
     import torch
     from paper_1003_0282_amd import lbaxi as L
 
+    if args.workload == "copy":
+        print(json.dumps(copy_probe(args.steps, args.warmup)))
+        return
     cases, prec, label = workload(args.workload)
+    if args.prec:
+        prec = {"fp64": 0, "fp32": 1, "fp32fast": 2}[args.prec]
+        label += " [precision %s]" % args.prec
     torch.cuda.set_device(0)
     lat = L.Lattices(cases, prec)
     lat.seed()
@@ -165,9 +202,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == 0 else "f32",
+        "dtype": "f32" if prec == 2 else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "description": label, "lattices": len(cases),
+        "config": {"workload": args.workload, "description": label,
+                   "population_storage": "f64" if prec == 0 else "f32",
+                   "lattices": len(cases),
                    "nodes": nodes, "bytes_per_update": bpu,
                    "bytes_per_update_f_only_convention": 144 if prec == 0 else 72,
                    "launch": {"tile_z": launch[0], "tile_r": launch[1], "grid": launch[2],

@@ -60,7 +60,13 @@ enum {
   LBAXI_ESTATE = -6     /* call not valid in the current state */
 };
 
-enum { LBAXI_FP64 = 0, LBAXI_FP32 = 1 };
+/* Precision of a handle.  FP64: populations stored and computed in double.
+ * FP32: populations stored in float (as deviations from w_a rho0), every
+ * node update computed in double -- FP32 rounding inside the update, not in
+ * storage, is what limits a float path on slowly converging flows.
+ * FP32_FAST: stored and computed in float.  Fields passed to lbaxi_seed and
+ * returned by lbaxi_macros are double for FP64 and float otherwise. */
+enum { LBAXI_FP64 = 0, LBAXI_FP32 = 1, LBAXI_FP32_FAST = 2 };
 enum { LBAXI_SWIRL = 1u, LBAXI_THERMAL = 2u, LBAXI_CARTESIAN = 4u };
 enum {
   LBAXI_SIDE_AXIS = 0,     /* south side only, r0 = 0: specular axis */
@@ -92,7 +98,7 @@ typedef struct {
 typedef struct {
   int32_t nz, nr;   /* nodes along z and r, each >= 2 */
   double r0;        /* radius of node row 0; 0 with an axis south side */
-  int32_t prec;     /* LBAXI_FP64 or LBAXI_FP32 (all instances of a batch) */
+  int32_t prec;     /* LBAXI_FP64 / _FP32 / _FP32_FAST (same for a whole batch) */
   uint32_t fields;  /* LBAXI_SWIRL | LBAXI_THERMAL | LBAXI_CARTESIAN */
   double tau;       /* tau_s of f */
   double tau_g;     /* tau_s of g, 0 -> paper default */
@@ -195,6 +201,12 @@ size_t lbaxi_abi_desc_size(void);
 
 /* Sum of nr * nz over the handle's lattices and the number of lattices. */
 lbaxi_status lbaxi_node_count(const lbaxi_t* h, int64_t* nodes, int32_t* n);
+
+/* Plain device-to-device streaming copy of `bytes` (a multiple of 16, both
+ * pointers 16-byte aligned) on hip_stream: the bandwidth reference used to
+ * calibrate HBM counters and the roofline fraction of the step kernel.
+ * Asynchronous; EINVAL on misaligned arguments. */
+lbaxi_status lbaxi_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -28,7 +28,7 @@ using namespace lbx;
 // ============================================================================
 
 struct Tile {
-  int inst, z0, r0, interior;
+  int inst, z0, r0, pad;
 };
 
 struct TileRange {
@@ -54,14 +54,15 @@ __device__ inline TileRange tile_range(int ntiles, int xcd) {
   return t;
 }
 
-template <typename R>
+// S: storage type of populations and fields; R: compute type.
+template <typename S>
 struct StepArgs {
   const InstP* ip;
   const Tile* tiles;
   const int* ntiles;
-  const R* src;
-  R* dst;
-  R* spd;
+  const S* src;
+  S* dst;
+  double* spd;            // |u| of the level processed (Eq. 57), always FP64
   const long long* tdev;  // time base in device memory (graph replays) or NULL
   long long t0;           // time level when tdev is NULL
   int k;                  // step index inside a graph
@@ -72,16 +73,19 @@ struct StepArgs {
   int nt_store;
 };
 
-template <typename R>
-__device__ inline void st(R* p, R v, int nt) {
+template <typename S>
+__device__ inline void st(S* p, S v, int nt) {
   if (nt)
     __builtin_nontemporal_store(v, p);
   else
     *p = v;
 }
 
-template <typename R, int F>
-__global__ void __launch_bounds__(1024) k_step(StepArgs<R> A) {
+// One time step: pull (padded planes, no boundary tests), macros, collision,
+// store at the node's own slots of the other buffer.  The halo kernel then
+// completes the boundary rules for the next pull.
+template <typename S, typename R, int F>
+__global__ void __launch_bounds__(1024) k_step(StepArgs<S> A) {
   const long long t = A.tdev ? (*A.tdev + A.k) : A.t0;
   const int ntiles = *A.ntiles;
   const TileRange tr = tile_range(ntiles, A.xcd);
@@ -94,44 +98,75 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs<R> A) {
     const int i = T.z0 + li, j = T.r0 + lj;
     if (i >= P.nz || j >= P.nr) continue;
     const PR<R> p = make_pr<R>(P, t);
-    const R* s = A.src + P.off;
+    const S* s = A.src + P.off;
     R f[9], g[4], h[4];
-    load_node<R, F>(P, s, i, j, T.interior != 0, pre, f, g, h);
+    load_node<S, R, F>(P, s, i, j, pre, f, g, h);
     const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
     if ((F & F_SWIRL) && axis_row) {
       // non-equilibrium extrapolation of g from row 1 (Sec. IV B)
       R f1[9], g1[4], h1[4];
-      load_node<R, F>(P, s, i, 1, false, pre, f1, g1, h1);
-      const Mac<R> m1 = macros<R, F>(p, 1, false, f1, g1, h1);
+      load_node<S, R, F>(P, s, i, 1, pre, f1, g1, h1);
+      const Mac<R> m1 = macros<R, F>(p, make_row<R, F>(p, 1), false, f1, g1, h1);
       const R q = (R)0.25 * p.rho0 * m1.uth;
 #pragma unroll
       for (int a = 0; a < 4; ++a)
         g[a] = g1[a] - q * ((R)1 + (R)2 * ((R)ez4(a) * m1.uz + (R)er4(a) * m1.ur));
     }
-    const Mac<R> m = macros<R, F>(p, j, axis_row, f, g, h);
-    collide<R, F>(p, m, f, g, h);
-    R* d = A.dst + P.off;
-    const int pl = P.plane, o = j * P.nz + i;
+    const Row<R> rw = make_row<R, F>(p, j);
+    const Mac<R> m = macros<R, F>(p, rw, axis_row, f, g, h);
+    collide<R, F>(p, rw, m, f, g, h);
+    S* d = A.dst + P.off;
+    const int pl = P.plane, o = nidx(P, j, i);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) st(d + a * pl + o, f[a], A.nt_store);
+    for (int a = 0; a < 9; ++a) st(d + a * pl + o, (S)f[a], A.nt_store);
     if (F & F_SWIRL) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a) st(d + (9 + a) * pl + o, g[a], A.nt_store);
+      for (int a = 0; a < 4; ++a) st(d + (9 + a) * pl + o, (S)g[a], A.nt_store);
     }
     if (F & F_THERMAL) {
       const int hb = (F & F_SWIRL) ? 13 : 9;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) st(d + (hb + a) * pl + o, h[a], A.nt_store);
+      for (int a = 0; a < 4; ++a) st(d + (hb + a) * pl + o, (S)h[a], A.nt_store);
     }
-    if (A.mode & MODE_SPEED) A.spd[P.off_fld + o] = sqrt(m.uz * m.uz + m.ur * m.ur);
+    if (A.mode & MODE_SPEED)
+      A.spd[P.off_fld + (long long)j * P.nz + i] = (double)sqrt(m.uz * m.uz + m.ur * m.ur);
   }
 }
 
+// Boundary node number p of a lattice: row 0, row nr-1, then columns 0 and
+// nz-1 without their corners.
+__device__ inline void perimeter_node(const InstP& P, int p, int& i, int& j) {
+  const int nz = P.nz, nr = P.nr;
+  if (p < nz) { i = p; j = 0; return; }
+  p -= nz;
+  if (p < nz) { i = p; j = nr - 1; return; }
+  p -= nz;
+  if (p < nr - 2) { i = 0; j = 1 + p; return; }
+  p -= nr - 2;
+  i = nz - 1; j = 1 + p;
+}
+
+// Ghost-slot fill after a step: tiles here are {instance, first perimeter
+// node, 0, 0}, one thread per perimeter node.
+template <typename S, int F>
+__global__ void __launch_bounds__(256) k_halo(const InstP* ip, const Tile* tiles,
+                                              const int* ntiles, S* buf) {
+  const int ti = blockIdx.x;
+  if (ti >= *ntiles) return;
+  const Tile T = tiles[ti];
+  const InstP& P = ip[T.inst];
+  const int p = T.z0 + threadIdx.x;
+  if (p >= 2 * P.nz + 2 * (P.nr - 2)) return;
+  int i, j;
+  perimeter_node(P, p, i, j);
+  HaloFill<S, F, 0>::run(P, buf + P.off, i, j);
+}
+
 // Equilibrium seeding: f^ = f_eq - S/2 at rho = rho0, g = g_eq, h = h_eq.
-template <typename R, int F>
+template <typename S, typename R, int F>
 __global__ void __launch_bounds__(1024) k_seed(const InstP* ip, const Tile* tiles,
-                                               const int* ntiles, R* buf, const R* uz_in,
-                                               const R* ur_in, const R* uth_in, const R* T_in,
+                                               const int* ntiles, S* buf, const S* uz_in,
+                                               const S* ur_in, const S* uth_in, const S* T_in,
                                                int tzlog) {
   const int ti = blockIdx.x;
   if (ti >= *ntiles) return;
@@ -143,31 +178,31 @@ __global__ void __launch_bounds__(1024) k_seed(const InstP* ip, const Tile* tile
   const PR<R> p = make_pr<R>(P, 0);
   const long long fo = P.off_fld + (long long)j * P.nz + i;
   const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
-  const R uz = uz_in ? uz_in[fo] : (R)0;
-  const R ur = (ur_in && !axis_row) ? ur_in[fo] : (R)0;
-  const R uth = ((F & F_SWIRL) && uth_in && !axis_row) ? uth_in[fo] : (R)0;
-  const R dT = ((F & F_THERMAL) && T_in) ? T_in[fo] - p.T_ref : (R)0;
-  const R ir = inv_radius(p, j);
+  const R uz = uz_in ? (R)uz_in[fo] : (R)0;
+  const R ur = (ur_in && !axis_row) ? (R)ur_in[fo] : (R)0;
+  const R uth = ((F & F_SWIRL) && uth_in && !axis_row) ? (R)uth_in[fo] : (R)0;
+  const R dT = ((F & F_THERMAL) && T_in) ? (R)T_in[fo] - p.T_ref : (R)0;
+  const R ir = make_row<R, F>(p, j).ir;
   R Fz = p.a_t;
   if (F & F_THERMAL) Fz += p.rho0 * p.gbeta * dT;
   R Fr = -(R)2 * p.mu0 * ur * ir * ir;
   if (F & F_SWIRL) Fr += p.rho0 * uth * uth * ir;
   const R usq = uz * uz + ur * ur;
-  R* d = buf + P.off;
-  const int pl = P.plane, o = j * P.nz + i;
+  S* d = buf + P.off;
+  const int pl = P.plane, o = nidx(P, j, i);
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
     const R ez = (R)ez9(a), er = (R)er9(a), w = (R)w9(a);
     const R eu = ez * uz + er * ur;
     const R Pa = (R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * usq;
-    const R S = w * ((R)1 + Pa) * ((R)3 * ((ez - uz) * Fz + (er - ur) * Fr) - p.rho0 * ur * ir);
-    d[a * pl + o] = w * p.rho0 * Pa - (R)0.5 * S;
+    const R Sa = w * ((R)1 + Pa) * ((R)3 * ((ez - uz) * Fz + (er - ur) * Fr) - p.rho0 * ur * ir);
+    d[a * pl + o] = (S)(w * p.rho0 * Pa - (R)0.5 * Sa);
   }
   if (F & F_SWIRL) {
 #pragma unroll
     for (int a = 0; a < 4; ++a)
       d[(9 + a) * pl + o] =
-          (R)0.25 * p.rho0 * uth * ((R)1 + (R)2 * ((R)ez4(a) * uz + (R)er4(a) * ur));
+          (S)((R)0.25 * p.rho0 * uth * ((R)1 + (R)2 * ((R)ez4(a) * uz + (R)er4(a) * ur)));
   }
   if (F & F_THERMAL) {
     const int hb = (F & F_SWIRL) ? 13 : 9;
@@ -175,28 +210,28 @@ __global__ void __launch_bounds__(1024) k_seed(const InstP* ip, const Tile* tile
 #pragma unroll
     for (int a = 0; a < 4; ++a)
       d[(hb + a) * pl + o] =
-          (R)0.25 * (dT + Tv * (R)2 * ((R)ez4(a) * uz + (R)er4(a) * ur));
+          (S)((R)0.25 * (dT + Tv * (R)2 * ((R)ez4(a) * uz + (R)er4(a) * ur)));
   }
 }
 
 // Macros at the current level of each lattice (own buffer parity and time).
-template <typename R, int F>
-__device__ inline Mac<R> node_macros(const InstP& P, const InstDyn& D, const R* bufA,
-                                     const R* bufB, int i, int j, bool interior) {
+template <typename S, typename R, int F>
+__device__ inline Mac<R> node_macros(const InstP& P, const InstDyn& D, const S* bufA,
+                                     const S* bufB, int i, int j) {
   const PR<R> p = make_pr<R>(P, D.t);
-  const R* s = (D.cur ? bufB : bufA) + P.off;
+  const S* s = (D.cur ? bufB : bufA) + P.off;
   R f[9], g[4], h[4];
-  load_node<R, F>(P, s, i, j, interior, D.pre != 0, f, g, h);
+  load_node<S, R, F>(P, s, i, j, D.pre != 0, f, g, h);
   const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
   // on the axis u_th = 0 and g does not enter the macros of Eqs. (16)-(17)
-  return macros<R, F>(p, j, axis_row, f, g, h);
+  return macros<R, F>(p, make_row<R, F>(p, j), axis_row, f, g, h);
 }
 
-template <typename R, int F>
+template <typename S, typename R, int F>
 __global__ void __launch_bounds__(1024) k_macros(const InstP* ip, const InstDyn* dyn,
                                                  const Tile* tiles, const int* ntiles,
-                                                 const R* bufA, const R* bufB, R* rho, R* uz,
-                                                 R* ur, R* uth, R* T, int tzlog) {
+                                                 const S* bufA, const S* bufB, S* rho, S* uz,
+                                                 S* ur, S* uth, S* T, int tzlog) {
   const int ti = blockIdx.x;
   if (ti >= *ntiles) return;
   const Tile Tl = tiles[ti];
@@ -204,13 +239,13 @@ __global__ void __launch_bounds__(1024) k_macros(const InstP* ip, const InstDyn*
   const int tz = 1 << tzlog;
   const int i = Tl.z0 + (threadIdx.x & (tz - 1)), j = Tl.r0 + (threadIdx.x >> tzlog);
   if (i >= P.nz || j >= P.nr) return;
-  const Mac<R> m = node_macros<R, F>(P, dyn[Tl.inst], bufA, bufB, i, j, Tl.interior != 0);
+  const Mac<R> m = node_macros<S, R, F>(P, dyn[Tl.inst], bufA, bufB, i, j);
   const long long o = P.off_fld + (long long)j * P.nz + i;
-  if (rho) rho[o] = m.rho;
-  if (uz) uz[o] = m.uz;
-  if (ur) ur[o] = m.ur;
-  if (uth) uth[o] = m.uth;
-  if (T) T[o] = (R)P.T_ref + m.dT;
+  if (rho) rho[o] = (S)m.rho;
+  if (uz) uz[o] = (S)m.uz;
+  if (ur) ur[o] = (S)m.ur;
+  if (uth) uth[o] = (S)m.uth;
+  if (T) T[o] = (S)((R)P.T_ref + m.dT);
 }
 
 // Bit pattern of a non-negative double: monotone in the value, and every NaN
@@ -220,11 +255,12 @@ __device__ inline unsigned long long key(double v) {
 }
 
 // Eq. (57) per lattice: max | |u|(t) - |u|(t-1) | with |u|(t-1) in spd.
-template <typename R, int F>
+template <typename S, typename R, int F>
 __global__ void __launch_bounds__(1024) k_residual(const InstP* ip, const InstDyn* dyn,
                                                    const Tile* tiles, const int* ntiles,
-                                                   const R* bufA, const R* bufB, const R* spd,
-                                                   unsigned long long* res, int tzlog) {
+                                                   const S* bufA, const S* bufB,
+                                                   const double* spd, unsigned long long* res,
+                                                   int tzlog) {
   __shared__ unsigned long long red[16];
   const int ti = blockIdx.x;
   if (ti >= *ntiles) return;  // uniform per workgroup
@@ -234,9 +270,9 @@ __global__ void __launch_bounds__(1024) k_residual(const InstP* ip, const InstDy
   const int i = Tl.z0 + (threadIdx.x & (tz - 1)), j = Tl.r0 + (threadIdx.x >> tzlog);
   unsigned long long v = 0;
   if (i < P.nz && j < P.nr) {
-    const Mac<R> m = node_macros<R, F>(P, dyn[Tl.inst], bufA, bufB, i, j, Tl.interior != 0);
+    const Mac<R> m = node_macros<S, R, F>(P, dyn[Tl.inst], bufA, bufB, i, j);
     const double sp = (double)sqrt(m.uz * m.uz + m.ur * m.ur);
-    v = key(sp - (double)spd[P.off_fld + (long long)j * P.nz + i]);
+    v = key(sp - spd[P.off_fld + (long long)j * P.nz + i]);
   }
   // wave-level max, then across the waves of the workgroup
   for (int off = 32; off > 0; off >>= 1) {
@@ -267,6 +303,16 @@ __global__ void k_add_time(long long* t, long long dv) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *t += dv;
 }
 
+// Plain streaming copy (16 bytes per lane per iteration), the bandwidth
+// reference against which the step kernel's HBM traffic is calibrated.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src,
+                                              u32x4* __restrict__ dst, long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+    __builtin_nontemporal_store(src[k], dst + k);
+}
+
 // ============================================================================
 // host runtime
 // ============================================================================
@@ -293,6 +339,8 @@ int n_planes(unsigned fields) {
   return 9 + ((fields & LBAXI_SWIRL) ? 4 : 0) + ((fields & LBAXI_THERMAL) ? 4 : 0);
 }
 
+size_t elem_size(int prec) { return prec == LBAXI_FP64 ? 8 : 4; }
+
 // Worst-case tile count over the shapes the runtime accepts (tile_z >= 64).
 long long max_tiles(const std::vector<lbaxi_desc>& d) {
   long long n = 0;
@@ -300,8 +348,21 @@ long long max_tiles(const std::vector<lbaxi_desc>& d) {
   return n;
 }
 
+// Boundary nodes of a lattice and the halo workgroups (256 nodes) covering them.
+int perimeter(const lbaxi_desc& x) { return 2 * x.nz + 2 * (x.nr - 2); }
+long long halo_tiles(const std::vector<lbaxi_desc>& d) {
+  long long n = 0;
+  for (const auto& x : d) n += (perimeter(x) + 255) / 256;
+  return n;
+}
+long long padded_plane(const lbaxi_desc& x) { return (long long)(x.nr + 2) * (x.nz + 2); }
+
+// Device workspace: parameters, three work lists (all tiles / tiles of
+// running lattices / halo chunks of running lattices) with their counts,
+// residual words, the time base, two padded population buffers and |u| of
+// Eq. (57).
 struct Layout {
-  size_t ip, dyn, tiles, ntiles, res, tdev, bufA, bufB, spd, total;
+  size_t ip, dyn, tiles_all, tiles_run, tiles_halo, counts, res, tdev, bufA, bufB, spd, total;
   std::vector<long long> off, off_fld;
   long long buf_elems, fld_elems;
 };
@@ -309,27 +370,30 @@ struct Layout {
 Layout layout(const std::vector<lbaxi_desc>& d) {
   Layout L;
   const int n = (int)d.size();
-  const size_t es = d[0].prec == LBAXI_FP64 ? 8 : 4;
+  const size_t es = elem_size(d[0].prec);
   const int np = n_planes(d[0].fields);
+  const size_t tb = sizeof(Tile) * (size_t)max_tiles(d);
   size_t o = 0;
   L.ip = o; o = align_up(o + sizeof(InstP) * n, 256);
   L.dyn = o; o = align_up(o + sizeof(InstDyn) * n, 256);
-  L.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)max_tiles(d), 256);
-  L.ntiles = o; o = align_up(o + sizeof(int), 256);
+  L.tiles_all = o; o = align_up(o + tb, 256);
+  L.tiles_run = o; o = align_up(o + tb, 256);
+  L.tiles_halo = o; o = align_up(o + sizeof(Tile) * (size_t)halo_tiles(d), 256);
+  L.counts = o; o = align_up(o + 4 * sizeof(int), 256);
   L.res = o; o = align_up(o + sizeof(unsigned long long) * n, 256);
   L.tdev = o; o = align_up(o + sizeof(long long), 256);
   long long e = 0, fe = 0;
   for (const auto& x : d) {
     L.off.push_back(e);
     L.off_fld.push_back(fe);
-    e += align_up((size_t)np * x.nz * x.nr, 64);
+    e += align_up((size_t)np * padded_plane(x), 64);
     fe += (long long)x.nz * x.nr;
   }
   L.buf_elems = e;
   L.fld_elems = fe;
   L.bufA = o; o = align_up(o + es * (size_t)e, 256);
   L.bufB = o; o = align_up(o + es * (size_t)e, 256);
-  L.spd = o; o = align_up(o + es * (size_t)align_up(fe, 64), 256);
+  L.spd = o; o = align_up(o + sizeof(double) * (size_t)align_up(fe, 64), 256);
   L.total = o;
   return L;
 }
@@ -348,9 +412,10 @@ lbaxi_status validate(const lbaxi_desc& d, int k) {
     return fail(s, b);
   };
   if (d.nz < 2 || d.nr < 2) return bad(LBAXI_EINVAL, "nz and nr must be >= 2");
-  if ((long long)n_planes(d.fields) * d.nz * d.nr >= (1LL << 31))
+  if ((long long)n_planes(d.fields) * (d.nz + 2) * (d.nr + 2) >= (1LL << 31))
     return bad(LBAXI_EINVAL, "lattice too large for 32-bit in-lattice offsets");
-  if (d.prec != LBAXI_FP64 && d.prec != LBAXI_FP32) return bad(LBAXI_EINVAL, "bad prec");
+  if (d.prec != LBAXI_FP64 && d.prec != LBAXI_FP32 && d.prec != LBAXI_FP32_FAST)
+    return bad(LBAXI_EINVAL, "bad prec");
   if (d.fields & ~7u) return bad(LBAXI_EINVAL, "unknown field bits");
   if (!(d.rho0 > 0)) return bad(LBAXI_EINVAL, "rho0 must be positive");
   if (!(d.r0 >= 0)) return bad(LBAXI_EINVAL, "r0 must be >= 0");
@@ -398,7 +463,8 @@ InstP make_inst(const lbaxi_desc& d, long long off, long long off_fld) {
   memset(&P, 0, sizeof P);
   P.nz = d.nz;
   P.nr = d.nr;
-  P.plane = d.nz * d.nr;
+  P.pitch = d.nz + 2;
+  P.plane = (d.nr + 2) * (d.nz + 2);
   P.cart = (d.fields & LBAXI_CARTESIAN) ? 1 : 0;
   P.r0 = d.r0;
   taus(d, P.tau, P.tau_g, P.tau_h);
@@ -439,6 +505,8 @@ int ilog2(int x) {
   return l;
 }
 
+enum { LIST_ALL = 0, LIST_RUN = 1, LIST_HALO = 2 };
+
 }  // namespace
 
 struct lbaxi_s {
@@ -452,8 +520,8 @@ struct lbaxi_s {
   Layout L;
   InstP* d_ip = nullptr;
   InstDyn* d_dyn = nullptr;
-  Tile* d_tiles = nullptr;
-  int* d_ntiles = nullptr;
+  Tile* d_tiles[3] = {nullptr, nullptr, nullptr};
+  int* d_counts = nullptr;  // [LIST_ALL, LIST_RUN, LIST_HALO]
   unsigned long long* d_res = nullptr;
   long long* d_t = nullptr;
   void* bufA = nullptr;
@@ -463,7 +531,6 @@ struct lbaxi_s {
   int cur = 0;
   bool pre = true;
   long long t = 0;
-  bool have_spd = false;
   // per lattice
   std::vector<int> status;
   std::vector<InstDyn> dyn;
@@ -472,48 +539,47 @@ struct lbaxi_s {
   // launch shape
   int tz = 64, tr = 4, grid = 0, xcd = 0, nt = 1;
   int K = 64;
-  std::vector<Tile> tiles_all;  // every lattice, current shape (seed/macros/residual)
-  std::vector<Tile> tiles_run;  // RUNNING lattices only (step)
-  int ntiles_all = 0, ntiles_run = 0;
-  // which tile list the device table holds: 0 none, 1 all, 2 run
-  int dev_tiles = 0;
+  std::vector<Tile> lists[3];
+  int count[3] = {0, 0, 0};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
 };
 
 namespace {
 
-void build_tiles(lbaxi_t* h) {
-  h->tiles_all.clear();
-  h->tiles_run.clear();
-  for (int k = 0; k < h->n; ++k) {
-    const lbaxi_desc& d = h->desc[k];
-    for (int j0 = 0; j0 < d.nr; j0 += h->tr)
-      for (int i0 = 0; i0 < d.nz; i0 += h->tz) {
-        Tile T;
-        T.inst = k;
-        T.z0 = i0;
-        T.r0 = j0;
-        T.interior = (i0 >= 1 && i0 + h->tz <= d.nz - 1 && j0 >= 1 && j0 + h->tr <= d.nr - 1);
-        h->tiles_all.push_back(T);
-        if (h->status[k] == LBAXI_RUNNING) h->tiles_run.push_back(T);
-      }
-  }
-  h->ntiles_all = (int)h->tiles_all.size();
-  h->ntiles_run = (int)h->tiles_run.size();
-  h->dev_tiles = 0;
+void drop_graphs(lbaxi_t* h) {
+  for (int q = 0; q < 2; ++q)
+    if (h->gexec[q]) {
+      (void)hipGraphExecDestroy(h->gexec[q]);
+      h->gexec[q] = nullptr;
+    }
 }
 
-lbaxi_status upload_tiles(lbaxi_t* h, int which) {
-  if (which == 2 && h->ntiles_run == h->ntiles_all) which = 1;  // same list
-  if (h->dev_tiles == which) return LBAXI_OK;
-  const std::vector<Tile>& v = which == 1 ? h->tiles_all : h->tiles_run;
-  const int n = (int)v.size();
-  if (n) HIPCHK(hipMemcpyAsync(h->d_tiles, v.data(), sizeof(Tile) * n, hipMemcpyHostToDevice,
-                               h->stream));
-  HIPCHK(hipMemcpyAsync(h->d_ntiles, &n, sizeof(int), hipMemcpyHostToDevice, h->stream));
-  // the host vectors must outlive the copies: synchronise (tables change rarely)
+// Rebuild the three work lists for the current shape and statuses, upload
+// them (synchronously: the host vectors are reused) and drop stale graphs.
+lbaxi_status build_tiles(lbaxi_t* h) {
+  for (auto& v : h->lists) v.clear();
+  for (int k = 0; k < h->n; ++k) {
+    const lbaxi_desc& d = h->desc[k];
+    const bool run = h->status[k] == LBAXI_RUNNING;
+    for (int j0 = 0; j0 < d.nr; j0 += h->tr)
+      for (int i0 = 0; i0 < d.nz; i0 += h->tz) {
+        const Tile T = {k, i0, j0, 0};
+        h->lists[LIST_ALL].push_back(T);
+        if (run) h->lists[LIST_RUN].push_back(T);
+      }
+    if (run)
+      for (int p0 = 0; p0 < perimeter(d); p0 += 256) h->lists[LIST_HALO].push_back(Tile{k, p0, 0, 0});
+  }
+  int cnt[4] = {0, 0, 0, 0};
+  for (int q = 0; q < 3; ++q) {
+    h->count[q] = cnt[q] = (int)h->lists[q].size();
+    if (cnt[q])
+      HIPCHK(hipMemcpyAsync(h->d_tiles[q], h->lists[q].data(), sizeof(Tile) * cnt[q],
+                            hipMemcpyHostToDevice, h->stream));
+  }
+  HIPCHK(hipMemcpyAsync(h->d_counts, cnt, sizeof cnt, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
-  h->dev_tiles = which;
+  drop_graphs(h);
   return LBAXI_OK;
 }
 
@@ -532,43 +598,49 @@ lbaxi_status upload_dyn(lbaxi_t* h) {
   return LBAXI_OK;
 }
 
-void drop_graphs(lbaxi_t* h) {
-  for (int q = 0; q < 2; ++q)
-    if (h->gexec[q]) {
-      (void)hipGraphExecDestroy(h->gexec[q]);
-      h->gexec[q] = nullptr;
-    }
-}
+template <typename S, typename R, int F>
+void* step_fn() { return reinterpret_cast<void*>(&k_step<S, R, F>); }
+template <typename S, typename R, int F>
+void* halo_fn() { return reinterpret_cast<void*>(&k_halo<S, F>); }
+template <typename S, typename R, int F>
+void* seed_fn() { return reinterpret_cast<void*>(&k_seed<S, R, F>); }
+template <typename S, typename R, int F>
+void* macros_fn() { return reinterpret_cast<void*>(&k_macros<S, R, F>); }
+template <typename S, typename R, int F>
+void* resid_fn() { return reinterpret_cast<void*>(&k_residual<S, R, F>); }
 
-template <typename R, int F>
-void* step_fn() {
-  return reinterpret_cast<void*>(&k_step<R, F>);
-}
+// Kernel instance for (precision, field set): FP64 stores and computes in
+// double, FP32 stores float and computes in double, FP32_FAST is float only.
+#define PICK_F(name, S, R, fields)                    \
+  (((fields) & 3) == 0   ? name<S, R, 0>()            \
+   : ((fields) & 3) == 1 ? name<S, R, 1>()            \
+   : ((fields) & 3) == 2 ? name<S, R, 2>()            \
+                         : name<S, R, 3>())
+#define PICK(name, prec, fields)                                   \
+  ((prec) == LBAXI_FP64   ? PICK_F(name, double, double, fields)   \
+   : (prec) == LBAXI_FP32 ? PICK_F(name, float, double, fields)    \
+                          : PICK_F(name, float, float, fields))
 
-void* pick_step(int prec, unsigned fields) {
-  const int F = fields & 3;
-  if (prec == LBAXI_FP64) {
-    switch (F) {
-      case 0: return step_fn<double, 0>();
-      case 1: return step_fn<double, 1>();
-      case 2: return step_fn<double, 2>();
-      default: return step_fn<double, 3>();
-    }
-  }
-  switch (F) {
-    case 0: return step_fn<float, 0>();
-    case 1: return step_fn<float, 1>();
-    case 2: return step_fn<float, 2>();
-    default: return step_fn<float, 3>();
-  }
-}
-
-// StepArgs is laid out identically for float and double (pointers only).
-StepArgs<double> step_args(lbaxi_t* h, int from, long long t0, bool use_tdev, int k, int mode) {
+// One step-kernel launch: its function, grid and arguments.  StepArgs has the
+// same layout for float and double storage (pointers only).
+struct StepLaunch {
+  void* fn;
+  int grid, block;
   StepArgs<double> a;
+};
+
+StepLaunch step_launch(lbaxi_t* h, int list, int from, long long t0, bool use_tdev, int k,
+                       int mode) {
+  StepLaunch L;
+  L.fn = PICK(step_fn, h->prec, h->fields);
+  L.block = h->tz * h->tr;
+  L.grid = h->grid > 0 ? std::min(h->grid, std::max(1, h->count[list]))
+                       : std::max(1, h->count[list]);
+  if (h->xcd && L.grid >= 8) L.grid &= ~7;
+  StepArgs<double>& a = L.a;
   a.ip = h->d_ip;
-  a.tiles = h->d_tiles;
-  a.ntiles = h->d_ntiles;
+  a.tiles = h->d_tiles[list];
+  a.ntiles = h->d_counts + list;
   a.src = (const double*)(from ? h->bufB : h->bufA);
   a.dst = (double*)(from ? h->bufA : h->bufB);
   a.spd = (double*)h->spd;
@@ -580,46 +652,79 @@ StepArgs<double> step_args(lbaxi_t* h, int from, long long t0, bool use_tdev, in
   a.tr = h->tr;
   a.xcd = h->xcd;
   a.nt_store = h->nt;
-  return a;
+  return L;
 }
 
-int step_grid(const lbaxi_t* h) {
-  return h->grid > 0 ? h->grid : std::max(1, h->ntiles_all);
+// Halo launch filling the ghost slots of buffer `buf` (0 = A, 1 = B).
+struct HaloLaunch {
+  void* fn;
+  int grid;
+  const InstP* ip;
+  const Tile* tiles;
+  const int* ntiles;
+  void* buf;
+};
+
+HaloLaunch halo_launch(lbaxi_t* h, int buf) {
+  HaloLaunch H;
+  H.fn = PICK(halo_fn, h->prec, h->fields);
+  H.grid = std::max(1, h->count[LIST_HALO]);
+  H.ip = h->d_ip;
+  H.tiles = h->d_tiles[LIST_HALO];
+  H.ntiles = h->d_counts + LIST_HALO;
+  H.buf = buf ? h->bufB : h->bufA;
+  return H;
 }
 
+// One time step of every running lattice by direct launches: the step kernel
+// (the first step after seeding reads each node's own slots, over every
+// tile), then the halo fill of the buffer just written.
 lbaxi_status launch_step(lbaxi_t* h, int mode) {
-  StepArgs<double> a = step_args(h, h->cur, h->t, false, 0, mode);
-  void* args[] = {&a};
-  HIPCHK(hipLaunchKernel(pick_step(h->prec, h->fields), dim3(step_grid(h)),
-                         dim3(h->tz * h->tr), args, 0, h->stream));
+  StepLaunch L = h->pre ? step_launch(h, LIST_ALL, h->cur, h->t, false, 0, mode | MODE_PRE)
+                        : step_launch(h, LIST_RUN, h->cur, h->t, false, 0, mode);
+  void* args[] = {&L.a};
+  HIPCHK(hipLaunchKernel(L.fn, dim3(L.grid), dim3(L.block), args, 0, h->stream));
+  HaloLaunch H = halo_launch(h, h->cur ^ 1);
+  void* hargs[] = {&H.ip, &H.tiles, &H.ntiles, &H.buf};
+  HIPCHK(hipLaunchKernel(H.fn, dim3(H.grid), dim3(256), hargs, 0, h->stream));
   h->cur ^= 1;
   h->t += 1;
   h->pre = false;
   return LBAXI_OK;
 }
 
+// Graph of K steps starting from buffer `from`: step kernel, halo fill, step
+// kernel, ...; a last node advances the device time base by K.
 lbaxi_status make_graph(lbaxi_t* h, int from) {
   hipGraph_t g;
   HIPCHK(hipGraphCreate(&g, 0));
-  hipGraphNode_t prev = nullptr;
-  void* fn = pick_step(h->prec, h->fields);
+  std::vector<hipGraphNode_t> prev;
   lbaxi_status st = LBAXI_OK;
-  for (int k = 0; k < h->K && st == LBAXI_OK; ++k) {
-    StepArgs<double> a = step_args(h, from ^ (k & 1), 0, true, k, 0);
-    void* args[] = {&a};
+  auto add = [&](void* fn, int grid, int block, void** args) {
     hipKernelNodeParams p;
     memset(&p, 0, sizeof p);
     p.func = fn;
-    p.gridDim = dim3(step_grid(h));
-    p.blockDim = dim3(h->tz * h->tr);
-    p.sharedMemBytes = 0;
+    p.gridDim = dim3(grid);
+    p.blockDim = dim3(block);
     p.kernelParams = args;
-    p.extra = nullptr;
     hipGraphNode_t node;
-    hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
-    if (e != hipSuccess) st = fail(LBAXI_EDEVICE, std::string("hipGraphAddKernelNode: ") +
-                                                      hipGetErrorString(e));
-    prev = node;
+    hipError_t e =
+        hipGraphAddKernelNode(&node, g, prev.empty() ? nullptr : prev.data(), prev.size(), &p);
+    if (e != hipSuccess) {
+      st = fail(LBAXI_EDEVICE, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
+      return;
+    }
+    prev.assign(1, node);
+  };
+  for (int k = 0; k < h->K && st == LBAXI_OK; ++k) {
+    const int src = from ^ (k & 1);
+    StepLaunch L = step_launch(h, LIST_RUN, src, 0, true, k, 0);
+    void* args[] = {&L.a};
+    add(L.fn, L.grid, L.block, args);
+    if (st != LBAXI_OK) break;
+    HaloLaunch H = halo_launch(h, src ^ 1);
+    void* hargs[] = {&H.ip, &H.tiles, &H.ntiles, &H.buf};
+    add(H.fn, H.grid, 256, hargs);
   }
   if (st == LBAXI_OK) {
     long long* tp = h->d_t;
@@ -632,7 +737,8 @@ lbaxi_status make_graph(lbaxi_t* h, int from) {
     p.blockDim = dim3(64);
     p.kernelParams = args;
     hipGraphNode_t node;
-    hipError_t e = hipGraphAddKernelNode(&node, g, &prev, 1, &p);
+    hipError_t e = hipGraphAddKernelNode(&node, g, prev.empty() ? nullptr : prev.data(),
+                                         prev.size(), &p);
     if (e != hipSuccess)
       st = fail(LBAXI_EDEVICE, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
   }
@@ -650,32 +756,13 @@ lbaxi_status check_handle(const lbaxi_t* h) {
   return LBAXI_OK;
 }
 
-template <typename R, int F>
-void* seed_fn() { return reinterpret_cast<void*>(&k_seed<R, F>); }
-template <typename R, int F>
-void* macros_fn() { return reinterpret_cast<void*>(&k_macros<R, F>); }
-template <typename R, int F>
-void* resid_fn() { return reinterpret_cast<void*>(&k_residual<R, F>); }
-
-#define PICK(name, prec, fields)                                            \
-  ((prec) == LBAXI_FP64                                                     \
-       ? ((fields & 3) == 0   ? name<double, 0>()                           \
-          : (fields & 3) == 1 ? name<double, 1>()                           \
-          : (fields & 3) == 2 ? name<double, 2>()                           \
-                              : name<double, 3>())                          \
-       : ((fields & 3) == 0   ? name<float, 0>()                            \
-          : (fields & 3) == 1 ? name<float, 1>()                            \
-          : (fields & 3) == 2 ? name<float, 2>()                            \
-                              : name<float, 3>()))
-
 lbaxi_status run_steps(lbaxi_t* h, long long n) {
   if (n <= 0) return LBAXI_OK;
   lbaxi_status st;
-  if (h->ntiles_run == 0) return LBAXI_OK;
-  if ((st = upload_tiles(h, 2)) != LBAXI_OK) return st;
+  if (h->count[LIST_RUN] == 0) return LBAXI_OK;
   long long left = n;
   if (h->pre) {
-    if ((st = launch_step(h, MODE_PRE | (left == 1 ? MODE_SPEED : 0))) != LBAXI_OK) return st;
+    if ((st = launch_step(h, left == 1 ? MODE_SPEED : 0)) != LBAXI_OK) return st;
     --left;
   }
   // the last step of the call records |u| for Eq. (57); graphs cover the rest
@@ -692,15 +779,14 @@ lbaxi_status run_steps(lbaxi_t* h, long long n) {
     if ((st = launch_step(h, left == 1 ? MODE_SPEED : 0)) != LBAXI_OK) return st;
     --left;
   }
-  h->have_spd = true;
   h->dyn_dirty = true;
   return LBAXI_OK;
 }
 
+// Residual words of every lattice (Eq. 57), as doubles on the host.
 lbaxi_status residuals(lbaxi_t* h, std::vector<double>& out) {
   lbaxi_status st;
   if ((st = upload_dyn(h)) != LBAXI_OK) return st;
-  if ((st = upload_tiles(h, 1)) != LBAXI_OK) return st;
   hipLaunchKernelGGL(k_fill_u64, dim3((h->n + 255) / 256), dim3(256), 0, h->stream, h->d_res,
                      h->n, 0ULL);
   HIPCHK(hipGetLastError());
@@ -711,12 +797,12 @@ lbaxi_status residuals(lbaxi_t* h, std::vector<double>& out) {
   unsigned long long* r = h->d_res;
   const InstP* ip = h->d_ip;
   const InstDyn* dy = h->d_dyn;
-  const Tile* tl = h->d_tiles;
-  const int* nt = h->d_ntiles;
+  const Tile* tl = h->d_tiles[LIST_ALL];
+  const int* nt = h->d_counts + LIST_ALL;
   int tzlog = ilog2(h->tz);
   void* args[] = {&ip, &dy, &tl, &nt, &A, &B, &S, &r, &tzlog};
-  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->ntiles_all)), dim3(h->tz * h->tr), args, 0,
-                         h->stream));
+  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])), dim3(h->tz * h->tr), args,
+                         0, h->stream));
   std::vector<unsigned long long> bits(h->n);
   HIPCHK(hipMemcpyAsync(bits.data(), h->d_res, sizeof(unsigned long long) * h->n,
                         hipMemcpyDeviceToHost, h->stream));
@@ -735,7 +821,7 @@ struct SaveHeader {
   int32_t version, n, prec;
   uint32_t fields;
   int64_t t;
-  int32_t cur, pre, have_spd, pad;
+  int32_t cur, pre, pad0, pad1;
   uint64_t desc_hash, buf_bytes;
 };
 
@@ -748,6 +834,14 @@ uint64_t desc_hash(const std::vector<lbaxi_desc>& d) {
     hsh *= 1099511628211ULL;
   }
   return hsh;
+}
+
+void freeze(lbaxi_t* h, int k, int status) {
+  h->status[k] = status;
+  h->dyn[k].cur = h->cur;
+  h->dyn[k].pre = h->pre ? 1 : 0;
+  h->dyn[k].t = h->t;
+  h->dyn_dirty = true;
 }
 
 }  // namespace
@@ -794,7 +888,8 @@ lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace,
   lbaxi_status st = lbaxi_workspace_bytes(n, descs, &need);
   if (st != LBAXI_OK) return st;
   if (!d_workspace) return fail(LBAXI_EINVAL, "NULL workspace");
-  if (reinterpret_cast<uintptr_t>(d_workspace) % 256) return fail(LBAXI_EINVAL, "workspace not 256-byte aligned");
+  if (reinterpret_cast<uintptr_t>(d_workspace) % 256)
+    return fail(LBAXI_EINVAL, "workspace not 256-byte aligned");
   if (bytes < need) return fail(LBAXI_ENOMEM, "workspace smaller than lbaxi_workspace_bytes");
   lbaxi_t* h = new (std::nothrow) lbaxi_s();
   if (!h) return fail(LBAXI_ENOMEM, "host allocation failed");
@@ -807,24 +902,20 @@ lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace,
   h->L = layout(h->desc);
   h->d_ip = reinterpret_cast<InstP*>(h->ws + h->L.ip);
   h->d_dyn = reinterpret_cast<InstDyn*>(h->ws + h->L.dyn);
-  h->d_tiles = reinterpret_cast<Tile*>(h->ws + h->L.tiles);
-  h->d_ntiles = reinterpret_cast<int*>(h->ws + h->L.ntiles);
+  h->d_tiles[LIST_ALL] = reinterpret_cast<Tile*>(h->ws + h->L.tiles_all);
+  h->d_tiles[LIST_RUN] = reinterpret_cast<Tile*>(h->ws + h->L.tiles_run);
+  h->d_tiles[LIST_HALO] = reinterpret_cast<Tile*>(h->ws + h->L.tiles_halo);
+  h->d_counts = reinterpret_cast<int*>(h->ws + h->L.counts);
   h->d_res = reinterpret_cast<unsigned long long*>(h->ws + h->L.res);
   h->d_t = reinterpret_cast<long long*>(h->ws + h->L.tdev);
   h->bufA = h->ws + h->L.bufA;
   h->bufB = h->ws + h->L.bufB;
   h->spd = h->ws + h->L.spd;
-  for (int k = 0; k < n; ++k) h->ip.push_back(make_inst(h->desc[k], h->L.off[k], h->L.off_fld[k]));
+  for (int k = 0; k < n; ++k)
+    h->ip.push_back(make_inst(h->desc[k], h->L.off[k], h->L.off_fld[k]));
   h->status.assign(n, LBAXI_RUNNING);
   h->dyn.assign(n, InstDyn{0, 1, 0});
   h->inst_spd.assign(n, 0);
-  // default launch shape: one wave along z, 4 rows, one workgroup per tile
-  h->tz = 64;
-  h->tr = 4;
-  h->grid = 0;
-  h->xcd = 0;
-  h->nt = 1;
-  build_tiles(h);
   hipError_t e = hipGetDevice(&h->device);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->d_ip, h->ip.data(), sizeof(InstP) * n, hipMemcpyHostToDevice,
@@ -834,9 +925,11 @@ lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace,
     delete h;
     return fail(LBAXI_EDEVICE, std::string("create: ") + hipGetErrorString(e));
   }
-  st = lbaxi_seed(h, nullptr, nullptr, nullptr, nullptr);
+  // default launch shape: one wave along z, 4 rows, one workgroup per tile
+  st = lbaxi_set_launch(h, 64, 4, 0, 0, 1);
+  if (st == LBAXI_OK) st = lbaxi_seed(h, nullptr, nullptr, nullptr, nullptr);
   if (st != LBAXI_OK) {
-    delete h;
+    lbaxi_destroy(h);
     return st;
   }
   *out = h;
@@ -853,22 +946,25 @@ lbaxi_status lbaxi_seed(lbaxi_t* h, const void* d_uz, const void* d_ur, const vo
                         const void* d_T) {
   lbaxi_status st = check_handle(h);
   if (st != LBAXI_OK) return st;
-  for (int k = 0; k < h->n; ++k) h->status[k] = LBAXI_RUNNING;
-  build_tiles(h);
-  if ((st = upload_tiles(h, 1)) != LBAXI_OK) return st;
+  bool changed = false;
+  for (int k = 0; k < h->n; ++k)
+    if (h->status[k] != LBAXI_RUNNING) {
+      h->status[k] = LBAXI_RUNNING;
+      changed = true;
+    }
+  if (changed && (st = build_tiles(h)) != LBAXI_OK) return st;
   void* fn = PICK(seed_fn, h->prec, h->fields);
   const InstP* ip = h->d_ip;
-  const Tile* tl = h->d_tiles;
-  const int* nt = h->d_ntiles;
+  const Tile* tl = h->d_tiles[LIST_ALL];
+  const int* nt = h->d_counts + LIST_ALL;
   void* buf = h->bufA;
   int tzlog = ilog2(h->tz);
   void* args[] = {&ip, &tl, &nt, &buf, &d_uz, &d_ur, &d_uth, &d_T, &tzlog};
-  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->ntiles_all)), dim3(h->tz * h->tr), args, 0,
-                         h->stream));
+  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])), dim3(h->tz * h->tr), args,
+                         0, h->stream));
   h->cur = 0;
   h->pre = true;
   h->t = 0;
-  h->have_spd = false;
   for (int k = 0; k < h->n; ++k) {
     h->dyn[k] = InstDyn{0, 1, 0};
     h->inst_spd[k] = 0;
@@ -893,18 +989,17 @@ lbaxi_status lbaxi_macros(lbaxi_t* h, void* d_rho, void* d_uz, void* d_ur, void*
   lbaxi_status st = check_handle(h);
   if (st != LBAXI_OK) return st;
   if ((st = upload_dyn(h)) != LBAXI_OK) return st;
-  if ((st = upload_tiles(h, 1)) != LBAXI_OK) return st;
   void* fn = PICK(macros_fn, h->prec, h->fields);
   const InstP* ip = h->d_ip;
   const InstDyn* dy = h->d_dyn;
-  const Tile* tl = h->d_tiles;
-  const int* nt = h->d_ntiles;
+  const Tile* tl = h->d_tiles[LIST_ALL];
+  const int* nt = h->d_counts + LIST_ALL;
   const void* A = h->bufA;
   const void* B = h->bufB;
   int tzlog = ilog2(h->tz);
   void* args[] = {&ip, &dy, &tl, &nt, &A, &B, &d_rho, &d_uz, &d_ur, &d_uth, &d_T, &tzlog};
-  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->ntiles_all)), dim3(h->tz * h->tr), args, 0,
-                         h->stream));
+  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])), dim3(h->tz * h->tr), args,
+                         0, h->stream));
   return LBAXI_OK;
 }
 
@@ -939,9 +1034,10 @@ lbaxi_status lbaxi_batch_run(lbaxi_t* h, double tol, int64_t max_steps, int64_t 
   if (check_every < 2 || max_steps < 0 || !(tol >= 0) || !host_status || !host_steps)
     return fail(LBAXI_EINVAL, "bad batch_run arguments");
   std::vector<double> last(h->n, -1.0);
-  const long long t_start = h->t;
+  std::vector<long long> t_start(h->n);
+  for (int k = 0; k < h->n; ++k) t_start[k] = h->status[k] == LBAXI_RUNNING ? h->t : h->dyn[k].t;
   long long done = 0;
-  while (done < max_steps && h->ntiles_run > 0) {
+  while (done < max_steps && h->count[LIST_RUN] > 0) {
     const long long n = std::min<long long>(check_every, max_steps - done);
     if ((st = run_steps(h, n)) != LBAXI_OK) return st;
     for (int k = 0; k < h->n; ++k)
@@ -953,35 +1049,27 @@ lbaxi_status lbaxi_batch_run(lbaxi_t* h, double tol, int64_t max_steps, int64_t 
     for (int k = 0; k < h->n; ++k) {
       if (h->status[k] != LBAXI_RUNNING) continue;
       last[k] = r[k];
-      int ns = LBAXI_RUNNING;
-      if (!std::isfinite(r[k])) ns = LBAXI_DIVERGED;
-      else if (r[k] <= tol) ns = LBAXI_CONVERGED;
-      if (ns != LBAXI_RUNNING) {
-        h->status[k] = ns;
-        h->dyn[k].cur = h->cur;
-        h->dyn[k].pre = 0;
-        h->dyn[k].t = h->t;
+      if (!std::isfinite(r[k])) {
+        freeze(h, k, LBAXI_DIVERGED);
+        changed = true;
+      } else if (r[k] <= tol) {
+        freeze(h, k, LBAXI_CONVERGED);
         changed = true;
       }
     }
-    if (changed) {
-      build_tiles(h);
-      h->dyn_dirty = true;
-    }
+    if (changed && (st = build_tiles(h)) != LBAXI_OK) return st;
   }
+  bool capped = false;
   for (int k = 0; k < h->n; ++k) {
     if (h->status[k] == LBAXI_RUNNING && done >= max_steps) {
-      h->status[k] = LBAXI_CAPPED;
-      h->dyn[k].cur = h->cur;
-      h->dyn[k].pre = h->pre ? 1 : 0;
-      h->dyn[k].t = h->t;
+      freeze(h, k, LBAXI_CAPPED);
+      capped = true;
     }
     host_status[k] = h->status[k];
-    host_steps[k] = (h->status[k] == LBAXI_RUNNING ? h->t : h->dyn[k].t) - t_start;
+    host_steps[k] = (h->status[k] == LBAXI_RUNNING ? h->t : h->dyn[k].t) - t_start[k];
     if (host_res) host_res[k] = last[k];
   }
-  build_tiles(h);
-  h->dyn_dirty = true;
+  if (capped && (st = build_tiles(h)) != LBAXI_OK) return st;
   return LBAXI_OK;
 }
 
@@ -992,15 +1080,12 @@ lbaxi_status lbaxi_set_launch(lbaxi_t* h, int32_t tile_z, int32_t tile_r, int32_
   if (tile_z < 64 || (tile_z & (tile_z - 1)) || tile_r < 1 || tile_z * tile_r > 1024 ||
       grid_blocks < 0)
     return fail(LBAXI_EINVAL, "tile_z must be a power of two >= 64, tile_z*tile_r <= 1024");
-  const bool shape = tile_z != h->tz || tile_r != h->tr;
   h->tz = tile_z;
   h->tr = tile_r;
   h->grid = grid_blocks;
   h->xcd = xcd_aware ? 1 : 0;
   h->nt = nt_store ? 1 : 0;
-  if (shape) build_tiles(h);
-  drop_graphs(h);
-  return LBAXI_OK;
+  return build_tiles(h);
 }
 
 lbaxi_status lbaxi_get_launch(const lbaxi_t* h, int32_t* cfg5) {
@@ -1029,7 +1114,7 @@ lbaxi_status lbaxi_autotune(lbaxi_t* h, int32_t steps_per_trial, int32_t* cfg5_o
   if (st != LBAXI_OK) return st;
   if (steps_per_trial < 2) return fail(LBAXI_EINVAL, "steps_per_trial must be >= 2");
   static const int shapes[][2] = {{64, 1}, {64, 2}, {64, 4}, {64, 8}, {128, 1},
-                                  {128, 2}, {128, 4}, {256, 1}, {256, 2}};
+                                  {128, 2}, {128, 4}, {256, 1}, {256, 2}, {512, 1}};
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -1063,7 +1148,7 @@ lbaxi_status lbaxi_autotune(lbaxi_t* h, int32_t steps_per_trial, int32_t* cfg5_o
     const int wg = b[0] * b[1];
     const int per_cu = std::max(1, 2048 / wg);
     const int grids[] = {dev_cu * per_cu, dev_cu * per_cu * 2, dev_cu * per_cu / 2};
-    const int base[3] = {b[0], b[1], 0};
+    const int base[2] = {b[0], b[1]};
     for (int gi = 0; gi < 3 && st == LBAXI_OK; ++gi)
       for (int xcd = 0; xcd < 2 && st == LBAXI_OK; ++xcd) {
         float ms;
@@ -1094,9 +1179,9 @@ lbaxi_status lbaxi_state_bytes(const lbaxi_t* h, size_t* bytes) {
   lbaxi_status st = check_handle(h);
   if (st != LBAXI_OK) return st;
   if (!bytes) return fail(LBAXI_EINVAL, "NULL bytes");
-  const size_t es = h->prec == LBAXI_FP64 ? 8 : 4;
   *bytes = sizeof(SaveHeader) + sizeof(InstDyn) * h->n + sizeof(int32_t) * h->n +
-           es * (size_t)h->L.buf_elems + es * (size_t)h->L.fld_elems;
+           sizeof(char) * h->n + elem_size(h->prec) * (size_t)h->L.buf_elems +
+           sizeof(double) * (size_t)h->L.fld_elems;
   return LBAXI_OK;
 }
 
@@ -1108,21 +1193,22 @@ lbaxi_status lbaxi_save(lbaxi_t* h, void* host_buf, size_t bytes) {
   if (!host_buf || bytes < need) return fail(LBAXI_EINVAL, "save buffer too small");
   for (int k = 0; k < h->n; ++k)
     if (h->status[k] == LBAXI_RUNNING) {
-      h->dyn[k].cur = h->cur; h->dyn[k].pre = h->pre; h->dyn[k].t = h->t;
+      h->dyn[k].cur = h->cur;
+      h->dyn[k].pre = h->pre;
+      h->dyn[k].t = h->t;
     }
-  const size_t es = h->prec == LBAXI_FP64 ? 8 : 4;
+  const size_t es = elem_size(h->prec);
   char* p = static_cast<char*>(host_buf);
   SaveHeader H;
   memset(&H, 0, sizeof H);
-  memcpy(H.magic, "LBAXISV1", 8);
-  H.version = 1;
+  memcpy(H.magic, "LBAXISV2", 8);
+  H.version = 2;
   H.n = h->n;
   H.prec = h->prec;
   H.fields = h->fields;
   H.t = h->t;
   H.cur = h->cur;
   H.pre = h->pre;
-  H.have_spd = h->have_spd;
   H.desc_hash = desc_hash(h->desc);
   H.buf_bytes = es * (size_t)h->L.buf_elems;
   memcpy(p, &H, sizeof H);
@@ -1131,15 +1217,19 @@ lbaxi_status lbaxi_save(lbaxi_t* h, void* host_buf, size_t bytes) {
   p += sizeof(InstDyn) * h->n;
   memcpy(p, h->status.data(), sizeof(int32_t) * h->n);
   p += sizeof(int32_t) * h->n;
+  memcpy(p, h->inst_spd.data(), h->n);
+  p += h->n;
   // every lattice's own current buffer, instance by instance
   const int np = n_planes(h->fields);
   for (int k = 0; k < h->n; ++k) {
-    const char* src = static_cast<const char*>(h->dyn[k].cur ? h->bufB : h->bufA) + es * h->L.off[k];
-    const size_t nb = es * (size_t)np * h->desc[k].nz * h->desc[k].nr;
+    const char* src =
+        static_cast<const char*>(h->dyn[k].cur ? h->bufB : h->bufA) + es * h->L.off[k];
+    const size_t nb = es * (size_t)np * padded_plane(h->desc[k]);
     HIPCHK(hipMemcpyAsync(p + es * h->L.off[k], src, nb, hipMemcpyDeviceToHost, h->stream));
   }
   p += es * (size_t)h->L.buf_elems;
-  HIPCHK(hipMemcpyAsync(p, h->spd, es * (size_t)h->L.fld_elems, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(p, h->spd, sizeof(double) * (size_t)h->L.fld_elems,
+                        hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return LBAXI_OK;
 }
@@ -1153,7 +1243,7 @@ lbaxi_status lbaxi_load(lbaxi_t* h, const void* host_buf, size_t bytes) {
   const char* p = static_cast<const char*>(host_buf);
   SaveHeader H;
   memcpy(&H, p, sizeof H);
-  if (memcmp(H.magic, "LBAXISV1", 8) || H.n != h->n || H.prec != h->prec ||
+  if (memcmp(H.magic, "LBAXISV2", 8) || H.n != h->n || H.prec != h->prec ||
       H.fields != h->fields || H.desc_hash != desc_hash(h->desc))
     return fail(LBAXI_EINVAL, "checkpoint does not match this handle");
   p += sizeof H;
@@ -1161,25 +1251,24 @@ lbaxi_status lbaxi_load(lbaxi_t* h, const void* host_buf, size_t bytes) {
   p += sizeof(InstDyn) * h->n;
   memcpy(h->status.data(), p, sizeof(int32_t) * h->n);
   p += sizeof(int32_t) * h->n;
-  const size_t es = h->prec == LBAXI_FP64 ? 8 : 4;
+  memcpy(h->inst_spd.data(), p, h->n);
+  p += h->n;
+  const size_t es = elem_size(h->prec);
   const int np = n_planes(h->fields);
   for (int k = 0; k < h->n; ++k) {
     char* dst = static_cast<char*>(h->dyn[k].cur ? h->bufB : h->bufA) + es * h->L.off[k];
-    const size_t nb = es * (size_t)np * h->desc[k].nz * h->desc[k].nr;
+    const size_t nb = es * (size_t)np * padded_plane(h->desc[k]);
     HIPCHK(hipMemcpyAsync(dst, p + es * h->L.off[k], nb, hipMemcpyHostToDevice, h->stream));
   }
   p += es * (size_t)h->L.buf_elems;
-  HIPCHK(hipMemcpyAsync(h->spd, p, es * (size_t)h->L.fld_elems, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(h->spd, p, sizeof(double) * (size_t)h->L.fld_elems,
+                        hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   h->t = H.t;
   h->cur = H.cur;
   h->pre = H.pre != 0;
-  h->have_spd = H.have_spd != 0;
-  for (int k = 0; k < h->n; ++k) h->inst_spd[k] = h->have_spd ? 1 : 0;
-  build_tiles(h);
-  drop_graphs(h);
   h->dyn_dirty = true;
-  return LBAXI_OK;
+  return build_tiles(h);
 }
 
 lbaxi_status lbaxi_node_count(const lbaxi_t* h, int64_t* nodes, int32_t* n) {
@@ -1191,5 +1280,23 @@ lbaxi_status lbaxi_node_count(const lbaxi_t* h, int64_t* nodes, int32_t* n) {
 }
 
 size_t lbaxi_abi_desc_size(void) { return sizeof(lbaxi_desc); }
+
+lbaxi_status lbaxi_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* hip_stream) {
+  if (!d_src || !d_dst || bytes % 16 || (reinterpret_cast<uintptr_t>(d_src) % 16) ||
+      (reinterpret_cast<uintptr_t>(d_dst) % 16))
+    return fail(LBAXI_EINVAL, "copy needs 16-byte aligned pointers and size");
+  const long long n = (long long)(bytes / 16);
+  if (n == 0) return LBAXI_OK;
+  int dev = 0, cu = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    cu = prop.multiProcessorCount;
+  const long long want = (n + 255) / 256;
+  const int grid = (int)std::min<long long>(want, (long long)cu * 16);
+  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream),
+                     static_cast<const u32x4*>(d_src), static_cast<u32x4*>(d_dst), n);
+  HIPCHK(hipGetLastError());
+  return LBAXI_OK;
+}
 
 }  // extern "C"

@@ -25,7 +25,9 @@ struct SideP {
 
 // Everything one lattice instance needs on the device (read once per tile).
 struct InstP {
-  int nz, nr, plane, cart;
+  int nz, nr, cart;
+  int pitch;  // nz + 2: row length of a padded plane
+  int plane;  // (nr + 2) * pitch: elements per padded plane
   double r0;
   double tau, tau_g, tau_h;  // paper convention: nu = tau / 3
   double rho0, mu0, nu_g;
@@ -75,7 +77,7 @@ __host__ __device__ constexpr int mr4(int a) { return a == 1 ? 3 : (a == 3 ? 1 :
 // Parameters of one instance converted to the compute type, per tile.
 template <typename R>
 struct PR {
-  R rho0, mu0, tau, tau_g, tau_h, nu_g, om0, omg0, omh0, gbeta, T_ref, r0;
+  R rho0, inv_rho0, mu0, tau, tau_g, tau_h, nu_g, om0, omg0, omh0, gbeta, T_ref, r0;
   R a_t;  // axial force density at the time level being processed
   int cart;
 };
@@ -84,6 +86,7 @@ template <typename R>
 __device__ inline PR<R> make_pr(const InstP& P, long long t) {
   PR<R> p;
   p.rho0 = (R)P.rho0;
+  p.inv_rho0 = (R)(1.0 / P.rho0);
   p.mu0 = (R)P.mu0;
   p.tau = (R)P.tau;
   p.tau_g = (R)P.tau_g;
@@ -102,16 +105,58 @@ __device__ inline PR<R> make_pr(const InstP& P, long long t) {
   return p;
 }
 
-// 1/r of row j; every 1/r term vanishes on the axis and in planar mode.
+// Reciprocal from the hardware estimate refined by Newton steps (two for
+// double, one for float): within an ulp or two of the IEEE quotient at a
+// fraction of the cost of a full division sequence.
+__device__ inline double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline float rcp(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// Row constants: 1/r (zero on the axis and in planar mode) and the
+// direction-dependent relaxation rates omega = omega0 (1 + tau e_r / r) of
+// f, g and h for e_r = +1 / -1, with the source weights 1 - omega/2 of f.
 template <typename R>
-__device__ inline R inv_radius(const PR<R>& p, int j) {
-  R r = p.r0 + (R)j;
-  return (p.cart || !(r > (R)0)) ? (R)0 : (R)1 / r;
+struct Row {
+  R ir, ir2;
+  R omp, omm, c0, cp, cm;  // f
+  R gp, gm, gsk;           // g: rates and nu_g / r
+  R hp, hm;                // h
+};
+
+template <typename R, int F>
+__device__ inline Row<R> make_row(const PR<R>& p, int j) {
+  Row<R> w;
+  const R r = p.r0 + (R)j;
+  w.ir = (p.cart || !(r > (R)0)) ? (R)0 : rcp(r);
+  w.ir2 = w.ir * w.ir;
+  w.omp = p.om0 * ((R)1 + p.tau * w.ir);
+  w.omm = p.om0 * ((R)1 - p.tau * w.ir);
+  w.c0 = (R)1 - (R)0.5 * p.om0;
+  w.cp = (R)1 - (R)0.5 * w.omp;
+  w.cm = (R)1 - (R)0.5 * w.omm;
+  if (F & F_SWIRL) {
+    w.gp = p.omg0 * ((R)1 + p.tau_g * w.ir);
+    w.gm = p.omg0 * ((R)1 - p.tau_g * w.ir);
+    w.gsk = p.nu_g * w.ir;
+  }
+  if (F & F_THERMAL) {
+    w.hp = p.omh0 * ((R)1 + p.tau_h * w.ir);
+    w.hm = p.omh0 * ((R)1 - p.tau_h * w.ir);
+  }
+  return w;
 }
 
 template <typename R>
 struct Mac {
-  R drho, rho, uz, ur, uth, dT, Fz, Fr, ir;
+  R drho, rho, uz, ur, uth, dT, Fz, Fr;
 };
 
 // Eqs. (14)-(17) solved explicitly with mu -> mu0 (Sec. III A): with the
@@ -119,85 +164,106 @@ struct Mac {
 // rho0 u_th^2 / r), u_r = (sum e_r f + G_r/2) / (sum f + mu0 / r^2),
 // rho = sum f / (1 + u_r / 2r), u_z = (sum e_z f + G_z/2) / sum f.
 template <typename R, int F>
-__device__ inline Mac<R> macros(const PR<R>& p, int j, bool axis_row, const R* f, const R* g,
-                                const R* h) {
+__device__ inline Mac<R> macros(const PR<R>& p, const Row<R>& w, bool axis_row, const R* f,
+                                const R* g, const R* h) {
   Mac<R> m;
-  const R ir = inv_radius(p, j);
+  const R ir = w.ir;
   const R s0d = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const R sz = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const R sr = (f[2] - f[4]) + (f[5] - f[8]) + (f[6] - f[7]);
   const R s0 = p.rho0 + s0d;
   R uth = (R)0;
-  if ((F & F_SWIRL) && !axis_row) uth = ((g[0] + g[1]) + (g[2] + g[3])) / p.rho0;
+  if ((F & F_SWIRL) && !axis_row) uth = ((g[0] + g[1]) + (g[2] + g[3])) * p.inv_rho0;
   R dT = (R)0;
   if (F & F_THERMAL) dT = (h[0] + h[1]) + (h[2] + h[3]);
   R Gz = p.a_t;
   if (F & F_THERMAL) Gz += p.rho0 * p.gbeta * dT;
   R Gr = (R)0;
   if (F & F_SWIRL) Gr = p.rho0 * uth * uth * ir;
-  const R ur = (sr + (R)0.5 * Gr) / (s0 + p.mu0 * ir * ir);
+  const R ur = (sr + (R)0.5 * Gr) * rcp(s0 + p.mu0 * w.ir2);
   const R x = (R)0.5 * ur * ir;
-  m.drho = (s0d - p.rho0 * x) / ((R)1 + x);
+  m.drho = (s0d - p.rho0 * x) * rcp((R)1 + x);
   m.rho = p.rho0 + m.drho;
-  m.uz = (sz + (R)0.5 * Gz) / s0;
+  m.uz = (sz + (R)0.5 * Gz) * rcp(s0);
   m.ur = ur;
   m.uth = uth;
   m.dT = dT;
   m.Fz = Gz;
-  m.Fr = Gr - (R)2 * p.mu0 * ur * ir * ir;
-  m.ir = ir;
+  m.Fr = Gr - (R)2 * p.mu0 * ur * w.ir2;
   return m;
+}
+
+// Collision of the direction pair (a, b) with e_b = -e_a (same weight w):
+// f_eq = w (drho + rho P) with P = 3 e.u + 4.5 (e.u)^2 - 1.5 u^2 (Eq. 6, in
+// deviation form) and S = w (1 + P) [3 (e - u).F - rho u_r / r] (Eq. 12);
+// f* = f - omega (f - f_eq) + (1 - omega/2) S (Eq. 13).
+template <typename R>
+__device__ inline void collide_pair(R& fa, R& fb, R eu, R eF, R w, R oma, R omb, R ca, R cb,
+                                    R drho, R rho, R k15, R C0) {
+  const R base = (R)4.5 * eu * eu - k15;
+  const R mid = w * (drho + rho * base);
+  const R odd = (R)3 * w * rho * eu;
+  const R Sa = w * ((R)1 + base + (R)3 * eu) * (C0 + (R)3 * eF);
+  const R Sb = w * ((R)1 + base - (R)3 * eu) * (C0 - (R)3 * eF);
+  fa = fa - oma * (fa - (mid + odd)) + ca * Sa;
+  fb = fb - omb * (fb - (mid - odd)) + cb * Sb;
 }
 
 // Eq. (13) with the source of Eq. (12) for f; Eq. (53)-(54) for g; the
 // temperature analogue for h.  Updates the populations in place.
 template <typename R, int F>
-__device__ inline void collide(const PR<R>& p, const Mac<R>& m, R* f, R* g, R* h) {
-  const R uz = m.uz, ur = m.ur, ir = m.ir;
-  const R usq = uz * uz + ur * ur;
-  const R omp = p.om0 * ((R)1 + p.tau * ir);
-  const R omm = p.om0 * ((R)1 - p.tau * ir);
-  const R rur = m.rho * ur * ir;
-#pragma unroll
-  for (int a = 0; a < 9; ++a) {
-    const R ez = (R)ez9(a), er = (R)er9(a), w = (R)w9(a);
-    const R eu = ez * uz + er * ur;
-    const R P = (R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * usq;
-    const R feqd = w * (m.drho + m.rho * P);
-    const R S = w * ((R)1 + P) * ((R)3 * ((ez - uz) * m.Fz + (er - ur) * m.Fr) - rur);
-    const R om = er9(a) > 0 ? omp : (er9(a) < 0 ? omm : p.om0);
-    f[a] = f[a] - om * (f[a] - feqd) + ((R)1 - (R)0.5 * om) * S;
+__device__ inline void collide(const PR<R>& p, const Row<R>& w, const Mac<R>& m, R* f, R* g,
+                               R* h) {
+  const R uz = m.uz, ur = m.ur;
+  const R k15 = (R)1.5 * (uz * uz + ur * ur);
+  const R C0 = -(R)3 * (uz * m.Fz + ur * m.Fr) - m.rho * ur * w.ir;
+  const R w1 = (R)(1.0 / 9.0), w5 = (R)(1.0 / 36.0);
+  {
+    const R w0 = (R)(4.0 / 9.0);
+    const R feqd = w0 * (m.drho - m.rho * k15);
+    const R S = w0 * ((R)1 - k15) * C0;
+    f[0] = f[0] - p.om0 * (f[0] - feqd) + w.c0 * S;
   }
+  // e = (1,0) / (-1,0); (0,1) / (0,-1); (1,1) / (-1,-1); (1,-1) / (-1,1)
+  collide_pair(f[1], f[3], uz, m.Fz, w1, p.om0, p.om0, w.c0, w.c0, m.drho, m.rho, k15, C0);
+  collide_pair(f[2], f[4], ur, m.Fr, w1, w.omp, w.omm, w.cp, w.cm, m.drho, m.rho, k15, C0);
+  collide_pair(f[5], f[7], uz + ur, m.Fz + m.Fr, w5, w.omp, w.omm, w.cp, w.cm, m.drho, m.rho,
+               k15, C0);
+  collide_pair(f[8], f[6], uz - ur, m.Fz - m.Fr, w5, w.omm, w.omp, w.cm, w.cp, m.drho, m.rho,
+               k15, C0);
   if (F & F_SWIRL) {
-    const R gp = p.omg0 * ((R)1 + p.tau_g * ir);
-    const R gm = p.omg0 * ((R)1 - p.tau_g * ir);
+    // g_eq = (rho0 u_th / 4)(1 + 2 e.u), S^g = -(1/r)(2 u_r + nu / r) g_eq
     const R q = (R)0.25 * p.rho0 * m.uth;
-    const R sk = -ir * ((R)2 * ur + p.nu_g * ir);
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const R eu = (R)ez4(a) * uz + (R)er4(a) * ur;
-      const R geq = q * ((R)1 + (R)2 * eu);
-      const R om = er4(a) > 0 ? gp : (er4(a) < 0 ? gm : p.omg0);
-      g[a] = g[a] - om * (g[a] - geq) + sk * geq;
-    }
+    const R sk = (R)1 - w.ir * ((R)2 * ur + w.gsk);  // g* = g - om (g - geq) + (sk - 1) geq
+    const R qz = (R)2 * q * uz, qr = (R)2 * q * ur;
+    const R gz0 = q + qz, gz1 = q - qz, gr0 = q + qr, gr1 = q - qr;
+    g[0] = g[0] - p.omg0 * g[0] + (p.omg0 + sk - (R)1) * gz0;
+    g[2] = g[2] - p.omg0 * g[2] + (p.omg0 + sk - (R)1) * gz1;
+    g[1] = g[1] - w.gp * g[1] + (w.gp + sk - (R)1) * gr0;
+    g[3] = g[3] - w.gm * g[3] + (w.gm + sk - (R)1) * gr1;
   }
   if (F & F_THERMAL) {
-    const R hp = p.omh0 * ((R)1 + p.tau_h * ir);
-    const R hm = p.omh0 * ((R)1 - p.tau_h * ir);
+    // h_eq = (T/4)(1 + 2 e.u), S^h = -(u_r / r) h_eq; h stored as h - T_ref/4
     const R T = p.T_ref + m.dT;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const R eu = (R)ez4(a) * uz + (R)er4(a) * ur;
-      const R heq = (R)0.25 * T * ((R)1 + (R)2 * eu);
-      const R heqd = (R)0.25 * (m.dT + T * (R)2 * eu);
-      const R om = er4(a) > 0 ? hp : (er4(a) < 0 ? hm : p.omh0);
-      h[a] = h[a] - om * (h[a] - heqd) - ur * ir * heq;
-    }
+    const R q = (R)0.25 * T, qd = (R)0.25 * m.dT;
+    const R sh = -ur * w.ir;
+    const R tz = (R)2 * q * uz, tr = (R)2 * q * ur;
+    h[0] = h[0] - p.omh0 * (h[0] - (qd + tz)) + sh * (q + tz);
+    h[2] = h[2] - p.omh0 * (h[2] - (qd - tz)) + sh * (q - tz);
+    h[1] = h[1] - w.hp * (h[1] - (qd + tr)) + sh * (q + tr);
+    h[3] = h[3] - w.hm * (h[3] - (qd - tr)) + sh * (q - tr);
   }
 }
 
-// ---- streaming: pull from the post-collision buffer ------------------------
-// s points at the instance's first plane; planes are nr*nz elements, z fastest.
+// ---- streaming ---------------------------------------------------------------
+// Each population plane is padded by one ghost node on every side: node
+// (i, j), i in [-1, nz], j in [-1, nr], lives at (j + 1) * pitch + (i + 1).
+// The step kernel pulls f_a(x) from x - e_a for every node without any test;
+// the ghost slots a real node pulls from are filled after every step by the
+// halo kernel with the boundary rules below, evaluated on the post-collision
+// values of real nodes.
+
+__device__ inline int nidx(const InstP& P, int j, int i) { return (j + 1) * P.pitch + (i + 1); }
 
 // Which segment of a z-end applies at row j (second one beyond r_split).
 __device__ inline void zseg(const InstP& P, const SideP& S, int j, int& kind, double& omega,
@@ -209,144 +275,168 @@ __device__ inline void zseg(const InstP& P, const SideP& S, int j, int& kind, do
   }
 }
 
-template <typename R, int A>
-__device__ inline R pull_f_edge(const InstP& P, const R* s, int i, int j) {
+// Boundary rules: the value node (i, j) receives in direction A when its
+// upstream node (i, j) - e_A lies outside the lattice.  A z-end is resolved
+// before the radial sides.  s points at the instance's first plane.
+//
+// f: moving-wall bounce-back adds 6 w_a rho0 (e_a . u_w); the axis mirrors
+// row 1; a free-slip z-end reflects e_z only.
+template <typename S, int A>
+__device__ inline double rule_f(const InstP& P, const S* s, int i, int j) {
   constexpr int ez = ez9(A), er = er9(A);
   const int nz = P.nz, nr = P.nr, pl = P.plane;
   int iu = i - ez;
   const int ju = j - er;
   if (iu < 0 || iu >= nz) {
-    const SideP& S = P.side[iu < 0 ? WEST : EAST];
-    if (S.kind == SIDE_PERIODIC) {
+    const SideP& W = P.side[iu < 0 ? WEST : EAST];
+    if (W.kind == SIDE_PERIODIC) {
       iu += (iu < 0) ? nz : -nz;
     } else {
       int kind, th; double om, T;
-      zseg(P, S, j, kind, om, th, T);
+      zseg(P, W, j, kind, om, th, T);
       if (kind == SIDE_FREESLIP) {
         constexpr int b = mz9(A);
-        if (ju >= 0 && ju < nr) return s[b * pl + ju * nz + i];
-        if (ju < 0 && P.side[SOUTH].kind == SIDE_AXIS) return s[mr9(b) * pl + nz + i];
-        return s[opp9(A) * pl + j * nz + i];
+        if (ju >= 0 && ju < nr) return (double)s[b * pl + nidx(P, ju, i)];
+        if (ju < 0 && P.side[SOUTH].kind == SIDE_AXIS) return (double)s[mr9(b) * pl + nidx(P, 1, i)];
+        return (double)s[opp9(A) * pl + nidx(P, j, i)];
       }
-      return s[opp9(A) * pl + j * nz + i] +
-             (R)(6.0 * w9(A) * P.rho0 * (ez * S.uz + er * S.ur));
+      return (double)s[opp9(A) * pl + nidx(P, j, i)] +
+             6.0 * w9(A) * P.rho0 * (ez * W.uz + er * W.ur);
     }
   }
   if (ju < 0) {
-    const SideP& S = P.side[SOUTH];
-    if (S.kind == SIDE_AXIS) return s[mr9(A) * pl + nz + iu];  // mirror of row 1
-    return s[opp9(A) * pl + j * nz + i] + (R)(6.0 * w9(A) * P.rho0 * (ez * S.uz + er * S.ur));
+    const SideP& W = P.side[SOUTH];
+    if (W.kind == SIDE_AXIS) return (double)s[mr9(A) * pl + nidx(P, 1, iu)];  // mirror of row 1
+    return (double)s[opp9(A) * pl + nidx(P, j, i)] + 6.0 * w9(A) * P.rho0 * (ez * W.uz + er * W.ur);
   }
   if (ju >= nr) {
-    const SideP& S = P.side[NORTH];
-    return s[opp9(A) * pl + j * nz + i] + (R)(6.0 * w9(A) * P.rho0 * (ez * S.uz + er * S.ur));
+    const SideP& W = P.side[NORTH];
+    return (double)s[opp9(A) * pl + nidx(P, j, i)] + 6.0 * w9(A) * P.rho0 * (ez * W.uz + er * W.ur);
   }
-  return s[A * pl + ju * nz + iu];
+  return (double)s[A * pl + nidx(P, ju, iu)];
 }
 
-template <typename R, int A>
-__device__ inline R pull_g_edge(const InstP& P, const R* s, int i, int j) {
+// g: anti-bounce-back with rho0 u_theta,w / 2 = rho0 omega r / 2 on walls,
+// zero flux on free slip; the axis value is replaced by the extrapolation.
+template <typename S, int A>
+__device__ inline double rule_g(const InstP& P, const S* s, int i, int j) {
   constexpr int ez = ez4(A), er = er4(A);
   const int nz = P.nz, nr = P.nr, pl = P.plane;
   int iu = i - ez;
   const int ju = j - er;
   if (iu < 0 || iu >= nz) {
-    const SideP& S = P.side[iu < 0 ? WEST : EAST];
-    if (S.kind == SIDE_PERIODIC) {
+    const SideP& W = P.side[iu < 0 ? WEST : EAST];
+    if (W.kind == SIDE_PERIODIC) {
       iu += (iu < 0) ? nz : -nz;
     } else {
       int kind, th; double om, T;
-      zseg(P, S, j, kind, om, th, T);
-      if (kind == SIDE_FREESLIP) return s[opp4(A) * pl + j * nz + i];
-      return -s[opp4(A) * pl + j * nz + i] + (R)(0.5 * P.rho0 * om * (P.r0 + (double)j));
+      zseg(P, W, j, kind, om, th, T);
+      if (kind == SIDE_FREESLIP) return (double)s[opp4(A) * pl + nidx(P, j, i)];
+      return -(double)s[opp4(A) * pl + nidx(P, j, i)] + 0.5 * P.rho0 * om * (P.r0 + (double)j);
     }
   }
   if (ju < 0) {
-    const SideP& S = P.side[SOUTH];
-    if (S.kind == SIDE_AXIS) return (R)0;  // replaced by the axis extrapolation
-    return -s[opp4(A) * pl + j * nz + i] + (R)(0.5 * P.rho0 * S.omega * (P.r0 - 0.5));
+    const SideP& W = P.side[SOUTH];
+    if (W.kind == SIDE_AXIS) return 0.0;
+    return -(double)s[opp4(A) * pl + nidx(P, j, i)] + 0.5 * P.rho0 * W.omega * (P.r0 - 0.5);
   }
   if (ju >= nr) {
-    const SideP& S = P.side[NORTH];
-    return -s[opp4(A) * pl + j * nz + i] +
-           (R)(0.5 * P.rho0 * S.omega * (P.r0 + (double)nr - 0.5));
+    const SideP& W = P.side[NORTH];
+    return -(double)s[opp4(A) * pl + nidx(P, j, i)] +
+           0.5 * P.rho0 * W.omega * (P.r0 + (double)nr - 0.5);
   }
-  return s[A * pl + ju * nz + iu];
+  return (double)s[A * pl + nidx(P, ju, iu)];
 }
 
-template <typename R, int A>
-__device__ inline R pull_h_edge(const InstP& P, const R* s, int i, int j) {
+// h (stored as h - T_ref/4): anti-bounce-back (T_w - T_ref)/2 on fixed-
+// temperature walls, bounce-back on adiabatic ones, mirror on the axis.
+template <typename S, int A>
+__device__ inline double rule_h(const InstP& P, const S* s, int i, int j) {
   constexpr int ez = ez4(A), er = er4(A);
   const int nz = P.nz, nr = P.nr, pl = P.plane;
   int iu = i - ez;
   const int ju = j - er;
   if (iu < 0 || iu >= nz) {
-    const SideP& S = P.side[iu < 0 ? WEST : EAST];
-    if (S.kind == SIDE_PERIODIC) {
+    const SideP& W = P.side[iu < 0 ? WEST : EAST];
+    if (W.kind == SIDE_PERIODIC) {
       iu += (iu < 0) ? nz : -nz;
     } else {
       int kind, th; double om, T;
-      zseg(P, S, j, kind, om, th, T);
-      if (kind == SIDE_WALL && th) return -s[opp4(A) * pl + j * nz + i] + (R)(0.5 * (T - P.T_ref));
-      return s[opp4(A) * pl + j * nz + i];
+      zseg(P, W, j, kind, om, th, T);
+      if (kind == SIDE_WALL && th)
+        return -(double)s[opp4(A) * pl + nidx(P, j, i)] + 0.5 * (T - P.T_ref);
+      return (double)s[opp4(A) * pl + nidx(P, j, i)];
     }
   }
   if (ju < 0) {
-    const SideP& S = P.side[SOUTH];
-    if (S.kind == SIDE_AXIS) return s[mr4(A) * pl + nz + iu];
-    if (S.thermal) return -s[opp4(A) * pl + j * nz + i] + (R)(0.5 * (S.T - P.T_ref));
-    return s[opp4(A) * pl + j * nz + i];
+    const SideP& W = P.side[SOUTH];
+    if (W.kind == SIDE_AXIS) return (double)s[mr4(A) * pl + nidx(P, 1, iu)];
+    if (W.thermal) return -(double)s[opp4(A) * pl + nidx(P, j, i)] + 0.5 * (W.T - P.T_ref);
+    return (double)s[opp4(A) * pl + nidx(P, j, i)];
   }
   if (ju >= nr) {
-    const SideP& S = P.side[NORTH];
-    if (S.thermal) return -s[opp4(A) * pl + j * nz + i] + (R)(0.5 * (S.T - P.T_ref));
-    return s[opp4(A) * pl + j * nz + i];
+    const SideP& W = P.side[NORTH];
+    if (W.thermal) return -(double)s[opp4(A) * pl + nidx(P, j, i)] + 0.5 * (W.T - P.T_ref);
+    return (double)s[opp4(A) * pl + nidx(P, j, i)];
   }
-  return s[A * pl + ju * nz + iu];
+  return (double)s[A * pl + nidx(P, ju, iu)];
 }
 
-template <typename R, int F, int A>
-struct EdgeLoader {
-  __device__ static inline void run(const InstP& P, const R* s, int i, int j, R* f, R* g, R* h) {
-    f[A] = pull_f_edge<R, A>(P, s, i, j);
+// Fill, for boundary node (i, j), every ghost slot it pulls from.  Sources
+// are always real nodes, so ghost writes never race with the reads.
+template <typename S, int F, int A>
+struct HaloFill {
+  __device__ static inline void run(const InstP& P, S* s, int i, int j) {
+    const int pl = P.plane;
+    {
+      const int iu = i - ez9(A), ju = j - er9(A);
+      if (iu < 0 || iu >= P.nz || ju < 0 || ju >= P.nr)
+        s[A * pl + nidx(P, ju, iu)] = (S)rule_f<S, A>(P, s, i, j);
+    }
     if constexpr (A < 4) {
-      if (F & F_SWIRL) g[A] = pull_g_edge<R, A>(P, s + 9 * P.plane, i, j);
-      if (F & F_THERMAL)
-        h[A] = pull_h_edge<R, A>(P, s + ((F & F_SWIRL) ? 13 : 9) * P.plane, i, j);
+      const int iu = i - ez4(A), ju = j - er4(A);
+      if (iu < 0 || iu >= P.nz || ju < 0 || ju >= P.nr) {
+        if (F & F_SWIRL) {
+          S* sg = s + 9 * pl;
+          sg[A * pl + nidx(P, ju, iu)] = (S)rule_g<S, A>(P, sg, i, j);
+        }
+        if (F & F_THERMAL) {
+          S* sh = s + ((F & F_SWIRL) ? 13 : 9) * pl;
+          sh[A * pl + nidx(P, ju, iu)] = (S)rule_h<S, A>(P, sh, i, j);
+        }
+      }
     }
-    if constexpr (A + 1 < 9) EdgeLoader<R, F, A + 1>::run(P, s, i, j, f, g, h);
+    if constexpr (A + 1 < 9) HaloFill<S, F, A + 1>::run(P, s, i, j);
   }
 };
 
-// Populations arriving at node (i, j).  pre: the buffer holds f^ itself
-// (right after seeding), so the node reads its own slots.  interior: the
-// whole tile is at least one node away from every side, so no rule applies.
-template <typename R, int F>
-__device__ inline void load_node(const InstP& P, const R* __restrict__ s, int i, int j,
-                                 bool interior, bool pre, R* f, R* g, R* h) {
-  const int nz = P.nz, pl = P.plane;
-  const R* sg = s + 9 * pl;
-  const R* sh = s + ((F & F_SWIRL) ? 13 : 9) * pl;
+// Populations arriving at node (i, j): a plain pull through the padded
+// planes.  pre: the buffer holds f^ itself (right after seeding), so the node
+// reads its own slots.
+template <typename S, typename R, int F>
+__device__ inline void load_node(const InstP& P, const S* __restrict__ s, int i, int j, bool pre,
+                                 R* f, R* g, R* h) {
+  const int pl = P.plane, pt = P.pitch;
+  const int o = nidx(P, j, i);
+  const S* sg = s + 9 * pl;
+  const S* sh = s + ((F & F_SWIRL) ? 13 : 9) * pl;
   if (pre) {
-    const int o = j * nz + i;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) f[a] = s[a * pl + o];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      if (F & F_SWIRL) g[a] = sg[a * pl + o];
-      if (F & F_THERMAL) h[a] = sh[a * pl + o];
-    }
-  } else if (interior) {
-#pragma unroll
-    for (int a = 0; a < 9; ++a) f[a] = s[a * pl + (j - er9(a)) * nz + (i - ez9(a))];
+    for (int a = 0; a < 9; ++a) f[a] = (R)s[a * pl + o];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const int o = (j - er4(a)) * nz + (i - ez4(a));
-      if (F & F_SWIRL) g[a] = sg[a * pl + o];
-      if (F & F_THERMAL) h[a] = sh[a * pl + o];
+      if (F & F_SWIRL) g[a] = (R)sg[a * pl + o];
+      if (F & F_THERMAL) h[a] = (R)sh[a * pl + o];
     }
   } else {
-    EdgeLoader<R, F, 0>::run(P, s, i, j, f, g, h);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) f[a] = (R)s[a * pl + o - er9(a) * pt - ez9(a)];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int q = o - er4(a) * pt - ez4(a);
+      if (F & F_SWIRL) g[a] = (R)sg[a * pl + q];
+      if (F & F_THERMAL) h[a] = (R)sh[a * pl + q];
+    }
   }
 }
 

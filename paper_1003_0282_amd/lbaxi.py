@@ -20,7 +20,7 @@ if not os.path.exists(LIB_PATH):
     raise ImportError("liblbaxi.so is missing: run `python -m paper_1003_0282_amd.build` "
                       "(the HIP library has no CPU fallback)")
 
-FP64, FP32 = 0, 1
+FP64, FP32, FP32_FAST = 0, 1, 2
 SWIRL, THERMAL, CARTESIAN = 1, 2, 4
 SIDE = {"axis": 0, "wall": 1, "periodic": 2, "freeslip": 3}
 RUNNING, CONVERGED, DIVERGED, CAPPED = 0, 1, 2, 3
@@ -69,6 +69,7 @@ _sigs = {
     "lbaxi_load": (_st, [_P, _P, C.c_size_t]),
     "lbaxi_node_count": (_st, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "lbaxi_abi_desc_size": (C.c_size_t, []),
+    "lbaxi_stream_copy": (_st, [_P, _P, C.c_size_t, _P]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(_L, _name)

@@ -44,12 +44,28 @@ def _compare(case, steps, prec, fields=None, label="", **kw):
                          om, prec, label), lat, o
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_hagen_poiseuille_c1(prec):
-    """4 x 32 pipe, a = 1e-6, tau 0.8, 20 000 steps from rest."""
+def test_hagen_poiseuille_c1():
+    """4 x 32 pipe, a = 1e-6, tau 0.8, 20 000 steps from rest (FP64)."""
     case = W.hagen_poiseuille()
-    e, lat, o = _compare(case, 20000, prec, label="HP")
-    print("HP prec", prec, e)
+    e, lat, o = _compare(case, 20000, 0, label="HP")
+    print("HP FP64", e)
+
+
+def test_hagen_poiseuille_fp32_storage_floor():
+    """The same steady pipe with FP32 populations.  Each step rounds every
+    stored population to float (relative 2^-24 of a deviation ~ u/3); at a
+    steady state that rounding is the same every step, so the slowest viscous
+    mode (e-fold R^2 / (nu j01^2) ~ 1700 steps here) accumulates it: the bound
+    2^-24 x 1700 ~ 1e-4 of u_max is the arithmetic's, and the float storage
+    with double arithmetic must stay well inside it."""
+    case = W.hagen_poiseuille()
+    o = oracle_run(case, 20000)
+    lat = gpu_run([case], 20000, 1)
+    gm = {k: v.reshape(case["nr"], case["nz"]) for k, v in to_np(lat.macros()).items()}
+    from _parity import errors
+    e, _ = errors(case, gm, o.macros())
+    print("HP FP32 storage", e)
+    assert e["uz"] < 5e-5 and e["ur"] < 1e-5, e
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -90,6 +106,21 @@ def test_random_state_cases(name, prec):
     fields = _fields(case, 7)
     e, lat, o = _compare(case, 300, prec, fields, label=name)
     print(name, prec, e)
+
+
+@pytest.mark.parametrize("name", ["melt", "annulus_moving"])
+def test_fp32_fast_variant(name):
+    """Float storage and float arithmetic: same scheme, looser agreement
+    (float rounding inside the update), 300 steps."""
+    case = CASES[name]()
+    fields = _fields(case, 8)
+    o = oracle_run(case, 300, fields)
+    lat = gpu_run([case], 300, 2, [fields])
+    gm = {k: v.reshape(case["nr"], case["nz"]) for k, v in to_np(lat.macros()).items()}
+    from _parity import errors
+    e, _ = errors(case, gm, o.macros())
+    print(name, "FP32_FAST", e)
+    assert max(e.values()) < 1e-4, e
 
 
 def test_first_step_from_seed():
