@@ -196,6 +196,14 @@ lbaxi_status lbaxi_state_bytes(const lbaxi_t* h, size_t* bytes);
 lbaxi_status lbaxi_save(lbaxi_t* h, void* host_buf, size_t bytes);
 lbaxi_status lbaxi_load(lbaxi_t* h, const void* host_buf, size_t bytes);
 
+/* Kernel timing for roofline fractions.  With profiling on, steps are
+ * launched one by one (no graph replay) and a pair of HIP events on the
+ * handle's stream brackets every launch of the fused step kernel.
+ * lbaxi_kernel_time synchronises the stream and returns the summed duration
+ * (ms) and the number of step-kernel launches since the previous call. */
+lbaxi_status lbaxi_set_profiling(lbaxi_t* h, int32_t on);
+lbaxi_status lbaxi_kernel_time(lbaxi_t* h, double* ms, int64_t* launches);
+
 /* sizeof(lbaxi_desc) as compiled into the library, for binding checks. */
 size_t lbaxi_abi_desc_size(void);
 

@@ -35,6 +35,20 @@ struct TileRange {
   int start, end, stride;
 };
 
+// Read-only kernel inputs (tile lists, lattice parameters) go through the
+// constant address space so that wave-uniform reads become scalar loads.
+template <typename T>
+__device__ inline T cload(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized structs only");
+  typedef const __attribute__((address_space(4))) int* cptr;
+  const cptr q = (cptr)p;
+  T v;
+  int* w = reinterpret_cast<int*>(&v);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) w[k] = q[k];
+  return v;
+}
+
 // Tiles handled by this workgroup.  With xcd_aware the grid is split into 8
 // interleaved groups (workgroup b runs on XCD b % 8), each walking its own
 // contiguous band of tiles so that neighbouring tiles share one L2.
@@ -93,40 +107,48 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs<S> A) {
   const int li = threadIdx.x & (tz - 1), lj = threadIdx.x >> A.tzlog;
   const bool pre = A.mode & MODE_PRE;
   for (int ti = tr.start; ti < tr.end; ti += tr.stride) {
-    const Tile T = A.tiles[ti];
-    const InstP& P = A.ip[T.inst];
+    const Tile T = cload(A.tiles + ti);
+    const InstP P = cload(A.ip + T.inst);
     const int i = T.z0 + li, j = T.r0 + lj;
     if (i >= P.nz || j >= P.nr) continue;
     const PR<R> p = make_pr<R>(P, t);
     const S* s = A.src + P.off;
-    R f[9], g[4], h[4];
-    load_node<S, R, F>(P, s, i, j, pre, f, g, h);
     const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
+    R gn[4];
     if ((F & F_SWIRL) && axis_row) {
-      // non-equilibrium extrapolation of g from row 1 (Sec. IV B)
+      // non-equilibrium extrapolation of g from row 1 (Sec. IV B), done before
+      // the node's own pull so that the two population sets are never live
+      // together
       R f1[9], g1[4], h1[4];
       load_node<S, R, F>(P, s, i, 1, pre, f1, g1, h1);
       const Mac<R> m1 = macros<R, F>(p, make_row<R, F>(p, 1), false, f1, g1, h1);
       const R q = (R)0.25 * p.rho0 * m1.uth;
 #pragma unroll
       for (int a = 0; a < 4; ++a)
-        g[a] = g1[a] - q * ((R)1 + (R)2 * ((R)ez4(a) * m1.uz + (R)er4(a) * m1.ur));
+        gn[a] = g1[a] - q * ((R)1 + (R)2 * ((R)ez4(a) * m1.uz + (R)er4(a) * m1.ur));
+    }
+    R f[9], g[4], h[4];
+    load_node<S, R, F>(P, s, i, j, pre, f, g, h);
+    if ((F & F_SWIRL) && axis_row) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) g[a] = gn[a];
     }
     const Row<R> rw = make_row<R, F>(p, j);
     const Mac<R> m = macros<R, F>(p, rw, axis_row, f, g, h);
     collide<R, F>(p, rw, m, f, g, h);
     S* d = A.dst + P.off;
-    const int pl = P.plane, o = nidx(P, j, i);
+    const int pl = P.plane;
+    const unsigned ob = (unsigned)nidx(P, j, i) * (unsigned)sizeof(S);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) st(d + a * pl + o, (S)f[a], A.nt_store);
+    for (int a = 0; a < 9; ++a) st(ptrb(d + a * pl, ob), (S)f[a], A.nt_store);
     if (F & F_SWIRL) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a) st(d + (9 + a) * pl + o, (S)g[a], A.nt_store);
+      for (int a = 0; a < 4; ++a) st(ptrb(d + (9 + a) * pl, ob), (S)g[a], A.nt_store);
     }
     if (F & F_THERMAL) {
       const int hb = (F & F_SWIRL) ? 13 : 9;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) st(d + (hb + a) * pl + o, (S)h[a], A.nt_store);
+      for (int a = 0; a < 4; ++a) st(ptrb(d + (hb + a) * pl, ob), (S)h[a], A.nt_store);
     }
     if (A.mode & MODE_SPEED)
       A.spd[P.off_fld + (long long)j * P.nz + i] = (double)sqrt(m.uz * m.uz + m.ur * m.ur);
@@ -153,8 +175,8 @@ __global__ void __launch_bounds__(256) k_halo(const InstP* ip, const Tile* tiles
                                               const int* ntiles, S* buf) {
   const int ti = blockIdx.x;
   if (ti >= *ntiles) return;
-  const Tile T = tiles[ti];
-  const InstP& P = ip[T.inst];
+  const Tile T = cload(tiles + ti);
+  const InstP P = cload(ip + T.inst);
   const int p = T.z0 + threadIdx.x;
   if (p >= 2 * P.nz + 2 * (P.nr - 2)) return;
   int i, j;
@@ -170,8 +192,8 @@ __global__ void __launch_bounds__(1024) k_seed(const InstP* ip, const Tile* tile
                                                int tzlog) {
   const int ti = blockIdx.x;
   if (ti >= *ntiles) return;
-  const Tile T = tiles[ti];
-  const InstP& P = ip[T.inst];
+  const Tile T = cload(tiles + ti);
+  const InstP P = cload(ip + T.inst);
   const int tz = 1 << tzlog;
   const int i = T.z0 + (threadIdx.x & (tz - 1)), j = T.r0 + (threadIdx.x >> tzlog);
   if (i >= P.nz || j >= P.nr) return;
@@ -234,8 +256,8 @@ __global__ void __launch_bounds__(1024) k_macros(const InstP* ip, const InstDyn*
                                                  S* ur, S* uth, S* T, int tzlog) {
   const int ti = blockIdx.x;
   if (ti >= *ntiles) return;
-  const Tile Tl = tiles[ti];
-  const InstP& P = ip[Tl.inst];
+  const Tile Tl = cload(tiles + ti);
+  const InstP P = cload(ip + Tl.inst);
   const int tz = 1 << tzlog;
   const int i = Tl.z0 + (threadIdx.x & (tz - 1)), j = Tl.r0 + (threadIdx.x >> tzlog);
   if (i >= P.nz || j >= P.nr) return;
@@ -264,8 +286,8 @@ __global__ void __launch_bounds__(1024) k_residual(const InstP* ip, const InstDy
   __shared__ unsigned long long red[16];
   const int ti = blockIdx.x;
   if (ti >= *ntiles) return;  // uniform per workgroup
-  const Tile Tl = tiles[ti];
-  const InstP& P = ip[Tl.inst];
+  const Tile Tl = cload(tiles + ti);
+  const InstP P = cload(ip + Tl.inst);
   const int tz = 1 << tzlog;
   const int i = Tl.z0 + (threadIdx.x & (tz - 1)), j = Tl.r0 + (threadIdx.x >> tzlog);
   unsigned long long v = 0;
@@ -355,7 +377,14 @@ long long halo_tiles(const std::vector<lbaxi_desc>& d) {
   for (const auto& x : d) n += (perimeter(x) + 255) / 256;
   return n;
 }
-long long padded_plane(const lbaxi_desc& x) { return (long long)(x.nr + 2) * (x.nz + 2); }
+// Padded rows: a 128-byte lead-in holding the ghost column, nz nodes, the
+// other ghost column, rounded up to 128 bytes.
+int row_lead(const lbaxi_desc& x) { return 128 / (x.prec == LBAXI_FP64 ? 8 : 4); }
+int row_pitch(const lbaxi_desc& x) {
+  const int q = row_lead(x);
+  return (q + x.nz + 1 + q - 1) / q * q;
+}
+long long padded_plane(const lbaxi_desc& x) { return (long long)(x.nr + 2) * row_pitch(x); }
 
 // Device workspace: parameters, three work lists (all tiles / tiles of
 // running lattices / halo chunks of running lattices) with their counts,
@@ -412,7 +441,7 @@ lbaxi_status validate(const lbaxi_desc& d, int k) {
     return fail(s, b);
   };
   if (d.nz < 2 || d.nr < 2) return bad(LBAXI_EINVAL, "nz and nr must be >= 2");
-  if ((long long)n_planes(d.fields) * (d.nz + 2) * (d.nr + 2) >= (1LL << 31))
+  if ((long long)n_planes(d.fields) * padded_plane(d) >= (1LL << 31))
     return bad(LBAXI_EINVAL, "lattice too large for 32-bit in-lattice offsets");
   if (d.prec != LBAXI_FP64 && d.prec != LBAXI_FP32 && d.prec != LBAXI_FP32_FAST)
     return bad(LBAXI_EINVAL, "bad prec");
@@ -463,8 +492,9 @@ InstP make_inst(const lbaxi_desc& d, long long off, long long off_fld) {
   memset(&P, 0, sizeof P);
   P.nz = d.nz;
   P.nr = d.nr;
-  P.pitch = d.nz + 2;
-  P.plane = (d.nr + 2) * (d.nz + 2);
+  P.pitch = row_pitch(d);
+  P.c0 = row_lead(d);
+  P.plane = (int)padded_plane(d);
   P.cart = (d.fields & LBAXI_CARTESIAN) ? 1 : 0;
   P.r0 = d.r0;
   taus(d, P.tau, P.tau_g, P.tau_h);
@@ -542,6 +572,10 @@ struct lbaxi_s {
   std::vector<Tile> lists[3];
   int count[3] = {0, 0, 0};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  // kernel timing: event pairs around step-kernel launches
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
 };
 
 namespace {
@@ -683,7 +717,19 @@ lbaxi_status launch_step(lbaxi_t* h, int mode) {
   StepLaunch L = h->pre ? step_launch(h, LIST_ALL, h->cur, h->t, false, 0, mode | MODE_PRE)
                         : step_launch(h, LIST_RUN, h->cur, h->t, false, 0, mode);
   void* args[] = {&L.a};
+  if (h->prof) {
+    while (h->ev.size() < h->ev_used + 2) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      h->ev.push_back(e);
+    }
+    HIPCHK(hipEventRecord(h->ev[h->ev_used], h->stream));
+  }
   HIPCHK(hipLaunchKernel(L.fn, dim3(L.grid), dim3(L.block), args, 0, h->stream));
+  if (h->prof) {
+    HIPCHK(hipEventRecord(h->ev[h->ev_used + 1], h->stream));
+    h->ev_used += 2;
+  }
   HaloLaunch H = halo_launch(h, h->cur ^ 1);
   void* hargs[] = {&H.ip, &H.tiles, &H.ntiles, &H.buf};
   HIPCHK(hipLaunchKernel(H.fn, dim3(H.grid), dim3(256), hargs, 0, h->stream));
@@ -766,7 +812,7 @@ lbaxi_status run_steps(lbaxi_t* h, long long n) {
     --left;
   }
   // the last step of the call records |u| for Eq. (57); graphs cover the rest
-  if (h->K > 0 && left - 1 >= h->K) {
+  if (h->K > 0 && !h->prof && left - 1 >= h->K) {
     const long long reps = (left - 1) / h->K;
     if (!h->gexec[h->cur] && (st = make_graph(h, h->cur)) != LBAXI_OK) return st;
     hipLaunchKernelGGL(k_set_time, dim3(1), dim3(64), 0, h->stream, h->d_t, h->t);
@@ -939,6 +985,7 @@ lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace,
 void lbaxi_destroy(lbaxi_t* h) {
   if (!h) return;
   drop_graphs(h);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -1280,6 +1327,30 @@ lbaxi_status lbaxi_node_count(const lbaxi_t* h, int64_t* nodes, int32_t* n) {
 }
 
 size_t lbaxi_abi_desc_size(void) { return sizeof(lbaxi_desc); }
+
+lbaxi_status lbaxi_set_profiling(lbaxi_t* h, int32_t on) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  h->prof = on != 0;
+  return LBAXI_OK;
+}
+
+lbaxi_status lbaxi_kernel_time(lbaxi_t* h, double* ms, int64_t* launches) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  if (!ms || !launches) return fail(LBAXI_EINVAL, "NULL output");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  double total = 0;
+  for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
+    float e = 0;
+    HIPCHK(hipEventElapsedTime(&e, h->ev[k], h->ev[k + 1]));
+    total += e;
+  }
+  *ms = total;
+  *launches = (int64_t)(h->ev_used / 2);
+  h->ev_used = 0;
+  return LBAXI_OK;
+}
 
 lbaxi_status lbaxi_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* hip_stream) {
   if (!d_src || !d_dst || bytes % 16 || (reinterpret_cast<uintptr_t>(d_src) % 16) ||

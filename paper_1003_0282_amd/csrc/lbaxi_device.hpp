@@ -26,7 +26,8 @@ struct SideP {
 // Everything one lattice instance needs on the device (read once per tile).
 struct InstP {
   int nz, nr, cart;
-  int pitch;  // nz + 2: row length of a padded plane
+  int pitch;  // row length of a padded plane (a multiple of 128 bytes)
+  int c0;     // column of node i = 0 (128 bytes in; the ghost column is c0 - 1)
   int plane;  // (nr + 2) * pitch: elements per padded plane
   double r0;
   double tau, tau_g, tau_h;  // paper convention: nu = tau / 3
@@ -257,13 +258,25 @@ __device__ inline void collide(const PR<R>& p, const Row<R>& w, const Mac<R>& m,
 
 // ---- streaming ---------------------------------------------------------------
 // Each population plane is padded by one ghost node on every side: node
-// (i, j), i in [-1, nz], j in [-1, nr], lives at (j + 1) * pitch + (i + 1).
+// (i, j), i in [-1, nz], j in [-1, nr], lives at (j + 1) * pitch + c0 + i,
+// with rows starting on 128-byte boundaries so that a wave's stores are
+// aligned.
 // The step kernel pulls f_a(x) from x - e_a for every node without any test;
 // the ghost slots a real node pulls from are filled after every step by the
 // halo kernel with the boundary rules below, evaluated on the post-collision
 // values of real nodes.
 
-__device__ inline int nidx(const InstP& P, int j, int i) { return (j + 1) * P.pitch + (i + 1); }
+__device__ inline int nidx(const InstP& P, int j, int i) { return (j + 1) * P.pitch + P.c0 + i; }
+
+// Element at byte offset boff from a plane base (boff < 4 GiB: a plane).
+template <typename S>
+__device__ inline S ldb(const S* base, unsigned boff) {
+  return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + boff);
+}
+template <typename S>
+__device__ inline S* ptrb(S* base, unsigned boff) {
+  return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + boff);
+}
 
 // Which segment of a z-end applies at row j (second one beyond r_split).
 __device__ inline void zseg(const InstP& P, const SideP& S, int j, int& kind, double& omega,
@@ -416,26 +429,29 @@ struct HaloFill {
 template <typename S, typename R, int F>
 __device__ inline void load_node(const InstP& P, const S* __restrict__ s, int i, int j, bool pre,
                                  R* f, R* g, R* h) {
+  // Loads are written as a wave-uniform plane base plus a 32-bit byte offset
+  // so that they use scalar-base addressing (one offset register per row).
   const int pl = P.plane, pt = P.pitch;
-  const int o = nidx(P, j, i);
+  const unsigned o = (unsigned)nidx(P, j, i);
   const S* sg = s + 9 * pl;
   const S* sh = s + ((F & F_SWIRL) ? 13 : 9) * pl;
+  constexpr unsigned es = sizeof(S);
   if (pre) {
 #pragma unroll
-    for (int a = 0; a < 9; ++a) f[a] = (R)s[a * pl + o];
+    for (int a = 0; a < 9; ++a) f[a] = (R)ldb(s + a * pl, o * es);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      if (F & F_SWIRL) g[a] = (R)sg[a * pl + o];
-      if (F & F_THERMAL) h[a] = (R)sh[a * pl + o];
+      if (F & F_SWIRL) g[a] = (R)ldb(sg + a * pl, o * es);
+      if (F & F_THERMAL) h[a] = (R)ldb(sh + a * pl, o * es);
     }
   } else {
 #pragma unroll
-    for (int a = 0; a < 9; ++a) f[a] = (R)s[a * pl + o - er9(a) * pt - ez9(a)];
+    for (int a = 0; a < 9; ++a) f[a] = (R)ldb(s + a * pl, (o - er9(a) * pt - ez9(a)) * es);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const int q = o - er4(a) * pt - ez4(a);
-      if (F & F_SWIRL) g[a] = (R)sg[a * pl + q];
-      if (F & F_THERMAL) h[a] = (R)sh[a * pl + q];
+      const unsigned q = (o - er4(a) * pt - ez4(a)) * es;
+      if (F & F_SWIRL) g[a] = (R)ldb(sg + a * pl, q);
+      if (F & F_THERMAL) h[a] = (R)ldb(sh + a * pl, q);
     }
   }
 }

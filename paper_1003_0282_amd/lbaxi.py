@@ -70,6 +70,8 @@ _sigs = {
     "lbaxi_node_count": (_st, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "lbaxi_abi_desc_size": (C.c_size_t, []),
     "lbaxi_stream_copy": (_st, [_P, _P, C.c_size_t, _P]),
+    "lbaxi_set_profiling": (_st, [_P, C.c_int32]),
+    "lbaxi_kernel_time": (_st, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(_L, _name)
@@ -267,6 +269,16 @@ class Lattices:
         c = (C.c_int32 * 5)()
         _check(_L.lbaxi_autotune(self.h, int(steps_per_trial), c), "lbaxi_autotune")
         return tuple(c[:])
+
+    def set_profiling(self, on: bool):
+        _check(_L.lbaxi_set_profiling(self.h, int(bool(on))), "lbaxi_set_profiling")
+
+    def kernel_time(self):
+        """(summed step-kernel milliseconds, launches) since the last call."""
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(_L.lbaxi_kernel_time(self.h, C.byref(ms), C.byref(n)), "lbaxi_kernel_time")
+        return float(ms.value), int(n.value)
 
     def save(self) -> bytes:
         n = C.c_size_t()
