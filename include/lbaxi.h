@@ -170,6 +170,12 @@ lbaxi_status lbaxi_time(const lbaxi_t* h, int32_t k, int64_t* t);
 lbaxi_status lbaxi_batch_run(lbaxi_t* h, double tol, int64_t max_steps, int64_t check_every,
                              int32_t* host_status, int64_t* host_steps, double* host_res);
 
+/* Let CAPPED lattices that stopped together with the last running ones
+ * (same time level) run again in the next lbaxi_step / lbaxi_batch_run, so
+ * that a long run can be split into calls; *host_resumed (may be NULL)
+ * receives their number. */
+lbaxi_status lbaxi_resume(lbaxi_t* h, int32_t* host_resumed);
+
 /* Launch shape of the fused step kernel: tile_z x tile_r nodes per
  * workgroup (tile_z a multiple of 64, tile_z * tile_r <= 1024), grid_blocks
  * persistent workgroups (0 = one workgroup per tile), xcd_aware = 1 gives

@@ -16,6 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbaxi.so")
+NNLIB = os.path.join(PKG, "liblbnn.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LBAXI_ARCH", "gfx950")
@@ -37,7 +38,8 @@ def _compile(out: str, sources: list[str], extra: list[str] | None = None) -> st
 
 
 def build() -> list[str]:
-    libs = [_compile(LIB, [os.path.join(SRC, "lbaxi.hip")])]
+    libs = [_compile(LIB, [os.path.join(SRC, "lbaxi.hip")]),
+            _compile(NNLIB, [os.path.join(SRC, "lbnn.hip")])]
     return libs
 
 

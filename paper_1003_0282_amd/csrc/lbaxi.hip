@@ -1120,6 +1120,24 @@ lbaxi_status lbaxi_batch_run(lbaxi_t* h, double tol, int64_t max_steps, int64_t 
   return LBAXI_OK;
 }
 
+lbaxi_status lbaxi_resume(lbaxi_t* h, int32_t* host_resumed) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  int n = 0;
+  for (int k = 0; k < h->n; ++k)
+    if (h->status[k] == LBAXI_CAPPED && h->dyn[k].t == h->t && h->dyn[k].cur == h->cur &&
+        (h->dyn[k].pre != 0) == h->pre) {
+      h->status[k] = LBAXI_RUNNING;
+      ++n;
+    }
+  if (host_resumed) *host_resumed = n;
+  if (n) {
+    h->dyn_dirty = true;
+    return build_tiles(h);
+  }
+  return LBAXI_OK;
+}
+
 lbaxi_status lbaxi_set_launch(lbaxi_t* h, int32_t tile_z, int32_t tile_r, int32_t grid_blocks,
                               int32_t xcd_aware, int32_t nt_store) {
   lbaxi_status st = check_handle(h);

@@ -1,0 +1,860 @@
+// lbnn.hip -- warm-start U-Net for the axisymmetric LB solver: BF16 MFMA
+// convolution kernels (forward, backward-data, backward-weight), the glue
+// kernels of the U-Net, MSE loss, Adam, and the C ABI of include/lbnn.h.
+//
+// Every 3x3 convolution is an implicit GEMM on v_mfma_f32_32x32x16_bf16:
+// one wave owns a 32 (pixels) x 32 (output channels) block of the output and
+// walks K = 9 taps x input channels in steps of 16, reading its A fragment
+// (8 consecutive channels of one neighbour pixel, 16 bytes) and B fragment
+// (8 consecutive K of one output channel, 16 bytes) straight from memory.
+// Any K order shared by A and B gives the same sum, so the only layout the
+// code relies on is the accumulator's (checked by lbnn_mfma_selftest):
+// register r of lane l holds row (r/4)*8 + (l/32)*4 + r%4, column l%32.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbnn.h"
+
+typedef unsigned short bf16s;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ inline float bf2f(bf16s h) { return __uint_as_float((unsigned)h << 16); }
+
+// FP32 -> BF16, round to nearest even (NaN stays NaN).
+__device__ inline bf16s f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (bf16s)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16s)(u >> 16);
+}
+
+__device__ inline f32x16 mfma(u16x8 a, u16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// Row of the 32x32 output block held by accumulator r of a lane in half g.
+__device__ inline int acc_row(int r, int g) { return (r >> 2) * 8 + g * 4 + (r & 3); }
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution as implicit GEMM.  in [B][H][W][Ck], wt [9][Cn][Ck]
+// (K contiguous), out [B][H][W][Cn].  sign = +1: out[p] = sum in[p + off]
+// (forward); sign = -1: out[p] = sum in[p - off] (adjoint, gradient of the
+// input with wt = the original [9][Ci][Co] weights).
+struct ConvArgs {
+  const bf16s* in;
+  const bf16s* wt;
+  const float* bias;  // [Cn] or NULL
+  const bf16s* mask;  // [B][H][W][Cn] or NULL: output zeroed where mask <= 0
+  bf16s* out;
+  int B, H, W, Ck, Cn, sign, relu;
+};
+
+__global__ void __launch_bounds__(256) k_conv(ConvArgs A) {
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int m = l & 31, g = l >> 5;
+  const long long npix = (long long)A.B * A.H * A.W;
+  const long long pix0 = ((long long)blockIdx.x * 4 + wave) * 32;
+  if (pix0 >= npix) return;
+  const int n0 = blockIdx.y * 32;
+  const long long p = pix0 + m;
+  const bool pin = p < npix;
+  int n = 0, y = 0, x = 0;
+  if (pin) {
+    const long long hw = (long long)A.H * A.W;
+    n = (int)(p / hw);
+    const int rem = (int)(p - (long long)n * hw);
+    y = rem / A.W;
+    x = rem - y * A.W;
+  }
+  f32x16 acc = {};
+  const u16x8 zero = {};
+  for (int t = 0; t < 9; ++t) {
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    const int yy = y + A.sign * dy, xx = x + A.sign * dx;
+    const bool ok = pin && yy >= 0 && yy < A.H && xx >= 0 && xx < A.W;
+    const bf16s* ap = A.in + (((long long)n * A.H + (ok ? yy : 0)) * A.W + (ok ? xx : 0)) * A.Ck + 8 * g;
+    const bf16s* bp = A.wt + ((long long)t * A.Cn + n0 + m) * A.Ck + 8 * g;
+    for (int c = 0; c < A.Ck; c += 16) {
+      const u16x8 a = ok ? *reinterpret_cast<const u16x8*>(ap + c) : zero;
+      const u16x8 b = *reinterpret_cast<const u16x8*>(bp + c);
+      acc = mfma(a, b, acc);
+    }
+  }
+  const int col = n0 + m;
+  const float bias = A.bias ? A.bias[col] : 0.0f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const long long q = pix0 + acc_row(r, g);
+    if (q >= npix) continue;
+    float v = acc[r] + bias;
+    if (A.relu && v < 0.0f) v = 0.0f;
+    const long long o = q * A.Cn + col;
+    if (A.mask && !(bf2f(A.mask[o]) > 0.0f)) v = 0.0f;
+    A.out[o] = f2bf(v);
+  }
+}
+
+// Weight gradient dW[t][ci][co] += sum_p x[p + off_t][ci] gz[p][co]: GEMM
+// with M = ci, N = co, K = pixels.  One wave per (tap, 32 ci, 32 co, chunk
+// of pixels), FP32 atomic accumulation into dW.  x has Cx channels (the
+// padded input of the first layer); only ci < Ci are real.
+struct WgradArgs {
+  const bf16s* x;   // [B][H][W][Cx]
+  const bf16s* gz;  // [B][H][W][Co]
+  float* dW;        // [9][Ci][Co]
+  int B, H, W, Cx, Ci, Co, chunk;
+};
+
+__global__ void __launch_bounds__(64) k_wgrad(WgradArgs A) {
+  const int l = threadIdx.x, m = l & 31, g = l >> 5;
+  const int cib = (A.Ci + 31) / 32;
+  const int blk = blockIdx.y;
+  const int t = blk % 9;
+  const int ci0 = ((blk / 9) % cib) * 32;
+  const int co0 = (blk / 9 / cib) * 32;
+  const bool row_ok = ci0 + m < A.Ci;
+  const int dy = t / 3 - 1, dx = t % 3 - 1;
+  const long long npix = (long long)A.B * A.H * A.W, hw = (long long)A.H * A.W;
+  const long long p_beg = (long long)blockIdx.x * A.chunk;
+  const long long p_end = std::min<long long>(p_beg + A.chunk, npix);
+  f32x16 acc = {};
+  for (long long p0 = p_beg; p0 < p_end; p0 += 16) {
+    u16x8 a, b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const long long p = p0 + 8 * g + e;
+      bf16s av = 0, bv = 0;
+      if (p < p_end) {
+        const int n = (int)(p / hw);
+        const int rem = (int)(p - (long long)n * hw);
+        const int y = rem / A.W, x = rem - (rem / A.W) * A.W;
+        const int yy = y + dy, xx = x + dx;
+        if (row_ok && yy >= 0 && yy < A.H && xx >= 0 && xx < A.W)
+          av = A.x[(((long long)n * A.H + yy) * A.W + xx) * A.Cx + ci0 + m];
+        bv = A.gz[p * A.Co + co0 + m];
+      }
+      a[e] = av;
+      b[e] = bv;
+    }
+    acc = mfma(a, b, acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int ci = ci0 + acc_row(r, g);
+    if (ci < A.Ci) atomicAdd(A.dW + ((long long)t * A.Ci + ci) * A.Co + co0 + m, acc[r]);
+  }
+}
+
+// Bias gradient db[c] += sum over a chunk of 256 pixels of gz[p][c].
+__global__ void __launch_bounds__(256) k_bgrad(const bf16s* gz, float* db, long long npix, int C) {
+  const long long p0 = (long long)blockIdx.x * 256;
+  const long long p1 = std::min<long long>(p0 + 256, npix);
+  for (int c = threadIdx.x; c < C; c += 256) {
+    float s = 0.0f;
+    for (long long p = p0; p < p1; ++p) s += bf2f(gz[p * C + c]);
+    atomicAdd(db + c, s);
+  }
+}
+
+// ---- U-Net glue --------------------------------------------------------------
+
+// FP32 [B][H][W][c_in] -> BF16 [B][H][W][16], zero channels beyond c_in.
+__global__ void k_input(const float* x, bf16s* out, long long npix, int c_in) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npix * 16) return;
+  const long long p = k >> 4;
+  const int c = (int)(k & 15);
+  out[k] = c < c_in ? f2bf(x[p * c_in + c]) : (bf16s)0;
+}
+
+// 2x2 average pooling: out [B][H/2][W/2][C].
+__global__ void k_pool(const bf16s* in, bf16s* out, int B, int H, int W, int C) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int h = H / 2, w = W / 2;
+  const long long total = (long long)B * h * w * C;
+  if (k >= total) return;
+  const int c = (int)(k % C);
+  long long q = k / C;
+  const int x = (int)(q % w);
+  q /= w;
+  const int y = (int)(q % h);
+  const int n = (int)(q / h);
+  const long long b = (((long long)n * H + 2 * y) * W + 2 * x) * C + c;
+  const float s = bf2f(in[b]) + bf2f(in[b + C]) + bf2f(in[b + (long long)W * C]) +
+                  bf2f(in[b + (long long)W * C + C]);
+  out[k] = f2bf(0.25f * s);
+}
+
+// Gradient into an encoder output e [B][H][W][C]: a quarter of the pooled
+// gradient of its 2x2 parent plus the skip gradient, zeroed where e <= 0.
+__global__ void k_pool_back(const bf16s* gp, const bf16s* gskip, const bf16s* e, bf16s* ge,
+                            int B, int H, int W, int C) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = (long long)B * H * W * C;
+  if (k >= total) return;
+  const int c = (int)(k % C);
+  long long q = k / C;
+  const int x = (int)(q % W);
+  q /= W;
+  const int y = (int)(q % H);
+  const int n = (int)(q / H);
+  const float v = 0.25f * bf2f(gp[(((long long)n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c]) +
+                  bf2f(gskip[k]);
+  ge[k] = bf2f(e[k]) > 0.0f ? f2bf(v) : (bf16s)0;
+}
+
+// cat [B][H][W][Cu + Cs] = (nearest 2x upsample of u [B][H/2][W/2][Cu], s).
+__global__ void k_upcat(const bf16s* u, const bf16s* s, bf16s* cat, int B, int H, int W, int Cu,
+                        int Cs) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = Cu + Cs;
+  const long long total = (long long)B * H * W * C;
+  if (k >= total) return;
+  const int c = (int)(k % C);
+  const long long p = k / C;
+  if (c < Cs + Cu && c >= Cu) {
+    cat[k] = s[p * Cs + (c - Cu)];
+    return;
+  }
+  const int x = (int)(p % W);
+  const long long q = p / W;
+  const int y = (int)(q % H);
+  const int n = (int)(q / H);
+  cat[k] = u[(((long long)n * (H / 2) + y / 2) * (W / 2) + x / 2) * Cu + c];
+}
+
+// Backward of k_upcat: gu [B][H/2][W/2][Cu] = sum of the 2x2 children,
+// zeroed where the upsampled tensor u <= 0 (it is a ReLU output); the skip
+// part is copied to gskip [B][H][W][Cs].
+__global__ void k_upcat_back(const bf16s* gcat, const bf16s* u, bf16s* gu, bf16s* gskip, int B,
+                             int H, int W, int Cu, int Cs) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = Cu + Cs;
+  const int h = H / 2, w = W / 2;
+  const long long nu = (long long)B * h * w * Cu;
+  const long long ns = (long long)B * H * W * Cs;
+  if (k < nu) {
+    const int c = (int)(k % Cu);
+    long long q = k / Cu;
+    const int x = (int)(q % w);
+    q /= w;
+    const int y = (int)(q % h);
+    const int n = (int)(q / h);
+    const long long b = (((long long)n * H + 2 * y) * W + 2 * x) * C + c;
+    const float v = bf2f(gcat[b]) + bf2f(gcat[b + C]) + bf2f(gcat[b + (long long)W * C]) +
+                    bf2f(gcat[b + (long long)W * C + C]);
+    gu[k] = bf2f(u[k]) > 0.0f ? f2bf(v) : (bf16s)0;
+  } else if (k < nu + ns) {
+    const long long j = k - nu;
+    const int c = (int)(j % Cs);
+    const long long p = j / Cs;
+    gskip[j] = gcat[p * C + Cu + c];
+  }
+}
+
+// Head: y[p][k] = sum_c d0[p][c] Wh[c][k] + bh[k] (FP32 parameters).  With a
+// target: gy = 2 (y - t) / N into gy and the squared error summed into loss.
+__global__ void __launch_bounds__(256) k_head(const bf16s* d0, const float* Wh, const float* bh,
+                                              float* y, const float* tgt, float* gy, double* loss,
+                                              long long npix, int C, int K, double inv_n) {
+  __shared__ float red[256];
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  float se = 0.0f;
+  if (p < npix) {
+    for (int k = 0; k < K; ++k) {
+      float s = bh[k];
+      for (int c = 0; c < C; ++c) s += bf2f(d0[p * C + c]) * Wh[c * K + k];
+      y[p * K + k] = s;
+      if (tgt) {
+        const float dlt = s - tgt[p * K + k];
+        se += dlt * dlt;
+        gy[p * K + k] = (float)(2.0 * inv_n) * dlt;
+      }
+    }
+  }
+  if (!tgt) return;
+  red[threadIdx.x] = se;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(loss, (double)red[0]);
+}
+
+// Head backward, input side: gd0[p][c] = (sum_k gy[p][k] Wh[c][k]) where
+// d0 > 0 (d0 is a ReLU output).
+__global__ void __launch_bounds__(256) k_head_back(const bf16s* d0, const float* gy,
+                                                   const float* Wh, bf16s* gd0, long long npix,
+                                                   int C, int K) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  for (int c = 0; c < C; ++c) {
+    float s = 0.0f;
+    for (int k = 0; k < K; ++k) s += gy[p * K + k] * Wh[c * K + k];
+    gd0[p * C + c] = bf2f(d0[p * C + c]) > 0.0f ? f2bf(s) : (bf16s)0;
+  }
+}
+
+// Head backward, parameter side: block c < C sums dWh[c][k] = sum_p d0[p][c]
+// gy[p][k], block C sums dbh[k] = sum_p gy[p][k] (K <= 8).
+__global__ void __launch_bounds__(256) k_head_wgrad(const bf16s* d0, const float* gy, float* dWh,
+                                                    float* dbh, long long npix, int C, int K) {
+  __shared__ float red[8][256];
+  const int c = blockIdx.x;
+  float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long p = threadIdx.x; p < npix; p += blockDim.x) {
+    const float d = c < C ? bf2f(d0[p * C + c]) : 1.0f;
+    for (int k = 0; k < K; ++k) acc[k] += d * gy[p * K + k];
+  }
+  for (int k = 0; k < K; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int sz = 128; sz > 0; sz >>= 1) {
+    if (threadIdx.x < sz)
+      for (int k = 0; k < K; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + sz];
+    __syncthreads();
+  }
+  if (threadIdx.x < K) {
+    if (c < C) dWh[c * K + threadIdx.x] = red[threadIdx.x][0];
+    else dbh[threadIdx.x] = red[threadIdx.x][0];
+  }
+}
+
+// FP32 master W [9][ci][co] -> BF16 copies wf [9][co][Ck] (forward) and
+// wb [9][Ck][co] (adjoint), input channels zero-padded to Ck.
+__global__ void k_cast_w(const float* W, bf16s* wf, bf16s* wb, int ci, int Ck, int co) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = 9LL * Ck * co;
+  if (k >= total) return;
+  const int o = (int)(k % co);
+  const int c = (int)((k / co) % Ck);
+  const int t = (int)(k / ((long long)co * Ck));
+  const bf16s v = c < ci ? f2bf(W[((long long)t * ci + c) * co + o]) : (bf16s)0;
+  wb[k] = v;
+  wf[((long long)t * co + o) * Ck + c] = v;
+}
+
+__global__ void k_adam(float* p, const float* g, float* m, float* v, long long n, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float gk = g[k];
+  const float mk = b1 * m[k] + (1.0f - b1) * gk;
+  const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+  m[k] = mk;
+  v[k] = vk;
+  p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+__global__ void k_zero(float* p, long long n) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0.0f;
+}
+
+__global__ void k_set_i32(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+__global__ void k_zero_d(double* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0.0;
+}
+
+__global__ void k_to_fields(const float* y, long long npix, int K, float4 sc, float4 of, float* f0,
+                            float* f1, float* f2, float* f3) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  if (f0 && K > 0) f0[p] = y[p * K + 0] * sc.x + of.x;
+  if (f1 && K > 1) f1[p] = y[p * K + 1] * sc.y + of.y;
+  if (f2 && K > 2) f2[p] = y[p * K + 2] * sc.z + of.z;
+  if (f3 && K > 3) f3[p] = y[p * K + 3] * sc.w + of.w;
+}
+
+// Layout self-test: A[i][k] = (i + 2k) mod 7 - 3, B[k][j] = (3k + j) mod 5 - 2
+// (exact in BF16, exact FP32 sums); each lane checks its 16 accumulators.
+__global__ void k_mfma_selftest(int* bad) {
+  const int l = threadIdx.x, m = l & 31, g = l >> 5;
+  u16x8 a, b;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int k = 8 * g + e;
+    a[e] = f2bf((float)((m + 2 * k) % 7 - 3));
+    b[e] = f2bf((float)((3 * k + m) % 5 - 2));
+  }
+  f32x16 acc = {};
+  acc = mfma(a, b, acc);
+  int nb = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = acc_row(r, g), j = m;
+    float s = 0.0f;
+    for (int k = 0; k < 16; ++k) s += (float)((i + 2 * k) % 7 - 3) * (float)((3 * k + j) % 5 - 2);
+    if (acc[r] != s) ++nb;
+  }
+  if (nb) atomicAdd(bad, nb);
+}
+
+// ============================================================================
+// host side
+// ============================================================================
+
+namespace {
+
+thread_local std::string g_nerr = "no error";
+lbaxi_status nfail(lbaxi_status s, const std::string& m) {
+  g_nerr = m;
+  return s;
+}
+#define NCHK(expr)                                                                      \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return nfail(LBAXI_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+struct Conv {
+  int ci, Ck, co;         // real / padded input channels, output channels
+  long long off_W, off_b; // offsets in the flat FP32 parameter vector
+  size_t wf, wb;          // byte offsets of the BF16 copies in the workspace
+};
+
+enum { E0A, E0B, E1A, E1B, E2A, E2B, E3A, E3B, D2A, D2B, D1A, D1B, D0A, D0B, NCONV };
+
+struct Plan {
+  lbnn_desc d;
+  Conv cv[NCONV];
+  long long off_hW, off_hb, nparam;
+  // workspace byte offsets
+  size_t params, grads, m1, m2, wcopies, loss, act, total;
+  // activations (BF16) per level, element counts per sample
+  size_t xin, e_a[4], e_b[4], pool[3], cat[3], d_a[3], d_b[3], y, gy, gbig1[4], gbig2[4],
+      gcat[3], gskip[3];
+};
+
+long long npix_lvl(const lbnn_desc& d, int l) { return (long long)(d.H >> l) * (d.W >> l); }
+
+bool plan(const lbnn_desc& d, Plan& P) {
+  P.d = d;
+  const int c0 = d.widths[0], c1 = d.widths[1], c2 = d.widths[2], c3 = d.widths[3];
+  const int io[NCONV][2] = {{d.c_in, c0}, {c0, c0}, {c0, c1}, {c1, c1}, {c1, c2},
+                            {c2, c2},     {c2, c3}, {c3, c3}, {c3 + c2, c2}, {c2, c2},
+                            {c2 + c1, c1}, {c1, c1}, {c1 + c0, c0}, {c0, c0}};
+  long long off = 0;
+  for (int k = 0; k < NCONV; ++k) {
+    Conv& c = P.cv[k];
+    c.ci = io[k][0];
+    c.Ck = k == E0A ? 16 : io[k][0];
+    c.co = io[k][1];
+    c.off_W = off;
+    off += 9LL * c.ci * c.co;
+    c.off_b = off;
+    off += c.co;
+  }
+  P.off_hW = off;
+  off += (long long)c0 * d.c_out;
+  P.off_hb = off;
+  off += d.c_out;
+  P.nparam = off;
+  size_t o = 0;
+  P.params = o; o = al(o + 4 * (size_t)P.nparam);
+  P.grads = o; o = al(o + 4 * (size_t)P.nparam);
+  P.m1 = o; o = al(o + 4 * (size_t)P.nparam);
+  P.m2 = o; o = al(o + 4 * (size_t)P.nparam);
+  P.wcopies = o;
+  for (int k = 0; k < NCONV; ++k) {
+    Conv& c = P.cv[k];
+    c.wf = o; o = al(o + 2 * 9 * (size_t)c.Ck * c.co);
+    c.wb = o; o = al(o + 2 * 9 * (size_t)c.Ck * c.co);
+  }
+  P.loss = o; o = al(o + 8);
+  P.act = o;
+  const size_t B = d.max_batch;
+  const int cw[4] = {c0, c1, c2, c3};
+  auto take = [&](size_t elems) { size_t r = o; o = al(o + 2 * elems * B); return r; };
+  P.xin = take(16 * (size_t)npix_lvl(d, 0));
+  for (int l = 0; l < 4; ++l) {
+    P.e_a[l] = take((size_t)cw[l] * npix_lvl(d, l));
+    P.e_b[l] = take((size_t)cw[l] * npix_lvl(d, l));
+  }
+  for (int l = 0; l < 3; ++l) {
+    P.pool[l] = take((size_t)cw[l] * npix_lvl(d, l + 1));
+    P.cat[l] = take((size_t)(cw[l + 1] + cw[l]) * npix_lvl(d, l));
+    P.d_a[l] = take((size_t)cw[l] * npix_lvl(d, l));
+    P.d_b[l] = take((size_t)cw[l] * npix_lvl(d, l));
+    P.gcat[l] = take((size_t)(cw[l + 1] + cw[l]) * npix_lvl(d, l));
+    P.gskip[l] = take((size_t)cw[l] * npix_lvl(d, l));
+  }
+  for (int l = 0; l < 4; ++l) {
+    // two gradient scratch tensors per level, wide enough for its channels
+    // and for the pooled gradient of the level above
+    const size_t cmax = std::max(cw[l], l > 0 ? cw[l - 1] : 0);
+    P.gbig1[l] = take(cmax * npix_lvl(d, l));
+    P.gbig2[l] = take(cmax * npix_lvl(d, l));
+  }
+  P.y = o; o = al(o + 4 * B * d.c_out * (size_t)npix_lvl(d, 0));
+  P.gy = o; o = al(o + 4 * B * d.c_out * (size_t)npix_lvl(d, 0));
+  P.total = o;
+  return true;
+}
+
+lbaxi_status validate(const lbnn_desc* d) {
+  if (!d) return nfail(LBAXI_EINVAL, "NULL desc");
+  if (d->H < 8 || d->W < 8 || d->H % 8 || d->W % 8) return nfail(LBAXI_EINVAL, "H, W must be multiples of 8");
+  if (d->c_in < 1 || d->c_in > 16) return nfail(LBAXI_EINVAL, "c_in must be in 1..16");
+  if (d->c_out < 1 || d->c_out > 8) return nfail(LBAXI_EINVAL, "c_out must be in 1..8");
+  for (int k = 0; k < 4; ++k)
+    if (d->widths[k] < 32 || d->widths[k] % 32) return nfail(LBAXI_EINVAL, "widths must be multiples of 32");
+  if (d->max_batch < 1) return nfail(LBAXI_EINVAL, "max_batch must be >= 1");
+  return LBAXI_OK;
+}
+
+}  // namespace
+
+struct lbnn_s {
+  Plan P;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int batch = 0;       // batch of the last forward
+  long long step = 0;  // Adam step counter
+  bool wdirty = true;  // BF16 copies out of date
+  template <typename T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  float* params() const { return at<float>(P.params); }
+  float* grads() const { return at<float>(P.grads); }
+  bf16s* act(size_t off) const { return at<bf16s>(off); }
+};
+
+namespace {
+
+unsigned blocks(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+lbaxi_status refresh_weights(lbnn_t* h) {
+  if (!h->wdirty) return LBAXI_OK;
+  for (int k = 0; k < NCONV; ++k) {
+    const Conv& c = h->P.cv[k];
+    hipLaunchKernelGGL(k_cast_w, dim3(blocks(9LL * c.Ck * c.co)), dim3(256), 0, h->stream,
+                       h->params() + c.off_W, h->at<bf16s>(c.wf), h->at<bf16s>(c.wb), c.ci, c.Ck,
+                       c.co);
+  }
+  NCHK(hipGetLastError());
+  h->wdirty = false;
+  return LBAXI_OK;
+}
+
+lbaxi_status conv(lbnn_t* h, const Conv& c, const bf16s* in, bf16s* out, int lvl, int B,
+                  bool adjoint, const bf16s* mask) {
+  ConvArgs A;
+  A.B = B;
+  A.H = h->P.d.H >> lvl;
+  A.W = h->P.d.W >> lvl;
+  A.in = in;
+  A.out = out;
+  A.mask = mask;
+  if (!adjoint) {
+    A.wt = h->at<bf16s>(c.wf);
+    A.bias = h->params() + c.off_b;
+    A.Ck = c.Ck;
+    A.Cn = c.co;
+    A.sign = 1;
+    A.relu = 1;
+  } else {
+    A.wt = h->at<bf16s>(c.wb);
+    A.bias = nullptr;
+    A.Ck = c.co;
+    A.Cn = c.Ck;
+    A.sign = -1;
+    A.relu = 0;
+  }
+  const long long npix = (long long)B * A.H * A.W;
+  dim3 grid(blocks(npix, 128), A.Cn / 32);
+  hipLaunchKernelGGL(k_conv, grid, dim3(256), 0, h->stream, A);
+  NCHK(hipGetLastError());
+  return LBAXI_OK;
+}
+
+lbaxi_status wgrad(lbnn_t* h, const Conv& c, const bf16s* x, const bf16s* gz, int lvl, int B) {
+  WgradArgs A;
+  A.x = x;
+  A.gz = gz;
+  A.dW = h->grads() + c.off_W;
+  A.B = B;
+  A.H = h->P.d.H >> lvl;
+  A.W = h->P.d.W >> lvl;
+  A.Cx = c.Ck;
+  A.Ci = c.ci;
+  A.Co = c.co;
+  A.chunk = 1024;
+  const long long npix = (long long)B * A.H * A.W;
+  dim3 grid(blocks(npix, A.chunk), 9 * ((A.Ci + 31) / 32) * (A.Co / 32));
+  hipLaunchKernelGGL(k_wgrad, grid, dim3(64), 0, h->stream, A);
+  NCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_bgrad, dim3(blocks(npix)), dim3(256), 0, h->stream, gz,
+                     h->grads() + c.off_b, npix, c.co);
+  NCHK(hipGetLastError());
+  return LBAXI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbaxi_status lbnn_workspace_bytes(const lbnn_desc* d, size_t* bytes) {
+  lbaxi_status s = validate(d);
+  if (s != LBAXI_OK) return s;
+  if (!bytes) return nfail(LBAXI_EINVAL, "NULL bytes");
+  Plan P;
+  plan(*d, P);
+  *bytes = P.total;
+  return LBAXI_OK;
+}
+
+lbaxi_status lbnn_create(const lbnn_desc* d, void* d_workspace, size_t bytes, void* hip_stream,
+                         lbnn_t** out) {
+  if (!out) return nfail(LBAXI_EINVAL, "NULL out");
+  *out = nullptr;
+  size_t need;
+  lbaxi_status s = lbnn_workspace_bytes(d, &need);
+  if (s != LBAXI_OK) return s;
+  if (!d_workspace || reinterpret_cast<uintptr_t>(d_workspace) % 256)
+    return nfail(LBAXI_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < need) return nfail(LBAXI_ENOMEM, "workspace smaller than lbnn_workspace_bytes");
+  lbnn_t* h = new (std::nothrow) lbnn_s();
+  if (!h) return nfail(LBAXI_ENOMEM, "host allocation failed");
+  plan(*d, h->P);
+  h->ws = static_cast<char*>(d_workspace);
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  const long long n = h->P.nparam;
+  for (size_t off : {h->P.params, h->P.grads, h->P.m1, h->P.m2})
+    hipLaunchKernelGGL(k_zero, dim3(blocks(n)), dim3(256), 0, h->stream, h->at<float>(off), n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    delete h;
+    return nfail(LBAXI_EDEVICE, hipGetErrorString(e));
+  }
+  *out = h;
+  return LBAXI_OK;
+}
+
+void lbnn_destroy(lbnn_t* h) { delete h; }
+
+lbaxi_status lbnn_param_count(const lbnn_t* h, int64_t* n) {
+  if (!h || !n) return nfail(LBAXI_EINVAL, "NULL argument");
+  *n = h->P.nparam;
+  return LBAXI_OK;
+}
+
+lbaxi_status lbnn_set_params(lbnn_t* h, const float* d_params) {
+  if (!h || !d_params) return nfail(LBAXI_EINVAL, "NULL argument");
+  NCHK(hipMemcpyAsync(h->params(), d_params, 4 * (size_t)h->P.nparam, hipMemcpyDeviceToDevice,
+                      h->stream));
+  const long long n = h->P.nparam;
+  for (size_t off : {h->P.m1, h->P.m2})
+    hipLaunchKernelGGL(k_zero, dim3(blocks(n)), dim3(256), 0, h->stream, h->at<float>(off), n);
+  NCHK(hipGetLastError());
+  h->step = 0;
+  h->wdirty = true;
+  return LBAXI_OK;
+}
+
+lbaxi_status lbnn_get_params(lbnn_t* h, float* d_params) {
+  if (!h || !d_params) return nfail(LBAXI_EINVAL, "NULL argument");
+  NCHK(hipMemcpyAsync(d_params, h->params(), 4 * (size_t)h->P.nparam, hipMemcpyDeviceToDevice,
+                      h->stream));
+  return LBAXI_OK;
+}
+
+lbaxi_status lbnn_forward(lbnn_t* h, const float* d_x, float* d_y, int32_t B) {
+  if (!h || !d_x) return nfail(LBAXI_EINVAL, "NULL argument");
+  const Plan& P = h->P;
+  if (B < 1 || B > P.d.max_batch) return nfail(LBAXI_EINVAL, "batch out of range");
+  lbaxi_status s;
+  if ((s = refresh_weights(h)) != LBAXI_OK) return s;
+  const int c0 = P.d.widths[0], c1 = P.d.widths[1], c2 = P.d.widths[2], c3 = P.d.widths[3];
+  const int cw[4] = {c0, c1, c2, c3};
+  const long long np0 = (long long)B * npix_lvl(P.d, 0);
+  hipLaunchKernelGGL(k_input, dim3(blocks(np0 * 16)), dim3(256), 0, h->stream, d_x,
+                     h->act(P.xin), np0, P.d.c_in);
+  NCHK(hipGetLastError());
+  const bf16s* x = h->act(P.xin);
+  for (int l = 0; l < 4; ++l) {
+    if (l > 0) {
+      const int Hh = P.d.H >> (l - 1), Ww = P.d.W >> (l - 1);
+      hipLaunchKernelGGL(k_pool, dim3(blocks((long long)B * (Hh / 2) * (Ww / 2) * cw[l - 1])),
+                         dim3(256), 0, h->stream, h->act(P.e_b[l - 1]), h->act(P.pool[l - 1]), B,
+                         Hh, Ww, cw[l - 1]);
+      NCHK(hipGetLastError());
+      x = h->act(P.pool[l - 1]);
+    }
+    if ((s = conv(h, P.cv[2 * l], x, h->act(P.e_a[l]), l, B, false, nullptr)) != LBAXI_OK) return s;
+    if ((s = conv(h, P.cv[2 * l + 1], h->act(P.e_a[l]), h->act(P.e_b[l]), l, B, false, nullptr)) !=
+        LBAXI_OK)
+      return s;
+  }
+  const bf16s* below = h->act(P.e_b[3]);
+  for (int l = 2; l >= 0; --l) {
+    const int Hl = P.d.H >> l, Wl = P.d.W >> l;
+    const long long tot = (long long)B * Hl * Wl * (cw[l + 1] + cw[l]);
+    hipLaunchKernelGGL(k_upcat, dim3(blocks(tot)), dim3(256), 0, h->stream, below,
+                       h->act(P.e_b[l]), h->act(P.cat[l]), B, Hl, Wl, cw[l + 1], cw[l]);
+    NCHK(hipGetLastError());
+    const int ka = D2A + 2 * (2 - l);
+    if ((s = conv(h, P.cv[ka], h->act(P.cat[l]), h->act(P.d_a[l]), l, B, false, nullptr)) != LBAXI_OK)
+      return s;
+    if ((s = conv(h, P.cv[ka + 1], h->act(P.d_a[l]), h->act(P.d_b[l]), l, B, false, nullptr)) !=
+        LBAXI_OK)
+      return s;
+    below = h->act(P.d_b[l]);
+  }
+  float* y = d_y ? d_y : h->at<float>(P.y);
+  hipLaunchKernelGGL(k_head, dim3(blocks(np0)), dim3(256), 0, h->stream, h->act(P.d_b[0]),
+                     h->params() + P.off_hW, h->params() + P.off_hb, h->at<float>(P.y),
+                     (const float*)nullptr, (float*)nullptr, (double*)nullptr, np0, c0, P.d.c_out,
+                     0.0);
+  NCHK(hipGetLastError());
+  if (d_y)
+    NCHK(hipMemcpyAsync(y, h->at<float>(P.y), 4 * (size_t)np0 * P.d.c_out,
+                        hipMemcpyDeviceToDevice, h->stream));
+  h->batch = B;
+  return LBAXI_OK;
+}
+
+lbaxi_status lbnn_backward(lbnn_t* h, const float* d_target, float* d_grads, double* host_loss) {
+  if (!h || !d_target) return nfail(LBAXI_EINVAL, "NULL argument");
+  if (h->batch < 1) return nfail(LBAXI_ESTATE, "no forward pass to differentiate");
+  const Plan& P = h->P;
+  const int B = h->batch;
+  const int c0 = P.d.widths[0], c1 = P.d.widths[1], c2 = P.d.widths[2], c3 = P.d.widths[3];
+  const int cw[4] = {c0, c1, c2, c3};
+  const long long np0 = (long long)B * npix_lvl(P.d, 0);
+  lbaxi_status s;
+  hipLaunchKernelGGL(k_zero, dim3(blocks(P.nparam)), dim3(256), 0, h->stream, h->grads(),
+                     P.nparam);
+  hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, h->stream, h->at<double>(P.loss));
+  // head: y again with the target, then its backward into gz of d0b
+  hipLaunchKernelGGL(k_head, dim3(blocks(np0)), dim3(256), 0, h->stream, h->act(P.d_b[0]),
+                     h->params() + P.off_hW, h->params() + P.off_hb, h->at<float>(P.y), d_target,
+                     h->at<float>(P.gy), h->at<double>(P.loss), np0, c0, P.d.c_out,
+                     1.0 / ((double)np0 * P.d.c_out));
+  hipLaunchKernelGGL(k_head_back, dim3(blocks(np0)), dim3(256), 0, h->stream, h->act(P.d_b[0]),
+                     h->at<float>(P.gy), h->params() + P.off_hW, h->act(P.gbig1[0]), np0, c0,
+                     P.d.c_out);
+  hipLaunchKernelGGL(k_head_wgrad, dim3(c0 + 1), dim3(256), 0, h->stream, h->act(P.d_b[0]),
+                     h->at<float>(P.gy), h->grads() + P.off_hW, h->grads() + P.off_hb, np0, c0,
+                     P.d.c_out);
+  NCHK(hipGetLastError());
+  // decoder levels 0, 1, 2: gz of the block output is in gbig1[l]
+  for (int l = 0; l <= 2; ++l) {
+    const int ka = D2A + 2 * (2 - l);
+    const Conv& ca = P.cv[ka];
+    const Conv& cb = P.cv[ka + 1];
+    bf16s* gzb = h->act(P.gbig1[l]);
+    bf16s* gza = h->act(P.gbig2[l]);
+    if ((s = wgrad(h, cb, h->act(P.d_a[l]), gzb, l, B)) != LBAXI_OK) return s;
+    if ((s = conv(h, cb, gzb, gza, l, B, true, h->act(P.d_a[l]))) != LBAXI_OK) return s;
+    if ((s = wgrad(h, ca, h->act(P.cat[l]), gza, l, B)) != LBAXI_OK) return s;
+    if ((s = conv(h, ca, gza, h->act(P.gcat[l]), l, B, true, nullptr)) != LBAXI_OK) return s;
+    // split: upsampled part -> gz of the level below's block output (masked by
+    // that ReLU output), skip part -> gskip[l]
+    const int Hl = P.d.H >> l, Wl = P.d.W >> l;
+    const bf16s* u = l < 2 ? h->act(P.d_b[l + 1]) : h->act(P.e_b[3]);
+    bf16s* gu = h->act(P.gbig1[l + 1]);
+    const long long tot =
+        (long long)B * (Hl / 2) * (Wl / 2) * cw[l + 1] + (long long)B * Hl * Wl * cw[l];
+    hipLaunchKernelGGL(k_upcat_back, dim3(blocks(tot)), dim3(256), 0, h->stream,
+                       h->act(P.gcat[l]), u, gu, h->act(P.gskip[l]), B, Hl, Wl, cw[l + 1], cw[l]);
+    NCHK(hipGetLastError());
+  }
+  // encoder levels 3, 2, 1, 0: gz of e_b[l] in gbig1[l]
+  for (int l = 3; l >= 0; --l) {
+    const Conv& ca = P.cv[2 * l];
+    const Conv& cb = P.cv[2 * l + 1];
+    bf16s* gzb = h->act(P.gbig1[l]);
+    bf16s* gza = h->act(P.gbig2[l]);
+    if ((s = wgrad(h, cb, h->act(P.e_a[l]), gzb, l, B)) != LBAXI_OK) return s;
+    if ((s = conv(h, cb, gzb, gza, l, B, true, h->act(P.e_a[l]))) != LBAXI_OK) return s;
+    const bf16s* xin = l > 0 ? h->act(P.pool[l - 1]) : h->act(P.xin);
+    if (l == 0) {
+      // first layer: padded 16 input channels, gradient of the input unused
+      if ((s = wgrad(h, ca, xin, gza, l, B)) != LBAXI_OK) return s;
+      break;
+    }
+    if ((s = wgrad(h, ca, xin, gza, l, B)) != LBAXI_OK) return s;
+    // gradient of the pooled input, then into e_b[l-1] with its skip part
+    bf16s* gp = h->act(P.gbig1[l]);  // gzb is dead now
+    if ((s = conv(h, ca, gza, gp, l, B, true, nullptr)) != LBAXI_OK) return s;
+    const int Hh = P.d.H >> (l - 1), Ww = P.d.W >> (l - 1);
+    hipLaunchKernelGGL(k_pool_back, dim3(blocks((long long)B * Hh * Ww * cw[l - 1])), dim3(256), 0,
+                       h->stream, gp, h->act(P.gskip[l - 1]), h->act(P.e_b[l - 1]),
+                       h->act(P.gbig1[l - 1]), B, Hh, Ww, cw[l - 1]);
+    NCHK(hipGetLastError());
+  }
+  if (d_grads)
+    NCHK(hipMemcpyAsync(d_grads, h->grads(), 4 * (size_t)P.nparam, hipMemcpyDeviceToDevice,
+                        h->stream));
+  if (host_loss) {
+    double L;
+    NCHK(hipMemcpyAsync(&L, h->at<double>(P.loss), 8, hipMemcpyDeviceToHost, h->stream));
+    NCHK(hipStreamSynchronize(h->stream));
+    *host_loss = L / ((double)np0 * P.d.c_out);
+  }
+  return LBAXI_OK;
+}
+
+lbaxi_status lbnn_adam(lbnn_t* h, float lr, float b1, float b2, float eps) {
+  if (!h) return nfail(LBAXI_EINVAL, "NULL handle");
+  h->step += 1;
+  const float c1 = 1.0f - powf(b1, (float)h->step), c2 = 1.0f - powf(b2, (float)h->step);
+  hipLaunchKernelGGL(k_adam, dim3(blocks(h->P.nparam)), dim3(256), 0, h->stream, h->params(),
+                     h->grads(), h->at<float>(h->P.m1), h->at<float>(h->P.m2), h->P.nparam, lr, b1,
+                     b2, eps, c1, c2);
+  NCHK(hipGetLastError());
+  h->wdirty = true;
+  return LBAXI_OK;
+}
+
+lbaxi_status lbnn_train_step(lbnn_t* h, const float* d_x, const float* d_target, int32_t batch,
+                             float lr, double* host_loss) {
+  lbaxi_status s = lbnn_forward(h, d_x, nullptr, batch);
+  if (s == LBAXI_OK) s = lbnn_backward(h, d_target, nullptr, host_loss);
+  if (s == LBAXI_OK) s = lbnn_adam(h, lr, 0.9f, 0.999f, 1e-8f);
+  return s;
+}
+
+lbaxi_status lbnn_to_fields(lbnn_t* h, const float* d_y, int32_t batch, const float* sc,
+                            const float* of, float* d_uz, float* d_ur, float* d_uth, float* d_T) {
+  if (!h || !d_y || !sc || !of) return nfail(LBAXI_EINVAL, "NULL argument");
+  if (batch < 1 || batch > h->P.d.max_batch) return nfail(LBAXI_EINVAL, "batch out of range");
+  const long long np = (long long)batch * npix_lvl(h->P.d, 0);
+  hipLaunchKernelGGL(k_to_fields, dim3(blocks(np)), dim3(256), 0, h->stream, d_y, np, h->P.d.c_out,
+                     make_float4(sc[0], sc[1], sc[2], sc[3]), make_float4(of[0], of[1], of[2], of[3]),
+                     d_uz, d_ur, d_uth, d_T);
+  NCHK(hipGetLastError());
+  return LBAXI_OK;
+}
+
+lbaxi_status lbnn_mfma_selftest(int32_t* d_counter, void* hip_stream, int32_t* host_mismatches) {
+  if (!host_mismatches || !d_counter) return nfail(LBAXI_EINVAL, "NULL argument");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, st, d_counter, 0);
+  hipLaunchKernelGGL(k_mfma_selftest, dim3(1), dim3(64), 0, st, d_counter);
+  NCHK(hipGetLastError());
+  int bad = -1;
+  NCHK(hipMemcpyAsync(&bad, d_counter, sizeof(int), hipMemcpyDeviceToHost, st));
+  NCHK(hipStreamSynchronize(st));
+  *host_mismatches = bad;
+  return LBAXI_OK;
+}
+
+const char* lbnn_last_error(void) { return g_nerr.c_str(); }
+
+}  // extern "C"

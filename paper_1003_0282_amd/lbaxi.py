@@ -60,6 +60,7 @@ _sigs = {
     "lbaxi_time": (_st, [_P, C.c_int32, C.POINTER(C.c_int64)]),
     "lbaxi_batch_run": (_st, [_P, C.c_double, C.c_int64, C.c_int64, C.POINTER(C.c_int32),
                               C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "lbaxi_resume": (_st, [_P, C.POINTER(C.c_int32)]),
     "lbaxi_set_launch": (_st, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "lbaxi_get_launch": (_st, [_P, C.POINTER(C.c_int32)]),
     "lbaxi_set_graph_steps": (_st, [_P, C.c_int32]),
@@ -252,6 +253,11 @@ class Lattices:
         _check(_L.lbaxi_batch_run(self.h, float(tol), int(max_steps), int(check_every), st,
                                   steps, res), "lbaxi_batch_run")
         return RunResult(np.array(st[:]), np.array(steps[:]), np.array(res[:]))
+
+    def resume(self) -> int:
+        n = C.c_int32()
+        _check(_L.lbaxi_resume(self.h, C.byref(n)), "lbaxi_resume")
+        return int(n.value)
 
     def set_launch(self, tile_z=64, tile_r=4, grid=0, xcd=0, nt_store=1):
         _check(_L.lbaxi_set_launch(self.h, tile_z, tile_r, grid, xcd, nt_store),

@@ -25,19 +25,39 @@ def L():
 
 
 def test_every_declared_symbol_is_exported(L):
-    lib = C.CDLL(L.LIB_PATH)
-    names = []
-    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
-        if hdr.endswith(".h"):
-            names += _declared(hdr)
-    assert len(names) >= 20
-    missing = [n for n in names if not hasattr(lib, n)]
-    assert not missing, missing
+    from paper_1003_0282_amd import lbnn
+    libs = {"lbaxi.h": C.CDLL(L.LIB_PATH), "lbnn.h": C.CDLL(lbnn.LIB_PATH)}
+    headers = sorted(h for h in os.listdir(os.path.join(ROOT, "include")) if h.endswith(".h"))
+    assert headers == sorted(libs)
+    total = 0
+    for hdr, lib in libs.items():
+        names = [n for n in _declared(hdr) if n.startswith(hdr.split(".")[0] + "_")]
+        total += len(names)
+        missing = [n for n in names if not hasattr(lib, n)]
+        assert not missing, (hdr, missing)
+    assert total >= 30
 
 
 def test_binding_covers_header(L):
+    from paper_1003_0282_amd import lbnn
     declared = set(_declared("lbaxi.h"))
     assert declared == set(L.exported_symbols()), declared ^ set(L.exported_symbols())
+    declared_nn = set(n for n in _declared("lbnn.h") if n.startswith("lbnn_"))
+    assert declared_nn == set(lbnn.exported_symbols()), declared_nn ^ set(lbnn.exported_symbols())
+
+
+def test_nn_workspace_and_validation():
+    import ctypes as C2
+    from paper_1003_0282_amd import lbnn
+    d = lbnn.Desc()
+    d.H, d.W, d.c_in, d.c_out, d.max_batch = 128, 256, 8, 4, 4
+    for k, w in enumerate((32, 64, 128, 256)):
+        d.widths[k] = w
+    b = C2.c_size_t()
+    assert lbnn._L.lbnn_workspace_bytes(C2.byref(d), C2.byref(b)) == 0
+    assert b.value > 4 * 4 * 1.9e6
+    d.widths[1] = 48
+    assert lbnn._L.lbnn_workspace_bytes(C2.byref(d), C2.byref(b)) == -1
 
 
 def test_desc_layout(L):
