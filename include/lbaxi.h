@@ -134,13 +134,15 @@ lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace,
 void lbaxi_destroy(lbaxi_t* h);
 
 /* Equilibrium seeding of every lattice (Eq. 6 and Eq. 54; the paper starts
- * from zero velocity): f^ = f_eq(rho0, u) - S(rho0, u)/2, g = g_eq, h = h_eq,
- * so Eqs. (16)-(17) return the given fields.  Each d_ pointer is a packed
- * field set of the handle's precision (double for FP64, float for FP32), or
- * NULL for zero velocity / T_ref.  u_r and u_theta are forced to 0 on an
- * axis row.  Resets the time to 0 and every status to RUNNING. */
-lbaxi_status lbaxi_seed(lbaxi_t* h, const void* d_uz, const void* d_ur, const void* d_uth,
-                        const void* d_T);
+ * from rest): f^ = f_eq(rho, u) - S(rho, u)/2 with S of Eq. (12), g = g_eq,
+ * h = h_eq, so Eqs. (16)-(17) return the given fields.  Each d_ pointer is a
+ * packed field set of the handle's precision (double for FP64, float for
+ * FP32), or NULL for rho0 / zero velocity / T_ref.  u_r and u_theta are
+ * forced to 0 on an axis row.  Resets the time to 0 and every status to
+ * RUNNING.  The fields are read by a kernel on the handle's stream: they must
+ * stay valid until that stream has passed this call. */
+lbaxi_status lbaxi_seed(lbaxi_t* h, const void* d_rho, const void* d_uz, const void* d_ur,
+                        const void* d_uth, const void* d_T);
 
 /* Advance every RUNNING lattice by n >= 0 time steps (asynchronous).  One
  * step = pull streaming with the boundary rules + macros (Eqs. 16-17) +

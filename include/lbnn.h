@@ -2,7 +2,7 @@
  * lbnn.h -- C ABI of the warm-start network for the axisymmetric lattice
  * Boltzmann solver (include/lbaxi.h): a 4-level convolutional U-Net that maps
  * per-node geometry / parameter features of a lattice to its steady macroscopic
- * fields (u_z, u_r, u_theta, T), trained and run with hand-written gfx950
+ * fields (rho, u_z, u_r, u_theta, T), trained and run with hand-written gfx950
  * kernels (BF16 MFMA with FP32 accumulation).  Its prediction seeds the
  * populations at equilibrium (lbaxi_seed, which follows Eqs. 6 and 54 of
  * Li, He, Tang, Tao, arXiv:1003.0282); the lattice Boltzmann run to the
@@ -78,12 +78,15 @@ lbaxi_status lbnn_adam(lbnn_t* h, float lr, float beta1, float beta2, float eps)
 lbaxi_status lbnn_train_step(lbnn_t* h, const float* d_x, const float* d_target, int32_t batch,
                              float lr, double* host_loss);
 
-/* Network output -> solver fields: channel k of d_y times scale[k] plus
- * offset[k] is written to field k (u_z, u_r, u_theta, T), each packed
- * [batch][H][W] in float (d_fields[k] may be NULL to skip). */
-lbaxi_status lbnn_to_fields(lbnn_t* h, const float* d_y, int32_t batch, const float* host_scale4,
-                            const float* host_offset4, float* d_uz, float* d_ur, float* d_uth,
-                            float* d_T);
+/* Network output -> solver fields: channel k of d_y [batch][H][W][c_out],
+ * optionally low-passed, times host_scale[k] plus host_offset[k], is written
+ * to d_fields[k] (a packed [batch][H][W] float field; NULL skips it), for k <
+ * c_out.  smooth = 1 applies the separable (1, 2, 1)/4 filter along H and W
+ * (edge values repeated), which removes the checkerboard (Nyquist) component
+ * of a prediction; smooth = 0 copies.  host_scale, host_offset and d_fields
+ * are host arrays of c_out entries. */
+lbaxi_status lbnn_to_fields(lbnn_t* h, const float* d_y, int32_t batch, const float* host_scale,
+                            const float* host_offset, int32_t smooth, float* const* d_fields);
 
 /* Self-test of the BF16 MFMA accumulator layout the convolution kernels
  * rely on: multiplies known 32x16 by 16x32 matrices on the device and

@@ -442,11 +442,13 @@ static void node_inputs(const orc_state* s, int i, int j, double* f, double* g,
   }
 }
 
-/* Equilibrium seeding: f^ = f_eq(rho0, u) - S(rho0, u)/2 (the paper's
+/* Equilibrium seeding: f^ = f_eq(rho, u) - S(rho, u)/2 (the paper's
  * f^ = f - Omega/2 - S/2 with Omega = 0), g = g_eq, h = h_eq.  NULL fields
- * mean zero velocity / T_ref.  On the axis row u_r and u_th are forced to 0. */
+ * mean rho0 / zero velocity / T_ref.  On the axis row u_r and u_th are forced
+ * to 0.  Summing Eq. (12) gives sum S = -rho u_r / r and sum e_r S = F_r -
+ * rho u_r^2 / r, so Eqs. (16)-(17) return the seeded rho and u exactly.      */
 void orc_seed(orc_state* s, const double* uz, const double* ur,
-              const double* uth, const double* T) {
+              const double* uth, const double* T, const double* rho) {
   const orc_params* p = &s->p;
   s->t = 0;
   s->have_spd = 0;
@@ -454,7 +456,7 @@ void orc_seed(orc_state* s, const double* uz, const double* ur,
     for (int i = 0; i < p->nz; ++i) {
       size_t n = (size_t)j * p->nz + i;
       double m[5];
-      m[0] = p->rho0;
+      m[0] = rho ? rho[n] : p->rho0;
       m[1] = uz ? uz[n] : 0.0;
       m[2] = ur ? ur[n] : 0.0;
       m[3] = (uth && p->swirl) ? uth[n] : 0.0;

@@ -81,7 +81,7 @@ def lib():
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.POINTER(_Params)]
         L.orc_destroy.argtypes = [C.c_void_p]
-        L.orc_seed.argtypes = [C.c_void_p, P, P, P, P]
+        L.orc_seed.argtypes = [C.c_void_p, P, P, P, P, P]
         L.orc_step.argtypes = [C.c_void_p, C.c_int64]
         L.orc_macros.argtypes = [C.c_void_p, P, P, P, P, P]
         L.orc_residual.restype = C.c_double
@@ -181,8 +181,8 @@ class Oracle:
         a = np.ascontiguousarray(a, dtype=np.float64).reshape(self.nr, self.nz)
         return a
 
-    def seed(self, uz=None, ur=None, uth=None, T=None):
-        fields = [self._field(x) for x in (uz, ur, uth, T)]
+    def seed(self, uz=None, ur=None, uth=None, T=None, rho=None):
+        fields = [self._field(x) for x in (uz, ur, uth, T, rho)]
         self.L.orc_seed(self.h, *[_ptr(x) for x in fields])
 
     def step(self, n: int = 1):

@@ -187,7 +187,8 @@ __global__ void __launch_bounds__(256) k_halo(const InstP* ip, const Tile* tiles
 // Equilibrium seeding: f^ = f_eq - S/2 at rho = rho0, g = g_eq, h = h_eq.
 template <typename S, typename R, int F>
 __global__ void __launch_bounds__(1024) k_seed(const InstP* ip, const Tile* tiles,
-                                               const int* ntiles, S* buf, const S* uz_in,
+                                               const int* ntiles, S* buf, const S* rho_in,
+                                               const S* uz_in,
                                                const S* ur_in, const S* uth_in, const S* T_in,
                                                int tzlog) {
   const int ti = blockIdx.x;
@@ -204,6 +205,8 @@ __global__ void __launch_bounds__(1024) k_seed(const InstP* ip, const Tile* tile
   const R ur = (ur_in && !axis_row) ? (R)ur_in[fo] : (R)0;
   const R uth = ((F & F_SWIRL) && uth_in && !axis_row) ? (R)uth_in[fo] : (R)0;
   const R dT = ((F & F_THERMAL) && T_in) ? (R)T_in[fo] - p.T_ref : (R)0;
+  const R drho = rho_in ? (R)rho_in[fo] - p.rho0 : (R)0;
+  const R rho = p.rho0 + drho;
   const R ir = make_row<R, F>(p, j).ir;
   R Fz = p.a_t;
   if (F & F_THERMAL) Fz += p.rho0 * p.gbeta * dT;
@@ -217,8 +220,8 @@ __global__ void __launch_bounds__(1024) k_seed(const InstP* ip, const Tile* tile
     const R ez = (R)ez9(a), er = (R)er9(a), w = (R)w9(a);
     const R eu = ez * uz + er * ur;
     const R Pa = (R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * usq;
-    const R Sa = w * ((R)1 + Pa) * ((R)3 * ((ez - uz) * Fz + (er - ur) * Fr) - p.rho0 * ur * ir);
-    d[a * pl + o] = (S)(w * p.rho0 * Pa - (R)0.5 * Sa);
+    const R Sa = w * ((R)1 + Pa) * ((R)3 * ((ez - uz) * Fz + (er - ur) * Fr) - rho * ur * ir);
+    d[a * pl + o] = (S)(w * (drho + rho * Pa) - (R)0.5 * Sa);
   }
   if (F & F_SWIRL) {
 #pragma unroll
@@ -973,7 +976,7 @@ lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace,
   }
   // default launch shape: one wave along z, 4 rows, one workgroup per tile
   st = lbaxi_set_launch(h, 64, 4, 0, 0, 1);
-  if (st == LBAXI_OK) st = lbaxi_seed(h, nullptr, nullptr, nullptr, nullptr);
+  if (st == LBAXI_OK) st = lbaxi_seed(h, nullptr, nullptr, nullptr, nullptr, nullptr);
   if (st != LBAXI_OK) {
     lbaxi_destroy(h);
     return st;
@@ -989,8 +992,8 @@ void lbaxi_destroy(lbaxi_t* h) {
   delete h;
 }
 
-lbaxi_status lbaxi_seed(lbaxi_t* h, const void* d_uz, const void* d_ur, const void* d_uth,
-                        const void* d_T) {
+lbaxi_status lbaxi_seed(lbaxi_t* h, const void* d_rho, const void* d_uz, const void* d_ur,
+                        const void* d_uth, const void* d_T) {
   lbaxi_status st = check_handle(h);
   if (st != LBAXI_OK) return st;
   bool changed = false;
@@ -1006,7 +1009,7 @@ lbaxi_status lbaxi_seed(lbaxi_t* h, const void* d_uz, const void* d_ur, const vo
   const int* nt = h->d_counts + LIST_ALL;
   void* buf = h->bufA;
   int tzlog = ilog2(h->tz);
-  void* args[] = {&ip, &tl, &nt, &buf, &d_uz, &d_ur, &d_uth, &d_T, &tzlog};
+  void* args[] = {&ip, &tl, &nt, &buf, &d_rho, &d_uz, &d_ur, &d_uth, &d_T, &tzlog};
   HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])), dim3(h->tz * h->tr), args,
                          0, h->stream));
   h->cur = 0;

@@ -368,14 +368,39 @@ __global__ void k_zero_d(double* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0.0;
 }
 
-__global__ void k_to_fields(const float* y, long long npix, int K, float4 sc, float4 of, float* f0,
-                            float* f1, float* f2, float* f3) {
+struct FieldOut {
+  float* p[8];
+  float sc[8], of[8];
+};
+
+// y [B][H][W][K] -> fields; smooth: separable (1, 2, 1)/4 along H and W with
+// the edge value repeated.
+__global__ void k_to_fields(const float* y, int B, int H, int W, int K, int smooth, FieldOut o) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npix) return;
-  if (f0 && K > 0) f0[p] = y[p * K + 0] * sc.x + of.x;
-  if (f1 && K > 1) f1[p] = y[p * K + 1] * sc.y + of.y;
-  if (f2 && K > 2) f2[p] = y[p * K + 2] * sc.z + of.z;
-  if (f3 && K > 3) f3[p] = y[p * K + 3] * sc.w + of.w;
+  const long long hw = (long long)H * W;
+  if (p >= (long long)B * hw) return;
+  const int n = (int)(p / hw);
+  const int rem = (int)(p - (long long)n * hw);
+  const int r = rem / W, c = rem - (rem / W) * W;
+  for (int k = 0; k < K; ++k) {
+    if (!o.p[k]) continue;
+    float v;
+    if (smooth) {
+      v = 0.0f;
+      for (int dr = -1; dr <= 1; ++dr) {
+        const int rr = min(max(r + dr, 0), H - 1);
+        const float wr = dr == 0 ? 0.5f : 0.25f;
+        for (int dc = -1; dc <= 1; ++dc) {
+          const int cc = min(max(c + dc, 0), W - 1);
+          const float wc = dc == 0 ? 0.5f : 0.25f;
+          v += wr * wc * y[(((long long)n * H + rr) * W + cc) * K + k];
+        }
+      }
+    } else {
+      v = y[p * K + k];
+    }
+    o.p[k][p] = v * o.sc[k] + o.of[k];
+  }
 }
 
 // Layout self-test: A[i][k] = (i + 2k) mod 7 - 3, B[k][j] = (3k + j) mod 5 - 2
@@ -831,13 +856,20 @@ lbaxi_status lbnn_train_step(lbnn_t* h, const float* d_x, const float* d_target,
 }
 
 lbaxi_status lbnn_to_fields(lbnn_t* h, const float* d_y, int32_t batch, const float* sc,
-                            const float* of, float* d_uz, float* d_ur, float* d_uth, float* d_T) {
-  if (!h || !d_y || !sc || !of) return nfail(LBAXI_EINVAL, "NULL argument");
+                            const float* of, int32_t smooth, float* const* d_fields) {
+  if (!h || !d_y || !sc || !of || !d_fields) return nfail(LBAXI_EINVAL, "NULL argument");
   if (batch < 1 || batch > h->P.d.max_batch) return nfail(LBAXI_EINVAL, "batch out of range");
+  if (smooth != 0 && smooth != 1) return nfail(LBAXI_EINVAL, "smooth must be 0 or 1");
+  FieldOut o;
+  for (int k = 0; k < 8; ++k) {
+    const bool use = k < h->P.d.c_out;
+    o.p[k] = use ? d_fields[k] : nullptr;
+    o.sc[k] = use ? sc[k] : 0.0f;
+    o.of[k] = use ? of[k] : 0.0f;
+  }
   const long long np = (long long)batch * npix_lvl(h->P.d, 0);
-  hipLaunchKernelGGL(k_to_fields, dim3(blocks(np)), dim3(256), 0, h->stream, d_y, np, h->P.d.c_out,
-                     make_float4(sc[0], sc[1], sc[2], sc[3]), make_float4(of[0], of[1], of[2], of[3]),
-                     d_uz, d_ur, d_uth, d_T);
+  hipLaunchKernelGGL(k_to_fields, dim3(blocks(np)), dim3(256), 0, h->stream, d_y, (int)batch,
+                     h->P.d.H, h->P.d.W, h->P.d.c_out, (int)smooth, o);
   NCHK(hipGetLastError());
   return LBAXI_OK;
 }

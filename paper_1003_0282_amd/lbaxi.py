@@ -44,6 +44,10 @@ class Desc(C.Structure):
                 ("north", Side), ("west", Side), ("east", Side)]
 
 
+# torch's HIP runtime is loaded before the library so that both use the
+# same one (the library only borrows torch's device memory and streams)
+import torch  # noqa: E402,F401
+
 _L = C.CDLL(LIB_PATH)
 _st = C.c_int32
 _P = C.c_void_p
@@ -53,7 +57,7 @@ _sigs = {
     "lbaxi_workspace_bytes": (_st, [C.c_int32, C.POINTER(Desc), C.POINTER(C.c_size_t)]),
     "lbaxi_create": (_st, [C.c_int32, C.POINTER(Desc), _P, C.c_size_t, _P, C.POINTER(_P)]),
     "lbaxi_destroy": (None, [_P]),
-    "lbaxi_seed": (_st, [_P, _P, _P, _P, _P]),
+    "lbaxi_seed": (_st, [_P, _P, _P, _P, _P, _P]),
     "lbaxi_step": (_st, [_P, C.c_int64]),
     "lbaxi_macros": (_st, [_P, _P, _P, _P, _P, _P]),
     "lbaxi_residual": (_st, [_P, C.POINTER(C.c_double)]),
@@ -210,9 +214,10 @@ class Lattices:
                 for k in range(self.n)]
 
     # -- API --
-    def seed(self, uz=None, ur=None, uth=None, T=None):
+    def seed(self, uz=None, ur=None, uth=None, T=None, rho=None):
+        """Equilibrium seeding from packed fields (None: rest / T_ref / rho0)."""
         self._keep = []
-        ptrs = [self._field_ptr(x) for x in (uz, ur, uth, T)]
+        ptrs = [self._field_ptr(x) for x in (rho, uz, ur, uth, T)]
         _check(_L.lbaxi_seed(self.h, *ptrs), "lbaxi_seed")
         self._keep_seed = self._keep  # inputs must live until the kernel ran
         self.stream.synchronize()

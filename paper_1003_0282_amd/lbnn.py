@@ -21,6 +21,10 @@ class Desc(C.Structure):
                 ("widths", C.c_int32 * 4), ("max_batch", C.c_int32)]
 
 
+# torch's HIP runtime is loaded before the library so that both use the
+# same one (the library only borrows torch's device memory and streams)
+import torch  # noqa: E402,F401
+
 _L = C.CDLL(LIB_PATH)
 _st = C.c_int32
 _P = C.c_void_p
@@ -36,7 +40,7 @@ _sigs = {
     "lbnn_adam": (_st, [_P, C.c_float, C.c_float, C.c_float, C.c_float]),
     "lbnn_train_step": (_st, [_P, _P, _P, C.c_int32, C.c_float, C.POINTER(C.c_double)]),
     "lbnn_to_fields": (_st, [_P, _P, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float),
-                             _P, _P, _P, _P]),
+                             C.c_int32, C.POINTER(_P)]),
     "lbnn_mfma_selftest": (_st, [_P, _P, C.POINTER(C.c_int32)]),
     "lbnn_last_error": (C.c_char_p, []),
 }
@@ -151,13 +155,15 @@ class Net:
                                   C.byref(L)), "lbnn_train_step")
         return float(L.value)
 
-    def to_fields(self, y, scale, offset, outs):
-        """y [B,H,W,c_out] -> up to four packed float fields (torch tensors or None)."""
-        sc = (C.c_float * 4)(*[float(v) for v in scale])
-        of = (C.c_float * 4)(*[float(v) for v in offset])
-        ptrs = [C.c_void_p(o.data_ptr()) if o is not None else None for o in outs]
-        _check(_L.lbnn_to_fields(self.h, C.c_void_p(y.data_ptr()), y.shape[0], sc, of, *ptrs),
-               "lbnn_to_fields")
+    def to_fields(self, y, scale, offset, outs, smooth=False):
+        """y [B,H,W,c_out] -> one packed float field per channel (torch tensors
+        or None to skip), optionally low-passed by (1, 2, 1)/4 along H and W."""
+        k = self.c_out
+        sc = (C.c_float * k)(*[float(v) for v in scale[:k]])
+        of = (C.c_float * k)(*[float(v) for v in offset[:k]])
+        ptrs = (_P * k)(*[o.data_ptr() if o is not None else None for o in outs[:k]])
+        _check(_L.lbnn_to_fields(self.h, C.c_void_p(y.data_ptr()), y.shape[0], sc, of,
+                                 int(bool(smooth)), ptrs), "lbnn_to_fields")
 
 
 def flatten_params(p: dict, names) -> np.ndarray:

@@ -157,16 +157,18 @@ def melt(Re_c: float, Re_x: float, Gr: float, nr: int = 128, nz: int = 256,
                      Re_c=float(Re_c), Re_x=float(Re_x), Gr=float(Gr))
 
 
-def melt_set(n: int, seed: int, nr: int = 128, nz: int = 256) -> list[dict]:
-    """Seeded melt instances: |Re_c|, |Re_x| ~ U[0, 1000] with random signs,
-    Gr log-uniform in [1e3, 1e5]."""
+def melt_set(n: int, seed: int, nr: int = 128, nz: int = 256, re_max: float = 1000.0,
+             signed: bool = False, gr_range=(1e3, 1e5), nu: float = 0.0125) -> list[dict]:
+    """Seeded melt instances: Re_c, Re_x ~ U[0, re_max] (with random signs when
+    signed, i.e. counter-rotation allowed), Gr log-uniform in gr_range."""
     rng = np.random.default_rng(seed)
     out = []
+    lo, hi = np.log10(gr_range[0]), np.log10(gr_range[1])
     for _ in range(n):
-        rc = rng.uniform(0, 1000) * rng.choice([-1.0, 1.0])
-        rx = rng.uniform(0, 1000) * rng.choice([-1.0, 1.0])
-        gr = 10.0 ** rng.uniform(3.0, 5.0)
-        out.append(melt(rc, rx, gr, nr=nr, nz=nz))
+        rc = rng.uniform(0, re_max) * (rng.choice([-1.0, 1.0]) if signed else 1.0)
+        rx = rng.uniform(0, re_max) * (rng.choice([-1.0, 1.0]) if signed else 1.0)
+        gr = 10.0 ** rng.uniform(lo, hi)
+        out.append(melt(rc, rx, gr, nr=nr, nz=nz, nu=nu))
     return out
 
 
@@ -178,13 +180,14 @@ def roofline_pipe(nz: int = 16384, nr: int = 2048, tau: float = 0.8, a: float = 
 # ---- seeded random states ----------------------------------------------------
 
 def random_fields(case: dict, seed: int, amp: float = 0.02) -> dict:
-    """Smooth-ish random macroscopic fields for parity runs (not steady)."""
+    """Random macroscopic fields (density, velocities, T) for parity runs (not steady)."""
     rng = np.random.default_rng(seed)
     nr, nz = case["nr"], case["nz"]
     out = {}
     for k in ("uz", "ur", "uth"):
         out[k] = amp * rng.uniform(-1.0, 1.0, size=(nr, nz))
     out["T"] = case.get("T_ref", 0.0) + 0.5 * rng.uniform(-1.0, 1.0, size=(nr, nz))
+    out["rho"] = case.get("rho0", 1.0) + 0.01 * rng.uniform(-1.0, 1.0, size=(nr, nz))
     return out
 
 

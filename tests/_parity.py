@@ -14,7 +14,8 @@ def oracle_run(case, steps, fields=None):
     if fields is None:
         o.seed()
     else:
-        o.seed(fields.get("uz"), fields.get("ur"), fields.get("uth"), fields.get("T"))
+        o.seed(fields.get("uz"), fields.get("ur"), fields.get("uth"), fields.get("T"),
+               fields.get("rho"))
     o.step(steps)
     return o
 
@@ -29,7 +30,7 @@ def gpu_run(cases, steps, prec, fields=None, launch=None, graph=None):
         lat.set_graph_steps(graph)
     if fields is not None:
         packed = {}
-        for k in ("uz", "ur", "uth", "T"):
+        for k in ("uz", "ur", "uth", "T", "rho"):
             if all(k in f for f in fields):
                 packed[k] = torch.cat([torch.as_tensor(np.asarray(f[k]).reshape(-1))
                                        for f in fields])

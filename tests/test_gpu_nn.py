@@ -104,3 +104,36 @@ def test_adam_matches_oracle_step():
     N.adam_step(p2, gd, m, v, 1, 1e-3)
     ref = lbnn.flatten_params(p2, names)
     assert np.abs(got - ref).max() < 1e-6
+
+
+def test_to_fields_scale_offset_and_smoothing():
+    import torch
+    from paper_1003_0282_amd import lbnn
+    B, H, W, K = 2, 16, 32, 5
+    net = lbnn.Net(H, W, 8, K, WIDTHS, max_batch=B)
+    rng = np.random.default_rng(7)
+    y = rng.standard_normal((B, H, W, K)).astype(np.float32)
+    yd = torch.tensor(y, device="cuda")
+    sc, of = [0.5, 2.0, -1.0, 3.0, 0.25], [1.0, 0.0, 0.5, -2.0, 0.0]
+    for smooth in (False, True):
+        outs = [torch.empty(B * H * W, device="cuda") for _ in range(K)]
+        outs[2] = None
+        net.to_fields(yd, sc, of, outs, smooth=smooth)
+        torch.cuda.synchronize()
+        yy = y.astype(np.float64)
+        if smooth:  # (1, 2, 1)/4 along H and W, edge values repeated
+            p = np.pad(yy, ((0, 0), (1, 1), (0, 0), (0, 0)), mode="edge")
+            yy = 0.25 * p[:, :-2] + 0.5 * p[:, 1:-1] + 0.25 * p[:, 2:]
+            p = np.pad(yy, ((0, 0), (0, 0), (1, 1), (0, 0)), mode="edge")
+            yy = 0.25 * p[:, :, :-2] + 0.5 * p[:, :, 1:-1] + 0.25 * p[:, :, 2:]
+        for k in range(K):
+            if outs[k] is None:
+                continue
+            want = (yy[..., k] * sc[k] + of[k]).reshape(-1)
+            assert np.abs(outs[k].cpu().numpy() - want).max() < 1e-5 * (1 + np.abs(want).max())
+    # a pure checkerboard is removed by the filter
+    cb = np.fromfunction(lambda b, i, j, k: (-1.0) ** (i + j), (B, H, W, K)).astype(np.float32)
+    outs = [torch.empty(B * H * W, device="cuda") for _ in range(K)]
+    net.to_fields(torch.tensor(cb, device="cuda"), [1.0] * K, [0.0] * K, outs, smooth=True)
+    inner = outs[0].cpu().numpy().reshape(B, H, W)[:, 1:-1, 1:-1]
+    assert np.abs(inner).max() < 1e-6

@@ -186,15 +186,22 @@ def test_seed_roundtrip(orc):
                        T_ref=0.5)
     fl = W.random_fields(case, 5)
     o = O.Oracle(case)
-    o.seed(fl["uz"], fl["ur"], fl["uth"], fl["T"])
-    m = o.macros()
     ur = fl["ur"].copy(); ur[0] = 0
     uth = fl["uth"].copy(); uth[0] = 0
-    assert np.abs(m["uz"] - fl["uz"]).max() < 1e-15
-    assert np.abs(m["ur"] - ur).max() < 1e-15
-    assert np.abs(m["uth"] - uth).max() < 1e-15
-    assert np.abs(m["T"] - fl["T"]).max() < 1e-15
-    assert np.abs(m["rho"] - 1.0).max() < 1e-15
+    for rho in (None, fl["rho"]):
+        o.seed(fl["uz"], fl["ur"], fl["uth"], fl["T"], rho)
+        m = o.macros()
+        assert np.abs(m["uz"] - fl["uz"]).max() < 1e-15
+        assert np.abs(m["ur"] - ur).max() < 1e-15
+        assert np.abs(m["uth"] - uth).max() < 1e-15
+        assert np.abs(m["T"] - fl["T"]).max() < 1e-15
+        assert np.abs(m["rho"] - (1.0 if rho is None else rho)).max() < 2e-15
+        # summing Eq. (12): sum S = -rho u_r / r, so sum f^ = rho (1 + u_r / 2r)
+        f, _, _ = o.get_state()
+        r = np.arange(case["nr"], dtype=float)[:, None]
+        ir = np.where(r > 0, 1.0 / np.maximum(r, 1), 0.0)
+        want = m["rho"] * (1.0 + 0.5 * ur * ir)
+        assert np.abs(f.sum(0) - want).max() < 2e-15
 
 
 def test_streaming_is_permutation_periodic_walls(orc):
