@@ -95,6 +95,57 @@ __device__ inline void st(S* p, S v, int nt) {
     *p = v;
 }
 
+// Pull of one node (i, j) into registers; on an axis row the swirl
+// populations are replaced by the non-equilibrium extrapolation of row 1
+// (Sec. IV B), computed before the node's own pull so that the two
+// population sets are never live together.
+template <typename S, typename R, int F>
+__device__ inline void pull_node(const InstP& P, const PR<R>& p, const S* s, int i, int j,
+                                 bool pre, R* f, R* g, R* h) {
+  const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
+  R gn[4];
+  if ((F & F_SWIRL) && axis_row) {
+    R f1[9], g1[4], h1[4];
+    load_node<S, R, F>(P, s, i, 1, pre, f1, g1, h1);
+    const Mac<R> m1 = macros<R, F>(p, make_row<R, F>(p, 1), false, f1, g1, h1);
+    const R q = (R)0.25 * p.rho0 * m1.uth;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      gn[a] = g1[a] - q * ((R)1 + (R)2 * ((R)ez4(a) * m1.uz + (R)er4(a) * m1.ur));
+  }
+  load_node<S, R, F>(P, s, i, j, pre, f, g, h);
+  if ((F & F_SWIRL) && axis_row) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) g[a] = gn[a];
+  }
+}
+
+// Macros, collision and store of one pulled node.
+template <typename S, typename R, int F>
+__device__ inline void finish_node(const StepArgs<S>& A, const InstP& P, const PR<R>& p, int i,
+                                   int j, R* f, R* g, R* h) {
+  const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
+  const Row<R> rw = make_row<R, F>(p, j);
+  const Mac<R> m = macros<R, F>(p, rw, axis_row, f, g, h);
+  collide<R, F>(p, rw, m, f, g, h);
+  S* d = A.dst + P.off;
+  const int pl = P.plane;
+  const unsigned ob = (unsigned)nidx(P, j, i) * (unsigned)sizeof(S);
+#pragma unroll
+  for (int a = 0; a < 9; ++a) st(ptrb(d + a * pl, ob), (S)f[a], A.nt_store);
+  if (F & F_SWIRL) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) st(ptrb(d + (9 + a) * pl, ob), (S)g[a], A.nt_store);
+  }
+  if (F & F_THERMAL) {
+    const int hb = (F & F_SWIRL) ? 13 : 9;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) st(ptrb(d + (hb + a) * pl, ob), (S)h[a], A.nt_store);
+  }
+  if (A.mode & MODE_SPEED)
+    A.spd[P.off_fld + (long long)j * P.nz + i] = (double)sqrt(m.uz * m.uz + m.ur * m.ur);
+}
+
 // One time step: pull (padded planes, no boundary tests), macros, collision,
 // store at the node's own slots of the other buffer.  The halo kernel then
 // completes the boundary rules for the next pull.
@@ -112,46 +163,9 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs<S> A) {
     const int i = T.z0 + li, j = T.r0 + lj;
     if (i >= P.nz || j >= P.nr) continue;
     const PR<R> p = make_pr<R>(P, t);
-    const S* s = A.src + P.off;
-    const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
-    R gn[4];
-    if ((F & F_SWIRL) && axis_row) {
-      // non-equilibrium extrapolation of g from row 1 (Sec. IV B), done before
-      // the node's own pull so that the two population sets are never live
-      // together
-      R f1[9], g1[4], h1[4];
-      load_node<S, R, F>(P, s, i, 1, pre, f1, g1, h1);
-      const Mac<R> m1 = macros<R, F>(p, make_row<R, F>(p, 1), false, f1, g1, h1);
-      const R q = (R)0.25 * p.rho0 * m1.uth;
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-        gn[a] = g1[a] - q * ((R)1 + (R)2 * ((R)ez4(a) * m1.uz + (R)er4(a) * m1.ur));
-    }
     R f[9], g[4], h[4];
-    load_node<S, R, F>(P, s, i, j, pre, f, g, h);
-    if ((F & F_SWIRL) && axis_row) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a) g[a] = gn[a];
-    }
-    const Row<R> rw = make_row<R, F>(p, j);
-    const Mac<R> m = macros<R, F>(p, rw, axis_row, f, g, h);
-    collide<R, F>(p, rw, m, f, g, h);
-    S* d = A.dst + P.off;
-    const int pl = P.plane;
-    const unsigned ob = (unsigned)nidx(P, j, i) * (unsigned)sizeof(S);
-#pragma unroll
-    for (int a = 0; a < 9; ++a) st(ptrb(d + a * pl, ob), (S)f[a], A.nt_store);
-    if (F & F_SWIRL) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a) st(ptrb(d + (9 + a) * pl, ob), (S)g[a], A.nt_store);
-    }
-    if (F & F_THERMAL) {
-      const int hb = (F & F_SWIRL) ? 13 : 9;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) st(ptrb(d + (hb + a) * pl, ob), (S)h[a], A.nt_store);
-    }
-    if (A.mode & MODE_SPEED)
-      A.spd[P.off_fld + (long long)j * P.nz + i] = (double)sqrt(m.uz * m.uz + m.ur * m.ur);
+    pull_node<S, R, F>(P, p, A.src + P.off, i, j, pre, f, g, h);
+    finish_node<S, R, F>(A, P, p, i, j, f, g, h);
   }
 }
 
