@@ -92,6 +92,7 @@ typedef struct {
   int nz, nr;
   double r0;          /* r_j = r0 + j; r0 = 0 puts the axis on node row 0 */
   int swirl, thermal, cartesian;
+  int wet;            /* 1: wall sides are wet-node walls (see wet_substitute) */
   double tau, tau_g, tau_h; /* paper convention */
   double rho0;
   double a0, period, phase; /* axial force density a(t) */
@@ -279,6 +280,15 @@ void orc_node_collide(const orc_params* p, int j, int64_t t, const double* fh,
  * boundary it crossed; a z-end is checked before the radial sides. */
 typedef struct { int kind; double omega; int thermal; double T; } seg_t;
 
+typedef struct {
+  int in, jn;      /* inner neighbour */
+  int free;        /* free-slip segment */
+  double uz, ur;   /* wall velocity in the meridian plane */
+  double omega;    /* wall angular speed */
+  int thermal;
+  double T;
+} wet_rule_t;
+
 static seg_t zwall_segment(const orc_params* p, const orc_side* s, int j) {
   seg_t sg;
   if (s->r_split >= 0.0 && r_of(p, j) > s->r_split) {
@@ -432,10 +442,12 @@ static void gather(const orc_state* s, int i, int j, double* f, double* g,
 
 /* Populations at (i, j) ready for the macros: on the axis row the swirl
  * populations are replaced by the extrapolated ones. */
+static int wet_wall_rule(const orc_params* p, int i, int j, wet_rule_t* w);
+
 static void node_inputs(const orc_state* s, int i, int j, double* f, double* g,
                         double* h) {
   gather(s, i, j, f, g, h);
-  if (s->p.swirl && is_axis_row(&s->p, j)) {
+  if (s->p.swirl && is_axis_row(&s->p, j) && !wet_wall_rule(&s->p, i, j, NULL)) {
     double f1[9], g1[4], h1[4];
     gather(s, i, 1, f1, g1, h1);
     node_axis_g(&s->p, s->t, f1, g1, h1, g);
@@ -512,6 +524,96 @@ static void stream_all(orc_state* s) {
 
 /* n time steps t -> t + n: collide every node (Eqs. 12-17, 53-54), then
  * stream.  The speed |u| of each collided level is kept for Eq. (57). */
+/* ---- wet-node walls ----------------------------------------------------------
+ * The paper treats the walls of its rotating flows by non-equilibrium
+ * extrapolation (Sec. IV B, its Ref. 59): the wall passes through the
+ * outermost node row or column, and after every streaming step the state of
+ * such a wall node b is rebuilt from its inner neighbour n,
+ *     f^(b) = E(rho_n, u_w; b) + [f^(n) - E(rho_n, u_n; n)],
+ * with E = f_eq - S/2 the equilibrium of the f^ variables (Eqs. 6, 12; the
+ * source taken with the wall values at b), and likewise g with the wall
+ * value rho0 Omega r_b of rho0 u_th and h with the wall temperature (or T_n
+ * on an adiabatic wall), rho_n and u_n being the Eq. (16)-(17) macros of n.
+ * Eqs. (16)-(17) then return exactly (rho_n, u_w) at b.  n is one node inward along the wall normal; a
+ * node on a z-end and a radial wall takes the z-end's values and its diagonal
+ * inner neighbour.  A free-slip z-end segment is a wet node too, with wall
+ * velocity (0, u_r,n), u_th,n and T_n (zero normal velocity, no shear, no
+ * flux).  Wall nodes keep their own g on the axis row.                     */
+static int wet_wall_rule(const orc_params* p, int i, int j, wet_rule_t* w) {
+  if (!p->wet) return 0;
+  const orc_side* zs = NULL;
+  int dz = 0;
+  if (i == 0 && p->side[2].kind != ORC_PERIODIC) {
+    zs = &p->side[2];
+    dz = 1;
+  } else if (i == p->nz - 1 && p->side[3].kind != ORC_PERIODIC) {
+    zs = &p->side[3];
+    dz = -1;
+  }
+  int north = j == p->nr - 1 && p->side[1].kind == ORC_WALL;
+  int south = j == 0 && p->side[0].kind == ORC_WALL;
+  if (!zs && !north && !south) return 0;
+  if (!w) return 1;
+  w->in = i + dz;
+  w->jn = j + (north ? -1 : (south ? 1 : 0));
+  if (zs) {
+    seg_t sg = zwall_segment(p, zs, j);
+    w->free = sg.kind == ORC_FREESLIP;
+    w->uz = zs->uz; w->ur = zs->ur;
+    w->omega = sg.omega; w->thermal = sg.thermal; w->T = sg.T;
+  } else {
+    const orc_side* rs = &p->side[north ? 1 : 0];
+    w->free = 0;
+    w->uz = rs->uz; w->ur = rs->ur;
+    w->omega = rs->omega; w->thermal = rs->thermal; w->T = rs->T;
+  }
+  return 1;
+}
+
+static void wet_substitute(orc_state* s) {
+  const orc_params* p = &s->p;
+  if (!p->wet) return;
+  for (int j = 0; j < p->nr; ++j)
+    for (int i = 0; i < p->nz; ++i) {
+      wet_rule_t w;
+      if (!wet_wall_rule(p, i, j, &w)) continue;
+      double f[9], g[4], h[4], m[5], mb[5], e1[9], e2[9], S1[9], S2[9];
+      /* mass of b as streamed in (its links out of the domain bounce back),
+       * kept by the substitution so that no mass crosses the wall */
+      double s0b = 0.0;
+      for (int a = 0; a < 9; ++a) s0b += s->f[IDX(p, a, j, i)];
+      node_inputs(s, w.in, w.jn, f, g, h); /* n is never a wall node */
+      orc_node_macros(p, w.jn, s->t, f, g, h, m);
+      double uzw = w.free ? 0.0 : w.uz, urw = w.free ? m[2] : w.ur;
+      double uthw = w.free ? m[3] : w.omega * r_of(p, j);
+      if (is_axis_row(p, j)) uthw = 0.0;
+      double Tw = (w.thermal && !w.free) ? w.T : m[4];
+      /* the equilibrium of the f^ variables is f_eq - S/2 (seeding), so that
+       * Eqs. (16)-(17) at b return exactly (rho_n, u_w) */
+      /* sum of f_eq - S/2 is rho (1 + u_r / 2r) (sum of Eq. 12) */
+      mb[0] = s0b / (1.0 + 0.5 * urw * inv_r(p, j));
+      mb[1] = uzw; mb[2] = urw; mb[3] = uthw; mb[4] = Tw;
+      orc_feq9(mb[0], mb[1], mb[2], e1);
+      orc_node_source(p, j, s->t, mb, e1, S1);
+      orc_feq9(m[0], m[1], m[2], e2);
+      orc_node_source(p, w.jn, s->t, m, e2, S2);
+      for (int a = 0; a < 9; ++a)
+        s->f[IDX(p, a, j, i)] = f[a] + (e1[a] - 0.5 * S1[a]) - (e2[a] - 0.5 * S2[a]);
+      if (p->swirl) {
+        double q1[4], q2[4];
+        orc_geq4(p->rho0, uthw, uzw, urw, q1);
+        orc_geq4(p->rho0, m[3], m[1], m[2], q2);
+        for (int a = 0; a < 4; ++a) s->g[IDX(p, a, j, i)] = g[a] + q1[a] - q2[a];
+      }
+      if (p->thermal) {
+        double q1[4], q2[4];
+        orc_heq4(Tw, uzw, urw, q1);
+        orc_heq4(m[4], m[1], m[2], q2);
+        for (int a = 0; a < 4; ++a) s->h[IDX(p, a, j, i)] = h[a] + q1[a] - q2[a];
+      }
+    }
+}
+
 void orc_step(orc_state* s, int64_t n) {
   const orc_params* p = &s->p;
   for (int64_t k = 0; k < n; ++k) {
@@ -531,6 +633,7 @@ void orc_step(orc_state* s, int64_t n) {
     s->have_spd = 1;
     stream_all(s);
     s->t += 1;
+    wet_substitute(s);
   }
 }
 

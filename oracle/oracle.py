@@ -47,6 +47,7 @@ class _Params(C.Structure):
         ("swirl", C.c_int),
         ("thermal", C.c_int),
         ("cartesian", C.c_int),
+        ("wet", C.c_int),
         ("tau", C.c_double),
         ("tau_g", C.c_double),
         ("tau_h", C.c_double),
@@ -138,6 +139,7 @@ def params(case: dict) -> _Params:
     p.swirl = int(bool(case.get("swirl", False)))
     p.thermal = int(bool(case.get("thermal", False)))
     p.cartesian = int(bool(case.get("cartesian", False)))
+    p.wet = int(bool(case.get("wet", False)))
     tau = float(case["tau"]) - 0.5
     p.tau = tau
     tg = float(case.get("tau_g", 0.0))

@@ -94,15 +94,17 @@ def womersley_paper(nz: int = 40) -> dict:
                      name="womersley_paper")
 
 
-def cavity(nr: int, nz: int, Re: float, U_t: float = 0.1) -> dict:
+def cavity(nr: int, nz: int, Re: float, U_t: float = 0.1, wet: bool = False) -> dict:
     """Closed cylinder with a rotating top lid (Sec. IV B): Re = Omega R^2 / nu,
-    lid speed U_t = Omega R, nu = U_t R / Re, tau_s = 3 nu + 1/2."""
-    R = nr - 0.5
+    lid speed U_t = Omega R, nu = U_t R / Re, tau_s = 3 nu + 1/2.  R = nr - 1/2
+    with halfway walls, nr - 1 with wet-node walls."""
+    R = nr - (1.0 if wet else 0.5)
     nu = U_t * R / Re
     omega = U_t / R
     return base_case(nz, nr, 3.0 * nu + 0.5, swirl=True, south=axis(), north=wall(),
-                     west=wall(), east=wall(omega=omega),
-                     name="cavity_%dx%d_Re%g" % (nz, nr, Re), Re=float(Re))
+                     west=wall(), east=wall(omega=omega), wet=bool(wet),
+                     name="cavity_%dx%d_Re%g%s" % (nz, nr, Re, "_wet" if wet else ""),
+                     Re=float(Re))
 
 
 def cavity_paper(Re: float = 990.0, nr: int = 100, nz: int = 150) -> dict:
@@ -135,16 +137,17 @@ def batch_cavities(n: int = 256, seed: int = 0, nr_lo: int = 64, nr_hi: int = 51
 
 
 def melt(Re_c: float, Re_x: float, Gr: float, nr: int = 128, nz: int = 256,
-         nu: float = 0.0125, Pr: float = 0.05, beta: float = 0.4) -> dict:
+         nu: float = 0.0125, Pr: float = 0.05, beta: float = 0.4, wet: bool = False) -> dict:
     """Rotating crystal / crucible melt with buoyancy (swirl + temperature).
 
-    Crucible of radius R_c = nr - 1/2 rotating at Omega_c = Re_c nu / R_c^2
-    (side wall at T = 1, bottom adiabatic); crystal disk r <= beta R_c on the
-    top rotating at Omega_x = Re_x nu / R_c^2 at T = 0; free, adiabatic surface
-    outside the crystal; Boussinesq buoyancy with g beta = Gr nu^2 / R_c^3
-    (unit temperature difference), T_ref = 1/2.  The D2Q4 temperature field
-    has diffusivity kappa = nu / Pr = tau_h / 2 (paper-convention tau_h)."""
-    Rc = nr - 0.5
+    Crucible of radius R_c (nr - 1/2 with halfway walls, nr - 1 with wet-node
+    walls) rotating at Omega_c = Re_c nu / R_c^2 (side wall at T = 1, bottom
+    adiabatic); crystal disk r <= beta R_c on the top rotating at
+    Omega_x = Re_x nu / R_c^2 at T = 0; free, adiabatic surface outside the
+    crystal; Boussinesq buoyancy with g beta = Gr nu^2 / R_c^3 (unit
+    temperature difference), T_ref = 1/2.  The D2Q4 temperature field has
+    diffusivity kappa = nu / Pr = tau_h / 2 (paper-convention tau_h)."""
+    Rc = nr - (1.0 if wet else 0.5)
     om_c = Re_c * nu / Rc ** 2
     om_x = Re_x * nu / Rc ** 2
     kappa = nu / Pr
@@ -152,13 +155,14 @@ def melt(Re_c: float, Re_x: float, Gr: float, nr: int = 128, nz: int = 256,
     return base_case(nz, nr, 3.0 * nu + 0.5, swirl=True, thermal=True,
                      tau_h=2.0 * kappa + 0.5, gbeta=Gr * nu * nu / Rc ** 3, T_ref=0.5,
                      south=axis(), north=wall(omega=om_c, thermal=1, T=1.0),
-                     west=wall(omega=om_c), east=top,
-                     name="melt_Rec%.0f_Rex%.0f_Gr%.0f" % (Re_c, Re_x, Gr),
+                     west=wall(omega=om_c), east=top, wet=bool(wet),
+                     name="melt_Rec%.0f_Rex%.0f_Gr%.0f%s" % (Re_c, Re_x, Gr, "_wet" if wet else ""),
                      Re_c=float(Re_c), Re_x=float(Re_x), Gr=float(Gr))
 
 
 def melt_set(n: int, seed: int, nr: int = 128, nz: int = 256, re_max: float = 1000.0,
-             signed: bool = False, gr_range=(1e3, 1e5), nu: float = 0.0125) -> list[dict]:
+             signed: bool = False, gr_range=(1e3, 1e5), nu: float = 0.0125,
+             wet: bool = False) -> list[dict]:
     """Seeded melt instances: Re_c, Re_x ~ U[0, re_max] (with random signs when
     signed, i.e. counter-rotation allowed), Gr log-uniform in gr_range."""
     rng = np.random.default_rng(seed)
@@ -168,7 +172,7 @@ def melt_set(n: int, seed: int, nr: int = 128, nz: int = 256, re_max: float = 10
         rc = rng.uniform(0, re_max) * (rng.choice([-1.0, 1.0]) if signed else 1.0)
         rx = rng.uniform(0, re_max) * (rng.choice([-1.0, 1.0]) if signed else 1.0)
         gr = 10.0 ** rng.uniform(lo, hi)
-        out.append(melt(rc, rx, gr, nr=nr, nz=nz, nu=nu))
+        out.append(melt(rc, rx, gr, nr=nr, nz=nz, nu=nu, wet=wet))
     return out
 
 

@@ -1,0 +1,126 @@
+"""Pins of the oracle's wet-node walls (non-equilibrium extrapolation, the
+wall treatment the paper uses for its rotating flows, Sec. IV B).  The wall
+passes through the outermost node row, so a pipe with nr rows has radius
+R = nr - 1 and an annulus spans r0 .. r0 + nr - 1.  Closed forms: Eq. (55)
+parabola, circular Couette u_th = A r + B / r, coaxial conduction
+T = a + b ln r; invariants: wall nodes carry the wall values exactly, no mass
+crosses a wet wall (planar box), and a rotating-lid cylinder reaches the
+Eq. (57) tolerance of the paper."""
+import numpy as np
+
+from paper_1003_0282_amd import workloads as W
+
+
+def _run(case, steps):
+    from oracle import oracle as O
+    o = O.Oracle(case)
+    o.seed()
+    o.step(steps)
+    return o, o.macros()
+
+
+def test_wet_hagen_poiseuille_second_order(orc):
+    errs = []
+    for nr in (12, 24):
+        a, tau_s = 1e-6, 0.8
+        nu = (tau_s - 0.5) / 3.0
+        R = nr - 1.0
+        o, m = _run(W.base_case(4, nr, tau_s, a0=a, wet=True), int(12 * R * R / nu))
+        r = np.arange(nr)
+        ua = a * (R * R - r * r) / (4.0 * nu)
+        uz = m["uz"][:, 0]
+        assert abs(uz[-1]) < 1e-15          # the wall node holds u_w = 0
+        assert np.abs(m["ur"]).max() < 1e-15
+        errs.append(np.abs(uz - ua).max() / ua.max())
+    assert errs[1] < 1e-2
+    assert np.log2(errs[0] / errs[1]) > 1.3
+
+
+def test_wet_circular_couette(orc):
+    """Inner cylinder at r0 turning, outer at rest: u_th = A r + B / r, no
+    radial flow (so no mass source), error falling under refinement."""
+    errs = []
+    for nr in (9, 17):
+        r0 = (nr - 1) / 2.0
+        Ri, Ro = r0, r0 + nr - 1
+        Oi = 0.01 / Ri
+        case = W.base_case(4, nr, 0.8, r0=r0, swirl=True, wet=True, south=W.wall(omega=Oi),
+                           north=W.wall())
+        o, m = _run(case, 30000 if nr == 9 else 80000)
+        r = r0 + np.arange(nr)
+        A = -Oi * Ri ** 2 / (Ro ** 2 - Ri ** 2)
+        B = Oi * Ri ** 2 * Ro ** 2 / (Ro ** 2 - Ri ** 2)
+        ua = A * r + B / r
+        assert abs(m["uth"][0, 0] - Oi * Ri) < 1e-15 and abs(m["uth"][-1, 0]) < 1e-15
+        assert np.abs(m["ur"]).max() < 1e-12
+        errs.append(np.abs(m["uth"][:, 0] - ua).max() / ua.max())
+    assert errs[1] < 1e-2
+    assert np.log2(errs[0] / errs[1]) > 1.3
+
+
+def test_wet_coaxial_conduction(orc):
+    errs = []
+    for nr in (9, 17):
+        r0 = (nr - 1) / 2.0
+        Ri, Ro = r0, r0 + nr - 1
+        case = W.base_case(4, nr, 0.8, r0=r0, thermal=True, tau_h=1.1, T_ref=0.5, wet=True,
+                           south=W.wall(thermal=1, T=1.0), north=W.wall(thermal=1, T=0.0))
+        o, m = _run(case, 8000 if nr == 9 else 30000)
+        r = r0 + np.arange(nr)
+        Ta = np.log(Ro / r) / np.log(Ro / Ri)
+        assert abs(m["T"][0, 0] - 1.0) < 1e-14 and abs(m["T"][-1, 0]) < 1e-14
+        errs.append(np.abs(m["T"][:, 0] - Ta).max())
+    assert errs[1] < 2e-3
+    assert np.log2(errs[0] / errs[1]) > 1.3
+
+
+def test_wet_wall_nodes_take_wall_values(orc):
+    """Crystal / crucible melt: after streaming, every wall node carries its
+    side's velocity, u_th = Omega r and (fixed-temperature walls) T; the
+    free-surface nodes have u_z = 0."""
+    case = W.melt(300.0, 500.0, 2e4, nr=16, nz=24, wet=True)
+    o, m = _run(case, 400)
+    nr, nz = case["nr"], case["nz"]
+    r = np.arange(nr, dtype=float)
+    om_c, top = case["north"]["omega"], case["east"]
+    side = m["uz"][-1, 1:-1], m["ur"][-1, 1:-1]  # corners take the z-end rules
+    assert np.abs(side[0]).max() < 1e-15 and np.abs(side[1]).max() < 1e-15
+    assert np.abs(m["uth"][-1, 1:-1] - om_c * (nr - 1)).max() < 1e-15
+    assert np.abs(m["T"][-1, 1:-1] - 1.0).max() < 1e-14       # crucible side wall
+    crystal = r <= top["r_split"]
+    assert np.abs(m["uz"][:, -1]).max() < 1e-15             # crystal and free surface
+    assert np.abs(m["uth"][crystal, -1] - top["omega"] * r[crystal]).max() < 1e-15
+    assert np.abs(m["T"][crystal, -1]).max() < 1e-14
+    assert np.abs(m["uth"][1:, 0] - om_c * r[1:]).max() < 1e-15  # rotating bottom
+
+
+def test_wet_walls_keep_mass_planar(orc):
+    """Planar (Cartesian) closed box with a sliding wall: the wall nodes keep
+    the mass they stream in, so the total mass is constant."""
+    from oracle import oracle as O
+    case = W.base_case(20, 14, 0.7, r0=1.0, cartesian=True, wet=True, south=W.wall(),
+                       north=W.wall(uz=0.05), west=W.wall(), east=W.wall())
+    o = O.Oracle(case)
+    o.seed()
+    m0 = o.get_state()[0].sum()
+    o.step(500)
+    m = o.macros()
+    assert abs(o.get_state()[0].sum() - m0) < 1e-11 * m0
+    assert np.abs(m["uz"][-1, 1:-1] - 0.05).max() < 1e-15
+
+
+def test_wet_melt_reaches_paper_tolerance(orc):
+    """A small crystal / crucible melt (rotation and buoyancy, Sec. IV B-C
+    geometry) reaches the paper's Eq. (57) criterion of 1e-8 from rest with
+    wet-node walls."""
+    from oracle import oracle as O
+    case = W.melt_set(1, 1, nr=32, nz=64, re_max=250.0, wet=True)[0]
+    o = O.Oracle(case)
+    o.seed()
+    res = 1.0
+    for _ in range(25):
+        o.step(2000)
+        res = o.residual()
+        if res < 1e-8:
+            break
+    assert 0 <= res < 1e-8, res
