@@ -67,7 +67,15 @@ enum {
  * FP32_FAST: stored and computed in float.  Fields passed to lbaxi_seed and
  * returned by lbaxi_macros are double for FP64 and float otherwise. */
 enum { LBAXI_FP64 = 0, LBAXI_FP32 = 1, LBAXI_FP32_FAST = 2 };
-enum { LBAXI_SWIRL = 1u, LBAXI_THERMAL = 2u, LBAXI_CARTESIAN = 4u };
+/* Field set and wall model bits of lbaxi_desc.fields.  LBAXI_WET_WALLS puts
+ * every wall side (radial walls and z-end wall / free-slip segments) through
+ * the outermost node row or column and rebuilds those nodes after each step
+ * by non-equilibrium extrapolation from their inner neighbour, the paper's
+ * wall treatment of its rotating flows (Sec. IV B); without it walls are
+ * halfway links half a spacing outside the last node.  The wall node keeps
+ * the mass it streamed in (no mass crosses the wall); its velocity, u_theta
+ * and T (fixed-temperature walls) take the wall values.  Needs nz, nr >= 3. */
+enum { LBAXI_SWIRL = 1u, LBAXI_THERMAL = 2u, LBAXI_CARTESIAN = 4u, LBAXI_WET_WALLS = 8u };
 enum {
   LBAXI_SIDE_AXIS = 0,     /* south side only, r0 = 0: specular axis */
   LBAXI_SIDE_WALL = 1,     /* halfway bounce-back wall */
@@ -99,7 +107,7 @@ typedef struct {
   int32_t nz, nr;   /* nodes along z and r, each >= 2 */
   double r0;        /* radius of node row 0; 0 with an axis south side */
   int32_t prec;     /* LBAXI_FP64 / _FP32 / _FP32_FAST (same for a whole batch) */
-  uint32_t fields;  /* LBAXI_SWIRL | LBAXI_THERMAL | LBAXI_CARTESIAN */
+  uint32_t fields;  /* LBAXI_SWIRL | LBAXI_THERMAL | LBAXI_CARTESIAN | LBAXI_WET_WALLS */
   double tau;       /* tau_s of f */
   double tau_g;     /* tau_s of g, 0 -> paper default */
   double tau_h;     /* tau_s of h, 0 -> tau */

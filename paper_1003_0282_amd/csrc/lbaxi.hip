@@ -42,11 +42,15 @@ __device__ inline T cload(const T* p) {
   static_assert(sizeof(T) % 4 == 0, "word-sized structs only");
   typedef const __attribute__((address_space(4))) int* cptr;
   const cptr q = (cptr)p;
-  T v;
-  int* w = reinterpret_cast<int*>(&v);
+  // the words become the struct through a union (no type-punned pointer)
+  union U {
+    int w[sizeof(T) / 4];
+    T v;
+    __device__ U() {}
+  } u;
 #pragma unroll
-  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) w[k] = q[k];
-  return v;
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) u.w[k] = q[k];
+  return u.v;
 }
 
 // Tiles handled by this workgroup.  With xcd_aware the grid is split into 8
@@ -100,9 +104,9 @@ __device__ inline void st(S* p, S v, int nt) {
 // (Sec. IV B), computed before the node's own pull so that the two
 // population sets are never live together.
 template <typename S, typename R, int F>
-__device__ inline void pull_node(const InstP& P, const PR<R>& p, const S* s, int i, int j,
-                                 bool pre, R* f, R* g, R* h) {
-  const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
+__device__ inline void pull_plain(const InstP& P, const PR<R>& p, const S* s, int i, int j,
+                                  bool pre, R* f, R* g, R* h, bool axis_g = true) {
+  const bool axis_row = axis_g && (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
   R gn[4];
   if ((F & F_SWIRL) && axis_row) {
     R f1[9], g1[4], h1[4];
@@ -117,6 +121,119 @@ __device__ inline void pull_node(const InstP& P, const PR<R>& p, const S* s, int
   if ((F & F_SWIRL) && axis_row) {
 #pragma unroll
     for (int a = 0; a < 4; ++a) g[a] = gn[a];
+  }
+}
+
+// ---- wet-node walls ------------------------------------------------------------
+// The paper treats the walls of its rotating flows by non-equilibrium
+// extrapolation (Sec. IV B, its Ref. 59).  With LBAXI_WET_WALLS the wall runs
+// through the outermost node row / column of every wall side; after each
+// streaming step the state of a wall node b is rebuilt from its inner
+// neighbour n:
+//   f^(b) = E(rho_b, u_w; b) + [f^(n) - E(rho_n, u_n; n)],  E = f_eq - S/2,
+//   g(b)  = g_eq(rho0 u_th,w, u_w) + [g(n) - g_eq(n)],  h likewise with T_w,
+// (rho_n, u_n) being n's macros (Eqs. 16-17), E the equilibrium of the f^
+// variables (Eqs. 6, 12 with the wall values at b), and rho_b chosen so that
+// b keeps the mass it streamed in (its links out of the domain bounce back):
+// sum E(rho, u) = rho (1 + u_r / 2r).  A node on a z-end and a radial wall
+// takes the z-end's values and its diagonal inner neighbour; a free-slip
+// segment is a wet node with u_w = (0, u_r,n), u_th,n and T_n.  Wall nodes
+// keep their own g on the axis row.
+struct WetRule {
+  int in, jn, free_, thermal;
+  double uz, ur, omega, T;
+};
+
+// The side of a wall node is chosen at run time; its parameters are read
+// from the lattice's parameter block in memory (Pg) rather than from the
+// register copy P, which a runtime member choice would push to scratch.
+__device__ inline bool wet_rule(const InstP& P, const InstP* Pg, int i, int j, WetRule* w) {
+  if (!P.wet) return false;
+  const bool west = i == 0 && P.side[WEST].kind != SIDE_PERIODIC;
+  const bool east = !west && i == P.nz - 1 && P.side[EAST].kind != SIDE_PERIODIC;
+  const bool north = j == P.nr - 1 && P.side[NORTH].kind == SIDE_WALL;
+  const bool south = j == 0 && P.side[SOUTH].kind == SIDE_WALL;
+  if (!west && !east && !north && !south) return false;
+  if (!w) return true;
+  w->in = i + (west ? 1 : (east ? -1 : 0));
+  w->jn = j + (north ? -1 : (south ? 1 : 0));
+  const int side = west ? WEST : (east ? EAST : (north ? NORTH : SOUTH));
+  const SideP Q = cload(&Pg->side[side]);
+  if (west || east) {
+    int kind;
+    zseg(P, Q, j, kind, w->omega, w->thermal, w->T);
+    w->free_ = kind == SIDE_FREESLIP;
+  } else {
+    w->free_ = 0;
+    w->omega = Q.omega;
+    w->thermal = Q.thermal;
+    w->T = Q.T;
+  }
+  w->uz = Q.uz;
+  w->ur = Q.ur;
+  return true;
+}
+
+// E_a = f_eq - S/2 of direction a in deviation form (f_eq = w (drho + rho P),
+// S = w (1 + P) [3 (e - u).F - rho u_r / r]).
+template <typename R>
+__device__ inline R eq_hat(int a, R drho, R rho, R uz, R ur, R Fz, R Fr, R ir) {
+  const R ez = (R)ez9(a), er = (R)er9(a), w = (R)w9(a);
+  const R eu = ez * uz + er * ur;
+  const R Pa = (R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * (uz * uz + ur * ur);
+  const R Sa = w * ((R)1 + Pa) * ((R)3 * ((ez - uz) * Fz + (er - ur) * Fr) - rho * ur * ir);
+  return w * (drho + rho * Pa) - (R)0.5 * Sa;
+}
+
+template <typename S, typename R, int F>
+__device__ inline void wall_state(const InstP& P, const PR<R>& p, const S* s, int i, int j,
+                                  const WetRule& w, R* f, R* g, R* h) {
+  R s0d;
+  {
+    R fo[9], go[4], ho[4];
+    load_node<S, R, F>(P, s, i, j, false, fo, go, ho);
+    s0d = ((fo[0] + fo[1]) + (fo[2] + fo[3])) + ((fo[4] + fo[5]) + (fo[6] + fo[7])) + fo[8];
+  }
+  R fn[9], gn[4], hn[4];
+  pull_plain<S, R, F>(P, p, s, w.in, w.jn, false, fn, gn, hn);
+  const bool axis_n = (w.jn == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
+  const bool axis_b = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
+  const Row<R> rn = make_row<R, F>(p, w.jn);
+  const Row<R> rb = make_row<R, F>(p, j);
+  const Mac<R> m = macros<R, F>(p, rn, axis_n, fn, gn, hn);
+  const R uzw = w.free_ ? (R)0 : (R)w.uz;
+  const R urw = w.free_ ? m.ur : (R)w.ur;
+  R uthw = w.free_ ? m.uth : (R)(w.omega * (P.r0 + (double)j));
+  if (axis_b) uthw = (R)0;
+  const R dTw = (w.thermal && !w.free_) ? (R)(w.T - P.T_ref) : m.dT;
+  const R x = (R)0.5 * urw * rb.ir;
+  const R drhob = (s0d - p.rho0 * x) * rcp((R)1 + x);
+  const R rhob = p.rho0 + drhob;
+  R Fzb = p.a_t;
+  if (F & F_THERMAL) Fzb += p.rho0 * p.gbeta * dTw;
+  R Frb = -(R)2 * p.mu0 * urw * rb.ir2;
+  if (F & F_SWIRL) Frb += p.rho0 * uthw * uthw * rb.ir;
+#pragma unroll
+  for (int a = 0; a < 9; ++a)
+    f[a] = fn[a] + eq_hat<R>(a, drhob, rhob, uzw, urw, Fzb, Frb, rb.ir) -
+           eq_hat<R>(a, m.drho, m.rho, m.uz, m.ur, m.Fz, m.Fr, rn.ir);
+  if (F & F_SWIRL) {
+    const R qb = (R)0.25 * p.rho0 * uthw, qn = (R)0.25 * p.rho0 * m.uth;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const R ez = (R)ez4(a), er = (R)er4(a);
+      g[a] = gn[a] + qb * ((R)1 + (R)2 * (ez * uzw + er * urw)) -
+             qn * ((R)1 + (R)2 * (ez * m.uz + er * m.ur));
+    }
+  }
+  if (F & F_THERMAL) {
+    const R Tb = p.T_ref + dTw, Tn = p.T_ref + m.dT;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const R ez = (R)ez4(a), er = (R)er4(a);
+      h[a] = hn[a] + (R)0.25 * (Tb * ((R)1 + (R)2 * (ez * uzw + er * urw)) -
+                                Tn * ((R)1 + (R)2 * (ez * m.uz + er * m.ur)));
+    }
   }
 }
 
@@ -146,6 +263,19 @@ __device__ inline void finish_node(const StepArgs<S>& A, const InstP& P, const P
     A.spd[P.off_fld + (long long)j * P.nz + i] = (double)sqrt(m.uz * m.uz + m.ur * m.ur);
 }
 
+// Boundary node number p of a lattice: row 0, row nr-1, then columns 0 and
+// nz-1 without their corners.
+__device__ inline void perimeter_node(const InstP& P, int p, int& i, int& j) {
+  const int nz = P.nz, nr = P.nr;
+  if (p < nz) { i = p; j = 0; return; }
+  p -= nz;
+  if (p < nz) { i = p; j = nr - 1; return; }
+  p -= nz;
+  if (p < nr - 2) { i = 0; j = 1 + p; return; }
+  p -= nr - 2;
+  i = nz - 1; j = 1 + p;
+}
+
 // One time step: pull (padded planes, no boundary tests), macros, collision,
 // store at the node's own slots of the other buffer.  The halo kernel then
 // completes the boundary rules for the next pull.
@@ -162,24 +292,39 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs<S> A) {
     const InstP P = cload(A.ip + T.inst);
     const int i = T.z0 + li, j = T.r0 + lj;
     if (i >= P.nz || j >= P.nr) continue;
+    // wet wall nodes are rebuilt by k_wall, except on the first step after
+    // seeding, where they collide their seeded state like any node
+    const bool wall = P.wet && wet_rule(P, nullptr, i, j, nullptr);
+    if (wall && !pre) continue;
     const PR<R> p = make_pr<R>(P, t);
     R f[9], g[4], h[4];
-    pull_node<S, R, F>(P, p, A.src + P.off, i, j, pre, f, g, h);
+    pull_plain<S, R, F>(P, p, A.src + P.off, i, j, pre, f, g, h, !wall);
     finish_node<S, R, F>(A, P, p, i, j, f, g, h);
   }
 }
 
-// Boundary node number p of a lattice: row 0, row nr-1, then columns 0 and
-// nz-1 without their corners.
-__device__ inline void perimeter_node(const InstP& P, int p, int& i, int& j) {
-  const int nz = P.nz, nr = P.nr;
-  if (p < nz) { i = p; j = 0; return; }
-  p -= nz;
-  if (p < nz) { i = p; j = nr - 1; return; }
-  p -= nz;
-  if (p < nr - 2) { i = 0; j = 1 + p; return; }
-  p -= nr - 2;
-  i = nz - 1; j = 1 + p;
+// Wet wall nodes of every running lattice after a streaming step (one
+// thread per perimeter node, tiles of the halo list): rebuild from the inner
+// neighbour, then macros, collision and store like k_step.  Reads the same
+// source buffer as k_step and writes other nodes of the same destination.
+template <typename S, typename R, int F>
+__global__ void __launch_bounds__(256) k_wall(StepArgs<S> A) {
+  const int ti = blockIdx.x;
+  if (ti >= *A.ntiles) return;
+  const Tile T = cload(A.tiles + ti);
+  const InstP P = cload(A.ip + T.inst);
+  if (!P.wet) return;
+  const int q = T.z0 + threadIdx.x;
+  if (q >= 2 * P.nz + 2 * (P.nr - 2)) return;
+  int i, j;
+  perimeter_node(P, q, i, j);
+  WetRule w;
+  if (!wet_rule(P, A.ip + T.inst, i, j, &w)) return;
+  const long long t = A.tdev ? (*A.tdev + A.k) : A.t0;
+  const PR<R> p = make_pr<R>(P, t);
+  R f[9], g[4], h[4];
+  wall_state<S, R, F>(P, p, A.src + P.off, i, j, w, f, g, h);
+  finish_node<S, R, F>(A, P, p, i, j, f, g, h);
 }
 
 // Ghost-slot fill after a step: tiles here are {instance, first perimeter
@@ -255,12 +400,16 @@ __global__ void __launch_bounds__(1024) k_seed(const InstP* ip, const Tile* tile
 
 // Macros at the current level of each lattice (own buffer parity and time).
 template <typename S, typename R, int F>
-__device__ inline Mac<R> node_macros(const InstP& P, const InstDyn& D, const S* bufA,
-                                     const S* bufB, int i, int j) {
+__device__ inline Mac<R> node_macros(const InstP& P, const InstP* Pg, const InstDyn& D,
+                                     const S* bufA, const S* bufB, int i, int j) {
   const PR<R> p = make_pr<R>(P, D.t);
   const S* s = (D.cur ? bufB : bufA) + P.off;
   R f[9], g[4], h[4];
-  load_node<S, R, F>(P, s, i, j, D.pre != 0, f, g, h);
+  WetRule w;
+  if (P.wet && !D.pre && wet_rule(P, Pg, i, j, &w))
+    wall_state<S, R, F>(P, p, s, i, j, w, f, g, h);
+  else
+    load_node<S, R, F>(P, s, i, j, D.pre != 0, f, g, h);
   const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
   // on the axis u_th = 0 and g does not enter the macros of Eqs. (16)-(17)
   return macros<R, F>(p, make_row<R, F>(p, j), axis_row, f, g, h);
@@ -278,7 +427,7 @@ __global__ void __launch_bounds__(1024) k_macros(const InstP* ip, const InstDyn*
   const int tz = 1 << tzlog;
   const int i = Tl.z0 + (threadIdx.x & (tz - 1)), j = Tl.r0 + (threadIdx.x >> tzlog);
   if (i >= P.nz || j >= P.nr) return;
-  const Mac<R> m = node_macros<S, R, F>(P, dyn[Tl.inst], bufA, bufB, i, j);
+  const Mac<R> m = node_macros<S, R, F>(P, ip + Tl.inst, dyn[Tl.inst], bufA, bufB, i, j);
   const long long o = P.off_fld + (long long)j * P.nz + i;
   if (rho) rho[o] = (S)m.rho;
   if (uz) uz[o] = (S)m.uz;
@@ -309,7 +458,7 @@ __global__ void __launch_bounds__(1024) k_residual(const InstP* ip, const InstDy
   const int i = Tl.z0 + (threadIdx.x & (tz - 1)), j = Tl.r0 + (threadIdx.x >> tzlog);
   unsigned long long v = 0;
   if (i < P.nz && j < P.nr) {
-    const Mac<R> m = node_macros<S, R, F>(P, dyn[Tl.inst], bufA, bufB, i, j);
+    const Mac<R> m = node_macros<S, R, F>(P, ip + Tl.inst, dyn[Tl.inst], bufA, bufB, i, j);
     const double sp = (double)sqrt(m.uz * m.uz + m.ur * m.ur);
     v = key(sp - spd[P.off_fld + (long long)j * P.nz + i]);
   }
@@ -462,7 +611,9 @@ lbaxi_status validate(const lbaxi_desc& d, int k) {
     return bad(LBAXI_EINVAL, "lattice too large for 32-bit in-lattice offsets");
   if (d.prec != LBAXI_FP64 && d.prec != LBAXI_FP32 && d.prec != LBAXI_FP32_FAST)
     return bad(LBAXI_EINVAL, "bad prec");
-  if (d.fields & ~7u) return bad(LBAXI_EINVAL, "unknown field bits");
+  if (d.fields & ~15u) return bad(LBAXI_EINVAL, "unknown field bits");
+  if ((d.fields & LBAXI_WET_WALLS) && (d.nz < 3 || d.nr < 3))
+    return bad(LBAXI_EINVAL, "wet-node walls need nz and nr >= 3");
   if (!(d.rho0 > 0)) return bad(LBAXI_EINVAL, "rho0 must be positive");
   if (!(d.r0 >= 0)) return bad(LBAXI_EINVAL, "r0 must be >= 0");
   const lbaxi_side* sd[4] = {&d.south, &d.north, &d.west, &d.east};
@@ -513,6 +664,7 @@ InstP make_inst(const lbaxi_desc& d, long long off, long long off_fld) {
   P.c0 = row_lead(d);
   P.plane = (int)padded_plane(d);
   P.cart = (d.fields & LBAXI_CARTESIAN) ? 1 : 0;
+  P.wet = (d.fields & LBAXI_WET_WALLS) ? 1 : 0;
   P.r0 = d.r0;
   taus(d, P.tau, P.tau_g, P.tau_h);
   P.rho0 = d.rho0;
@@ -559,6 +711,7 @@ enum { LIST_ALL = 0, LIST_RUN = 1, LIST_HALO = 2 };
 struct lbaxi_s {
   int n = 0, prec = 0;
   unsigned fields = 0;
+  bool any_wet = false;  // some lattice has wet-node walls (k_wall runs)
   std::vector<lbaxi_desc> desc;
   std::vector<InstP> ip;
   hipStream_t stream = nullptr;
@@ -654,6 +807,8 @@ void* step_fn() { return reinterpret_cast<void*>(&k_step<S, R, F>); }
 template <typename S, typename R, int F>
 void* halo_fn() { return reinterpret_cast<void*>(&k_halo<S, F>); }
 template <typename S, typename R, int F>
+void* wall_fn() { return reinterpret_cast<void*>(&k_wall<S, R, F>); }
+template <typename S, typename R, int F>
 void* seed_fn() { return reinterpret_cast<void*>(&k_seed<S, R, F>); }
 template <typename S, typename R, int F>
 void* macros_fn() { return reinterpret_cast<void*>(&k_macros<S, R, F>); }
@@ -706,6 +861,18 @@ StepLaunch step_launch(lbaxi_t* h, int list, int from, long long t0, bool use_td
   return L;
 }
 
+// Wet-wall launch of the same step: the step's arguments over the
+// perimeter tiles of the running lattices.
+StepLaunch wall_launch(lbaxi_t* h, const StepLaunch& S) {
+  StepLaunch W = S;
+  W.fn = PICK(wall_fn, h->prec, h->fields);
+  W.block = 256;
+  W.grid = std::max(1, h->count[LIST_HALO]);
+  W.a.tiles = h->d_tiles[LIST_HALO];
+  W.a.ntiles = h->d_counts + LIST_HALO;
+  return W;
+}
+
 // Halo launch filling the ghost slots of buffer `buf` (0 = A, 1 = B).
 struct HaloLaunch {
   void* fn;
@@ -747,6 +914,11 @@ lbaxi_status launch_step(lbaxi_t* h, int mode) {
     HIPCHK(hipEventRecord(h->ev[h->ev_used + 1], h->stream));
     h->ev_used += 2;
   }
+  if (h->any_wet && !h->pre) {
+    StepLaunch Wl = wall_launch(h, L);
+    void* wargs[] = {&Wl.a};
+    HIPCHK(hipLaunchKernel(Wl.fn, dim3(Wl.grid), dim3(Wl.block), wargs, 0, h->stream));
+  }
   HaloLaunch H = halo_launch(h, h->cur ^ 1);
   void* hargs[] = {&H.ip, &H.tiles, &H.ntiles, &H.buf};
   HIPCHK(hipLaunchKernel(H.fn, dim3(H.grid), dim3(256), hargs, 0, h->stream));
@@ -785,6 +957,12 @@ lbaxi_status make_graph(lbaxi_t* h, int from) {
     void* args[] = {&L.a};
     add(L.fn, L.grid, L.block, args);
     if (st != LBAXI_OK) break;
+    if (h->any_wet) {
+      StepLaunch Wl = wall_launch(h, L);
+      void* wargs[] = {&Wl.a};
+      add(Wl.fn, Wl.grid, Wl.block, wargs);
+      if (st != LBAXI_OK) break;
+    }
     HaloLaunch H = halo_launch(h, src ^ 1);
     void* hargs[] = {&H.ip, &H.tiles, &H.ntiles, &H.buf};
     add(H.fn, H.grid, 256, hargs);
@@ -960,6 +1138,8 @@ lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace,
   h->desc.assign(descs, descs + n);
   h->prec = descs[0].prec;
   h->fields = descs[0].fields;
+  for (int k = 0; k < n; ++k)
+    if (descs[k].fields & LBAXI_WET_WALLS) h->any_wet = true;
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
   h->ws = static_cast<char*>(d_workspace);
   h->L = layout(h->desc);

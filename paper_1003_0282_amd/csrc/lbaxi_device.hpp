@@ -26,6 +26,7 @@ struct SideP {
 // Everything one lattice instance needs on the device (read once per tile).
 struct InstP {
   int nz, nr, cart;
+  int wet;    // wall sides are wet-node walls (wall through the outer node row)
   int pitch;  // row length of a padded plane (a multiple of 128 bytes)
   int c0;     // column of node i = 0 (128 bytes in; the ghost column is c0 - 1)
   int plane;  // (nr + 2) * pitch: elements per padded plane

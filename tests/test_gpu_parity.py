@@ -95,6 +95,18 @@ CASES = {
                                           east=W.split_wall(W.wall(omega=-2e-3, thermal=1, T=0.0),
                                                             W.freeslip(), 7.0),
                                           gbeta=1e-4, T_ref=0.5),
+    # wet-node walls (the wall through the outer node row)
+    "cavity_wet": lambda: W.cavity(37, 70, 400.0, wet=True),
+    "melt_wet": lambda: W.melt(-300.0, 500.0, 2e4, nr=29, nz=75, wet=True),
+    "pipe_wet": lambda: W.base_case(6, 21, 0.8, a0=2e-5, wet=True),
+    "annulus_wet": lambda: W.base_case(66, 19, 0.75, r0=5.0, wet=True, swirl=True, thermal=True,
+                                       south=W.wall(uz=1e-3, omega=1e-3, thermal=1, T=1.0),
+                                       north=W.wall(omega=-5e-4), west=W.wall(ur=2e-3),
+                                       east=W.split_wall(W.wall(thermal=1, T=0.2), W.freeslip(),
+                                                         12.0),
+                                       tau_h=0.9, gbeta=2e-4, T_ref=0.5),
+    "planar_wet": lambda: W.base_case(65, 10, 0.7, cartesian=True, wet=True, south=W.wall(),
+                                      east=W.wall(), west=W.wall(ur=1e-3), a0=2e-5),
 }
 
 
@@ -123,11 +135,28 @@ def test_fp32_fast_variant(name):
     assert max(e.values()) < 1e-4, e
 
 
-def test_first_step_from_seed():
+@pytest.mark.parametrize("name", ["melt", "melt_wet"])
+def test_first_step_from_seed(name):
     """One step from seeded random fields (own-slot read, then collision)."""
-    case = CASES["melt"]()
+    case = CASES[name]()
     _compare(case, 1, 0, _fields(case, 3), label="one step")
     _compare(case, 2, 0, _fields(case, 3), label="two steps")
+
+
+def test_wet_and_halfway_lattices_in_one_batch():
+    """A batch may mix the two wall models; each lattice matches the oracle."""
+    from _parity import errors
+    cases = [CASES["cavity_wet"](), CASES["cavity"](), CASES["melt_wet"]()]
+    cases[2] = dict(cases[2], thermal=False, gbeta=0.0)  # one field set per batch
+    cases[1] = dict(cases[1])
+    fields = [_fields(c, 30 + k) for k, c in enumerate(cases)]
+    lat = gpu_run(cases, 150, 0, fields)
+    ms = lat.macros_list()
+    for k, c in enumerate(cases):
+        o = oracle_run(c, 150, fields[k])
+        gm = {key: v.double().cpu().numpy() for key, v in ms[k].items()}
+        e, _ = errors(c, gm, o.macros())
+        assert max(e.values()) < 1e-10, (k, e)
 
 
 @pytest.mark.parametrize("launch", [(64, 1, 0, 0, 0), (128, 2, 0, 0, 1), (256, 4, 0, 0, 1),
