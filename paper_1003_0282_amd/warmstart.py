@@ -20,13 +20,14 @@ import json
 import math
 import os
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 
 from . import lbaxi as L
 from . import lbnn as N
 from . import workloads as W
+from .steady import Solve, solve  # noqa: F401  (re-exported for callers)
 
 C_IN, C_OUT = 8, 5
 WIDTHS = (32, 64, 128, 256)
@@ -43,10 +44,12 @@ def features(cases) -> np.ndarray:
     out = []
     for c in cases:
         nr, nz = int(c["nr"]), int(c["nz"])
-        Rc = nr - 0.5
+        wet = bool(c.get("wet"))
+        Rc = nr - (1.0 if wet else 0.5)   # wall through / half a spacing beyond the last row
         one = np.ones((nr, nz))
         r = np.arange(nr)[:, None] / Rc * one
-        z = (np.arange(nz)[None, :] + 0.5) / nz * one
+        zc = np.arange(nz)[None, :] / (nz - 1.0) if wet else (np.arange(nz)[None, :] + 0.5) / nz
+        z = zc * one
         rs = float(c["east"].get("r_split", -1.0))
         crystal = (np.arange(nr)[:, None] <= rs) * one
         rec, rex = c["Re_c"] / 1000.0, c["Re_x"] / 1000.0
@@ -80,101 +83,7 @@ def targets(fields: dict, sc: Scales, shape) -> np.ndarray:
     return np.stack([c.reshape(B, nr, nz) for c in ch], -1).astype(np.float32)
 
 
-# ---- solver runs ------------------------------------------------------------
-
-@dataclass
-class Solve:
-    status: np.ndarray
-    steps: np.ndarray
-    residual: np.ndarray
-    wall_s: float
-    fields: dict = field(default_factory=dict)  # packed numpy float64 per FIELDS
-    hist_steps: np.ndarray = None  # steps done at each residual check
-    hist_wall: np.ndarray = None   # seconds since the start (seeding included)
-    hist_res: np.ndarray = None    # [checks, n] Eq. (57) residual, NaN once frozen
-    hist_err: np.ndarray = None    # [checks, n] distance to a reference field (if given)
-
-    def first_crossing(self, tol: float):
-        """Per instance: index of the first check with residual <= tol, -1 if none."""
-        ok = np.nan_to_num(self.hist_res, nan=np.inf) <= tol
-        idx = np.argmax(ok, axis=0)
-        return np.where(ok.any(axis=0), idx, -1)
-
-    def first_within(self, err: float):
-        """Per instance: index of the first check from which the distance to
-        the reference stays <= err, -1 if never."""
-        bad = ~(np.nan_to_num(self.hist_err, nan=np.inf) <= err)
-        last_bad = len(bad) - 1 - np.argmax(bad[::-1], axis=0)
-        idx = np.where(bad.any(axis=0), last_bad + 1, 0)
-        return np.where(idx < len(bad), idx, -1)
-
-
-def _ref_distance(lat, ref, n):
-    """Per instance: max |u - u_ref| over the three velocity components,
-    divided by the instance's max |u_ref| (ref: packed device tensors)."""
-    import torch
-    m = lat.macros(("uz", "ur", "uth"))
-    out = np.zeros(n)
-    d = torch.stack([(m[k].double() - ref[k]).abs() for k in ("uz", "ur", "uth")]).amax(0)
-    a = torch.stack([ref[k].abs() for k in ("uz", "ur", "uth")]).amax(0)
-    for i in range(n):
-        sl = slice(int(lat.offsets[i]), int(lat.offsets[i + 1]))
-        out[i] = float(d[sl].max() / a[sl].max())
-    return out
-
-
-def solve(cases, init=None, tol=1e-8, max_steps=2_000_000, check_every=1000, budget_s=None,
-          prec=L.FP32, launch=None, log=None, tag="", log_every_s=15.0, ref=None) -> Solve:
-    """Run every case to the Eq. (57) tolerance (or max_steps) in one batched
-    handle, recording every instance's residual at each check; `init` is None
-    (from rest) or a dict of packed device fields for Lattices.seed; with
-    `ref` (packed float64 device velocity fields) the distance to it is
-    recorded at each check as well (outside the timed quantities' meaning:
-    the macros pass it needs is included in the wall clock)."""
-    import torch
-    lat = L.Lattices(cases, prec)
-    if launch is not None:
-        lat.set_launch(*launch)
-    n = len(cases)
-    steps = np.zeros(n, np.int64)
-    res = np.full(n, np.nan)
-    hs, hw, hr, he = [], [], [], []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lat.seed(**init) if init is not None else lat.seed()
-    done, last_log = 0, 0.0
-    status = np.zeros(n, np.int32)
-    while True:
-        r = lat.run(tol, check_every, check_every)
-        done += check_every
-        steps += r.steps
-        cur = np.where(r.steps > 0, r.residual, np.nan)
-        res = np.where(r.steps > 0, r.residual, res)
-        status = r.status
-        el = time.perf_counter() - t0
-        hs.append(done)
-        hw.append(el)
-        hr.append(cur)
-        if ref is not None:
-            he.append(_ref_distance(lat, ref, n))
-        live = int((status == L.RUNNING).sum() + (status == L.CAPPED).sum())
-        stop = live == 0 or done >= max_steps or (budget_s is not None and el > budget_s)
-        if log and (stop or el - last_log > log_every_s):
-            last_log = el
-            log("%s t=%d live %d/%d conv %d div %d res med %.2e max %.2e  %.1fs" % (
-                tag, done, live, n, int((status == L.CONVERGED).sum()),
-                int((status == L.DIVERGED).sum()), np.nanmedian(res), np.nanmax(res), el))
-        if stop:
-            break
-        lat.resume()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    m = lat.macros(FIELDS)
-    out = {k: m[k].double().cpu().numpy() for k in FIELDS}
-    lat.close()
-    return Solve(status.copy(), steps, res, wall, out, np.asarray(hs), np.asarray(hw),
-                 np.asarray(hr), np.asarray(he) if ref is not None else None)
-
+# ---- solver runs: see steady.py ---------------------------------------------
 
 # ---- network ------------------------------------------------------------------
 
@@ -296,7 +205,8 @@ def experiment(n_train=256, n_eval=16, nr=128, nz=256, re_max=1000.0, tol=1e-8,
                gen_steps=1_200_000, eval_steps=3_000_000, train_steps=3000, batch=8, lr=1e-3,
                gen_budget_s=None, train_budget_s=None, eval_budget_s=None, check_every=1000,
                seed_train=2, seed_eval=1, tols=(1e-6, 3e-7, 1e-7, 3e-8, 1e-8),
-               errs=(0.1, 0.03, 0.01, 0.003), out_dir=None, smooth_variants=(True,), log=print):
+               errs=(0.1, 0.03, 0.01, 0.003), out_dir=None, smooth_variants=(True,), wet=False,
+               log=print):
     """Generate steady training fields with the batched solver, train the
     network on them, then solve held-out cases from rest and from the
     prediction and compare the time to each residual tolerance."""
@@ -304,9 +214,9 @@ def experiment(n_train=256, n_eval=16, nr=128, nz=256, re_max=1000.0, tol=1e-8,
     res = {"config": dict(n_train=n_train, n_eval=n_eval, nr=nr, nz=nz, re_max=re_max, tol=tol,
                           gen_steps=gen_steps, eval_steps=eval_steps, train_steps=train_steps,
                           batch=batch, lr=lr, check_every=check_every, seed_train=seed_train,
-                          seed_eval=seed_eval)}
-    tr = W.melt_set(n_train, seed_train, nr=nr, nz=nz, re_max=re_max)
-    ev = W.melt_set(n_eval, seed_eval, nr=nr, nz=nz, re_max=re_max)
+                          seed_eval=seed_eval, wet=wet)}
+    tr = W.melt_set(n_train, seed_train, nr=nr, nz=nz, re_max=re_max, wet=wet)
+    ev = W.melt_set(n_eval, seed_eval, nr=nr, nz=nz, re_max=re_max, wet=wet)
     rho0, T_ref = tr[0]["rho0"], tr[0]["T_ref"]
 
     g = solve(tr, tol=tol, max_steps=gen_steps, check_every=check_every, budget_s=gen_budget_s,
@@ -399,11 +309,12 @@ def main(argv=None):
     ap.add_argument("--check-every", type=int, default=1000)
     ap.add_argument("--out", default=None)
     ap.add_argument("--variants", default="smooth", help="comma list of smooth,raw")
+    ap.add_argument("--wet", action="store_true", help="wet-node walls (the paper's treatment)")
     a = ap.parse_args(argv)
     variants = tuple(v == "smooth" for v in a.variants.split(","))
     r = experiment(a.n_train, a.n_eval, a.nr, a.nz, a.re_max, a.tol, a.gen_steps, a.eval_steps,
                    a.train_steps, a.batch, a.lr, a.gen_budget, a.train_budget, a.eval_budget,
-                   check_every=a.check_every, out_dir=a.out, smooth_variants=variants,
+                   check_every=a.check_every, out_dir=a.out, smooth_variants=variants, wet=a.wet,
                    log=lambda s: print(s, flush=True))
     print(json.dumps({k: r[k] for k in ("generate", "train")}))
     for tag in ("nn_smooth", "nn_raw"):
