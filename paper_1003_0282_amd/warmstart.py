@@ -206,10 +206,12 @@ def experiment(n_train=256, n_eval=16, nr=128, nz=256, re_max=1000.0, tol=1e-8,
                gen_budget_s=None, train_budget_s=None, eval_budget_s=None, check_every=1000,
                seed_train=2, seed_eval=1, tols=(1e-6, 3e-7, 1e-7, 3e-8, 1e-8),
                errs=(0.1, 0.03, 0.01, 0.003), out_dir=None, smooth_variants=(True,), wet=False,
-               log=print):
+               ref_tol=1e-10, ref_steps=2_000_000, ref_budget_s=None, log=print):
     """Generate steady training fields with the batched solver, train the
     network on them, then solve held-out cases from rest and from the
-    prediction and compare the time to each residual tolerance."""
+    prediction and compare the time to each residual tolerance and to each
+    distance from reference steady fields (an FP64 run to ref_tol), and the
+    distance of each run's final field from that reference."""
     import torch
     res = {"config": dict(n_train=n_train, n_eval=n_eval, nr=nr, nz=nz, re_max=re_max, tol=tol,
                           gen_steps=gen_steps, eval_steps=eval_steps, train_steps=train_steps,
@@ -246,17 +248,22 @@ def experiment(n_train=256, n_eval=16, nr=128, nz=256, re_max=1000.0, tol=1e-8,
                         params=net.nparam, scales=sc.s.tolist())
     del X, Y
 
-    # from rest once to get the reference (its final field), then again with
-    # the distance to it tracked (the run is deterministic)
-    z0 = solve(ev, tol=tol, max_steps=eval_steps, check_every=check_every,
-               budget_s=eval_budget_s, log=log, tag="zero")
-    ref = {k: torch.tensor(z0.fields[k], device="cuda") for k in ("uz", "ur", "uth")}
-    z = solve(ev, tol=tol, max_steps=eval_steps, check_every=check_every,
-              budget_s=eval_budget_s, log=log, tag="zero_ref", ref=ref)
+    # reference steady fields: FP64 from rest to a residual far below tol
+    ref_run = solve(ev, tol=ref_tol, max_steps=ref_steps, check_every=check_every,
+                    budget_s=ref_budget_s, prec=L.FP64, log=log, tag="reference")
+    ref = {k: torch.tensor(ref_run.fields[k], device="cuda") for k in ("uz", "ur", "uth")}
     shape = (n_eval, nr, nz)
+    res["reference"] = dict(wall_s=ref_run.wall_s, status=ref_run.status.tolist(),
+                            steps=ref_run.steps.tolist(), residual=ref_run.residual.tolist(),
+                            prec="f64", tol=ref_tol)
+    # from rest and from the prediction, with the distance to the reference
+    # recorded at every check (the same macros pass in both runs)
+    z = solve(ev, tol=tol, max_steps=eval_steps, check_every=check_every,
+              budget_s=eval_budget_s, log=log, tag="zero", ref=ref)
+    dz = rel_field_error(z.fields, ref_run.fields, shape)
     res["eval"] = dict(cases=[c["name"] for c in ev],
-                       zero=dict(wall_s=z0.wall_s, steps=z0.steps.tolist(),
-                                 status=z0.status.tolist(), residual=z0.residual.tolist()))
+                       zero=dict(wall_s=z.wall_s, steps=z.steps.tolist(), status=z.status.tolist(),
+                                 residual=z.residual.tolist(), final_error=dz.tolist()))
     for smooth in smooth_variants:
         tag = "nn_smooth" if smooth else "nn_raw"
         torch.cuda.synchronize()
@@ -266,21 +273,17 @@ def experiment(n_train=256, n_eval=16, nr=128, nz=256, re_max=1000.0, tol=1e-8,
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - t0
         pred = {k: v.double().cpu().numpy() for k, v in init.items()}
-        w0 = solve(ev, init=init, tol=tol, max_steps=eval_steps, check_every=check_every,
-                   budget_s=eval_budget_s, log=log, tag=tag)
         w = solve(ev, init=init, tol=tol, max_steps=eval_steps, check_every=check_every,
-                  budget_s=eval_budget_s, log=log, tag=tag + "_ref", ref=ref)
-        both = (z0.status == L.CONVERGED) & (w0.status == L.CONVERGED)
-        fd = rel_field_error(w0.fields, z0.fields, shape)
-        cmp_res = compare(z0, w0, t_inf, tols)
-        cmp_err = compare(z, w, t_inf, (), errs)
+                  budget_s=eval_budget_s, log=log, tag=tag, ref=ref)
+        dw = rel_field_error(w.fields, ref_run.fields, shape)
+        cmp = compare(z, w, t_inf, tols, errs)
         res["eval"][tag] = dict(
-            wall_s=w0.wall_s + t_inf, inference_s=t_inf, steps=w0.steps.tolist(),
-            status=w0.status.tolist(), residual=w0.residual.tolist(),
-            by_tol=cmp_res["residual"], by_distance=cmp_err.get("distance", []),
-            prediction_error=rel_field_error(pred, z0.fields, shape).tolist(),
-            final_difference=fd.tolist(),
-            final_difference_converged_max=float(fd[both].max()) if both.any() else None)
+            wall_s=w.wall_s + t_inf, inference_s=t_inf, steps=w.steps.tolist(),
+            status=w.status.tolist(), residual=w.residual.tolist(),
+            by_tol=cmp["residual"], by_distance=cmp.get("distance", []),
+            prediction_error=rel_field_error(pred, ref_run.fields, shape).tolist(),
+            final_error=dw.tolist(),
+            final_difference=rel_field_error(w.fields, z.fields, shape).tolist())
     if out_dir:
         os.makedirs(out_dir, exist_ok=True)
         save_model(os.path.join(out_dir, "melt_unet_%dx%d.npz" % (nz, nr)), net, sc,
@@ -307,6 +310,9 @@ def main(argv=None):
     ap.add_argument("--train-budget", type=float, default=None)
     ap.add_argument("--eval-budget", type=float, default=None)
     ap.add_argument("--check-every", type=int, default=1000)
+    ap.add_argument("--ref-tol", type=float, default=1e-10)
+    ap.add_argument("--ref-steps", type=int, default=2_000_000)
+    ap.add_argument("--ref-budget", type=float, default=None)
     ap.add_argument("--out", default=None)
     ap.add_argument("--variants", default="smooth", help="comma list of smooth,raw")
     ap.add_argument("--wet", action="store_true", help="wet-node walls (the paper's treatment)")
@@ -315,13 +321,17 @@ def main(argv=None):
     r = experiment(a.n_train, a.n_eval, a.nr, a.nz, a.re_max, a.tol, a.gen_steps, a.eval_steps,
                    a.train_steps, a.batch, a.lr, a.gen_budget, a.train_budget, a.eval_budget,
                    check_every=a.check_every, out_dir=a.out, smooth_variants=variants, wet=a.wet,
+                   ref_tol=a.ref_tol, ref_steps=a.ref_steps, ref_budget_s=a.ref_budget,
                    log=lambda s: print(s, flush=True))
     print(json.dumps({k: r[k] for k in ("generate", "train")}))
     for tag in ("nn_smooth", "nn_raw"):
         if tag not in r["eval"]:
             continue
         e = r["eval"][tag]
-        print(tag, "prediction error median %.3f" % float(np.median(e["prediction_error"])))
+        print(tag, "prediction error median %.3f" % float(np.median(e["prediction_error"])),
+              "final error vs reference: nn median %.2e max %.2e, zero median %.2e max %.2e" % (
+                  np.median(e["final_error"]), np.max(e["final_error"]),
+                  np.median(r["eval"]["zero"]["final_error"]), np.max(r["eval"]["zero"]["final_error"])))
         for d in e["by_tol"] + e["by_distance"]:
             print(tag, json.dumps({k: v for k, v in d.items()
                                    if not k.startswith("steps_") or k == "steps_ratio_median"}))

@@ -1,9 +1,9 @@
 """The learned warm start end to end on small melts (32 x 64 nodes, wet-node
 walls as in the paper's rotating flows), with the network trained on the GPU
 by the library's own kernels on steady fields the batched solver generates:
-the warm-started runs reach the steady field (the from-rest run's final
-state) and the Eq. (57) residual 1e-6 in fewer steps than the runs from
-rest, and both end on the same field."""
+the warm-started runs come within 10 % of reference steady fields (FP64,
+residual 1e-10) and reach the Eq. (57) residual 1e-6 in fewer steps than the
+runs from rest, and stop as close to the reference as they do."""
 import numpy as np
 import pytest
 
@@ -22,7 +22,7 @@ def test_warm_start_reaches_the_steady_field_sooner():
     r = WS.experiment(n_train=96, n_eval=8, nr=32, nz=64, re_max=250.0, tol=1e-8,
                       gen_steps=200_000, eval_steps=150_000, train_steps=800, batch=8, lr=1e-3,
                       check_every=1000, tols=(1e-6, 1e-8), errs=(0.1, 0.03), wet=True,
-                      log=None)
+                      ref_tol=1e-10, ref_steps=400_000, log=None)
     e = r["eval"]["nn_smooth"]
     print({k: r[k] for k in ("generate", "train")})
     for d in e["by_distance"] + e["by_tol"]:
@@ -34,5 +34,8 @@ def test_warm_start_reaches_the_steady_field_sooner():
     r6 = {d["tol"]: d for d in e["by_tol"]}[1e-6]
     assert r6["reached_both"] >= 6
     assert r6["steps_ratio_median"] > 1.1
-    # same steady field from either start (max |du| / u_max per lattice)
-    assert np.median(e["final_difference"]) < 1e-2
+    # at the same Eq. (57) tolerance both starts end as close to the
+    # reference steady field (FP64, residual 1e-10) as each other
+    z_err = np.asarray(r["eval"]["zero"]["final_error"])
+    n_err = np.asarray(e["final_error"])
+    assert np.median(n_err) < 2.0 * np.median(z_err) + 1e-3
