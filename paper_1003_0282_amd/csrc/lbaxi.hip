@@ -35,24 +35,6 @@ struct TileRange {
   int start, end, stride;
 };
 
-// Read-only kernel inputs (tile lists, lattice parameters) go through the
-// constant address space so that wave-uniform reads become scalar loads.
-template <typename T>
-__device__ inline T cload(const T* p) {
-  static_assert(sizeof(T) % 4 == 0, "word-sized structs only");
-  typedef const __attribute__((address_space(4))) int* cptr;
-  const cptr q = (cptr)p;
-  // the words become the struct through a union (no type-punned pointer)
-  union U {
-    int w[sizeof(T) / 4];
-    T v;
-    __device__ U() {}
-  } u;
-#pragma unroll
-  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) u.w[k] = q[k];
-  return u.v;
-}
-
 // Tiles handled by this workgroup.  With xcd_aware the grid is split into 8
 // interleaved groups (workgroup b runs on XCD b % 8), each walking its own
 // contiguous band of tiles so that neighbouring tiles share one L2.
@@ -340,7 +322,7 @@ __global__ void __launch_bounds__(256) k_halo(const InstP* ip, const Tile* tiles
   if (p >= 2 * P.nz + 2 * (P.nr - 2)) return;
   int i, j;
   perimeter_node(P, p, i, j);
-  HaloFill<S, F, 0>::run(P, buf + P.off, i, j);
+  HaloFill<S, F, 0>::run(P, ip + T.inst, buf + P.off, i, j);
 }
 
 // Equilibrium seeding: f^ = f_eq - S/2 at rho = rho0, g = g_eq, h = h_eq.

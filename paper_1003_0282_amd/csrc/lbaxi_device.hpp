@@ -279,6 +279,24 @@ __device__ inline S* ptrb(S* base, unsigned boff) {
   return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + boff);
 }
 
+// Read-only kernel inputs (tile lists, lattice parameters) go through the
+// constant address space so that wave-uniform reads become scalar loads.
+template <typename T>
+__device__ inline T cload(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized structs only");
+  typedef const __attribute__((address_space(4))) int* cptr;
+  const cptr q = (cptr)p;
+  // the words become the struct through a union (no type-punned pointer)
+  union U {
+    int w[sizeof(T) / 4];
+    T v;
+    __device__ U() {}
+  } u;
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) u.w[k] = q[k];
+  return u.v;
+}
+
 // Which segment of a z-end applies at row j (second one beyond r_split).
 __device__ inline void zseg(const InstP& P, const SideP& S, int j, int& kind, double& omega,
                             int& thermal, double& T) {
@@ -296,13 +314,13 @@ __device__ inline void zseg(const InstP& P, const SideP& S, int j, int& kind, do
 // f: moving-wall bounce-back adds 6 w_a rho0 (e_a . u_w); the axis mirrors
 // row 1; a free-slip z-end reflects e_z only.
 template <typename S, int A>
-__device__ inline double rule_f(const InstP& P, const S* s, int i, int j) {
+__device__ inline double rule_f(const InstP& P, const InstP* Pg, const S* s, int i, int j) {
   constexpr int ez = ez9(A), er = er9(A);
   const int nz = P.nz, nr = P.nr, pl = P.plane;
   int iu = i - ez;
   const int ju = j - er;
   if (iu < 0 || iu >= nz) {
-    const SideP& W = P.side[iu < 0 ? WEST : EAST];
+    const SideP W = cload(&Pg->side[iu < 0 ? WEST : EAST]);  // run-time side: from memory
     if (W.kind == SIDE_PERIODIC) {
       iu += (iu < 0) ? nz : -nz;
     } else {
@@ -333,13 +351,13 @@ __device__ inline double rule_f(const InstP& P, const S* s, int i, int j) {
 // g: anti-bounce-back with rho0 u_theta,w / 2 = rho0 omega r / 2 on walls,
 // zero flux on free slip; the axis value is replaced by the extrapolation.
 template <typename S, int A>
-__device__ inline double rule_g(const InstP& P, const S* s, int i, int j) {
+__device__ inline double rule_g(const InstP& P, const InstP* Pg, const S* s, int i, int j) {
   constexpr int ez = ez4(A), er = er4(A);
   const int nz = P.nz, nr = P.nr, pl = P.plane;
   int iu = i - ez;
   const int ju = j - er;
   if (iu < 0 || iu >= nz) {
-    const SideP& W = P.side[iu < 0 ? WEST : EAST];
+    const SideP W = cload(&Pg->side[iu < 0 ? WEST : EAST]);  // run-time side: from memory
     if (W.kind == SIDE_PERIODIC) {
       iu += (iu < 0) ? nz : -nz;
     } else {
@@ -365,13 +383,13 @@ __device__ inline double rule_g(const InstP& P, const S* s, int i, int j) {
 // h (stored as h - T_ref/4): anti-bounce-back (T_w - T_ref)/2 on fixed-
 // temperature walls, bounce-back on adiabatic ones, mirror on the axis.
 template <typename S, int A>
-__device__ inline double rule_h(const InstP& P, const S* s, int i, int j) {
+__device__ inline double rule_h(const InstP& P, const InstP* Pg, const S* s, int i, int j) {
   constexpr int ez = ez4(A), er = er4(A);
   const int nz = P.nz, nr = P.nr, pl = P.plane;
   int iu = i - ez;
   const int ju = j - er;
   if (iu < 0 || iu >= nz) {
-    const SideP& W = P.side[iu < 0 ? WEST : EAST];
+    const SideP W = cload(&Pg->side[iu < 0 ? WEST : EAST]);  // run-time side: from memory
     if (W.kind == SIDE_PERIODIC) {
       iu += (iu < 0) ? nz : -nz;
     } else {
@@ -400,27 +418,27 @@ __device__ inline double rule_h(const InstP& P, const S* s, int i, int j) {
 // are always real nodes, so ghost writes never race with the reads.
 template <typename S, int F, int A>
 struct HaloFill {
-  __device__ static inline void run(const InstP& P, S* s, int i, int j) {
+  __device__ static inline void run(const InstP& P, const InstP* Pg, S* s, int i, int j) {
     const int pl = P.plane;
     {
       const int iu = i - ez9(A), ju = j - er9(A);
       if (iu < 0 || iu >= P.nz || ju < 0 || ju >= P.nr)
-        s[A * pl + nidx(P, ju, iu)] = (S)rule_f<S, A>(P, s, i, j);
+        s[A * pl + nidx(P, ju, iu)] = (S)rule_f<S, A>(P, Pg, s, i, j);
     }
     if constexpr (A < 4) {
       const int iu = i - ez4(A), ju = j - er4(A);
       if (iu < 0 || iu >= P.nz || ju < 0 || ju >= P.nr) {
         if (F & F_SWIRL) {
           S* sg = s + 9 * pl;
-          sg[A * pl + nidx(P, ju, iu)] = (S)rule_g<S, A>(P, sg, i, j);
+          sg[A * pl + nidx(P, ju, iu)] = (S)rule_g<S, A>(P, Pg, sg, i, j);
         }
         if (F & F_THERMAL) {
           S* sh = s + ((F & F_SWIRL) ? 13 : 9) * pl;
-          sh[A * pl + nidx(P, ju, iu)] = (S)rule_h<S, A>(P, sh, i, j);
+          sh[A * pl + nidx(P, ju, iu)] = (S)rule_h<S, A>(P, Pg, sh, i, j);
         }
       }
     }
-    if constexpr (A + 1 < 9) HaloFill<S, F, A + 1>::run(P, s, i, j);
+    if constexpr (A + 1 < 9) HaloFill<S, F, A + 1>::run(P, Pg, s, i, j);
   }
 };
 
