@@ -134,6 +134,44 @@ def copy_probe(steps: int, warmup: int, nbytes: int = 4 << 30):
             "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def sequential_probe(steps: int):
+    """The 256 cavities of batch256 run one after another (one handle each,
+    default launch shape, graphs on) against the same lattices in one
+    batched handle: aggregate MLUPS of both."""
+    import torch
+    from paper_1003_0282_amd import lbaxi as L
+    from paper_1003_0282_amd import workloads as W
+    cases = W.batch_cavities(256, seed=0)
+    nodes = sum(c["nz"] * c["nr"] for c in cases)
+    lats = [L.Lattices([c], L.FP32) for c in cases]
+    for lat in lats:
+        lat.seed()
+        lat.step(64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lat in lats:
+        lat.step(steps)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t0
+    del lats
+    batch = L.Lattices(cases, L.FP32)
+    batch.seed()
+    batch.step(64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    torch.cuda.synchronize()
+    bat_s = time.perf_counter() - t0
+    seq, bat = nodes * steps / seq_s / 1e6, nodes * steps / bat_s / 1e6
+    return {"metric": "aggregate MLUPS of 256 cavities: one after another vs one batched handle",
+            "value": round(bat / seq, 3), "unit": "x (batched / sequential)", "n_gpus": 1,
+            "steps": steps, "higher_is_better": True, "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "batch256_sequential", "lattices": len(cases), "nodes": nodes,
+                       "population_storage": "f32", "launch": "default (64 x 4 tiles)"},
+            "sequential_mlups": round(seq, 1), "batched_mlups": round(bat, 1)}
+
+
 def warmstart_probe():
     """Time to the Eq. (57) residual 1e-8 of 16 held-out 128 x 256 melts
     (wet-node walls, FP32 storage) from rest and from the learned warm start,
@@ -195,6 +233,9 @@ def main():
         return
     if args.workload == "warmstart":
         print(json.dumps(warmstart_probe()))
+        return
+    if args.workload == "batch256_sequential":
+        print(json.dumps(sequential_probe(args.steps)))
         return
     cases, prec, label = workload(args.workload)
     if args.prec:

@@ -107,14 +107,15 @@ def cavity(nr: int, nz: int, Re: float, U_t: float = 0.1, wet: bool = False) -> 
                      Re=float(Re))
 
 
-def cavity_paper(Re: float = 990.0, nr: int = 100, nz: int = 150) -> dict:
-    """The paper's lid-driven run: 100 x 150 (A = 1.5), tau = 0.02 (paper
-    convention, nu = tau/3)."""
+def cavity_paper(Re: float = 990.0, nr: int = 100, nz: int = 150, wet: bool = False) -> dict:
+    """The paper's lid-driven run (Sec. IV B, Table 2): 100 x 150 (A = 1.5),
+    tau = 0.02 (paper convention, nu = tau/3), Omega = Re nu / R^2."""
     nu = 0.02 / 3.0
-    R = nr - 0.5
+    R = nr - (1.0 if wet else 0.5)
     omega = Re * nu / (R * R)
     return base_case(nz, nr, 0.52, swirl=True, south=axis(), north=wall(), west=wall(),
-                     east=wall(omega=omega), name="cavity_paper_Re%g" % Re, Re=float(Re))
+                     east=wall(omega=omega), wet=bool(wet),
+                     name="cavity_paper_Re%g%s" % (Re, "_wet" if wet else ""), Re=float(Re))
 
 
 def batch_cavities(n: int = 256, seed: int = 0, nr_lo: int = 64, nr_hi: int = 512,
