@@ -229,7 +229,7 @@ lbaxi_status lbaxi_node_count(const lbaxi_t* h, int64_t* nodes, int32_t* n);
 /* Plain device-to-device streaming copy of `bytes` (a multiple of 16, both
  * pointers 16-byte aligned) on hip_stream: the bandwidth reference used to
  * calibrate HBM counters and the roofline fraction of the step kernel.
- * Asynchronous; EINVAL on misaligned arguments. */
+ * Asynchronous; EINVAL on misaligned arguments or a copy above 8 TiB. */
 lbaxi_status lbaxi_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* hip_stream);
 
 #ifdef __cplusplus

@@ -140,19 +140,19 @@ __device__ inline bool wet_rule(const InstP& P, const InstP* Pg, int i, int j, W
   w->in = i + (west ? 1 : (east ? -1 : 0));
   w->jn = j + (north ? -1 : (south ? 1 : 0));
   const int side = west ? WEST : (east ? EAST : (north ? NORTH : SOUTH));
-  const SideP Q = cload(&Pg->side[side]);
+  const SideP* Q = &Pg->side[side];
   if (west || east) {
     int kind;
-    zseg(P, Q, j, kind, w->omega, w->thermal, w->T);
+    zseg_g(P, Q, j, kind, w->omega, w->thermal, w->T);
     w->free_ = kind == SIDE_FREESLIP;
   } else {
     w->free_ = 0;
-    w->omega = Q.omega;
-    w->thermal = Q.thermal;
-    w->T = Q.T;
+    w->omega = cload(&Q->omega);
+    w->thermal = cload(&Q->thermal);
+    w->T = cload(&Q->T);
   }
-  w->uz = Q.uz;
-  w->ur = Q.ur;
+  w->uz = cload(&Q->uz);
+  w->ur = cload(&Q->ur);
   return true;
 }
 
@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(256) k_halo(const InstP* ip, const Tile* tiles
   if (p >= 2 * P.nz + 2 * (P.nr - 2)) return;
   int i, j;
   perimeter_node(P, p, i, j);
-  HaloFill<S, F, 0>::run(P, ip + T.inst, buf + P.off, i, j);
+  halo_fill<S, F>(P, ip + T.inst, buf + P.off, i, j);
 }
 
 // Equilibrium seeding: f^ = f_eq - S/2 at rho = rho0, g = g_eq, h = h_eq.
@@ -478,9 +478,10 @@ __global__ void k_add_time(long long* t, long long dv) {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src,
                                               u32x4* __restrict__ dst, long long n) {
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
-    __builtin_nontemporal_store(src[k], dst + k);
+  // one 16-byte element per lane, one workgroup per 4 KiB: no loop, so that
+  // every wave has its load in flight from the start
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) __builtin_nontemporal_store(src[k], dst + k);
 }
 
 // ============================================================================
@@ -525,14 +526,22 @@ long long halo_tiles(const std::vector<lbaxi_desc>& d) {
   for (const auto& x : d) n += (perimeter(x) + 255) / 256;
   return n;
 }
-// Padded rows: a 128-byte lead-in holding the ghost column, nz nodes, the
-// other ghost column, rounded up to 128 bytes.
+// Padded rows: a 128-byte lead-in (node 0 starts a 128-byte line), nz
+// nodes and one spare slot, rounded up to 128 bytes; rows -1 and nr are the
+// ghost rows.  After the nr + 2 rows come the ghost-column strips of the two
+// z-ends, nr + 2 slots each, rounded up to 128 bytes.
 int row_lead(const lbaxi_desc& x) { return 128 / (x.prec == LBAXI_FP64 ? 8 : 4); }
 int row_pitch(const lbaxi_desc& x) {
   const int q = row_lead(x);
   return (q + x.nz + 1 + q - 1) / q * q;
 }
-long long padded_plane(const lbaxi_desc& x) { return (long long)(x.nr + 2) * row_pitch(x); }
+int strip_len(const lbaxi_desc& x) {
+  const int q = row_lead(x);
+  return (x.nr + 2 + q - 1) / q * q;
+}
+long long padded_plane(const lbaxi_desc& x) {
+  return (long long)(x.nr + 2) * row_pitch(x) + 2LL * strip_len(x);
+}
 
 // Device workspace: parameters, three work lists (all tiles / tiles of
 // running lattices / halo chunks of running lattices) with their counts,
@@ -645,6 +654,8 @@ InstP make_inst(const lbaxi_desc& d, long long off, long long off_fld) {
   P.pitch = row_pitch(d);
   P.c0 = row_lead(d);
   P.plane = (int)padded_plane(d);
+  P.sw = (d.nr + 2) * row_pitch(d);
+  P.se = P.sw + strip_len(d);
   P.cart = (d.fields & LBAXI_CARTESIAN) ? 1 : 0;
   P.wet = (d.fields & LBAXI_WET_WALLS) ? 1 : 0;
   P.r0 = d.r0;
@@ -1555,13 +1566,9 @@ lbaxi_status lbaxi_stream_copy(const void* d_src, void* d_dst, size_t bytes, voi
     return fail(LBAXI_EINVAL, "copy needs 16-byte aligned pointers and size");
   const long long n = (long long)(bytes / 16);
   if (n == 0) return LBAXI_OK;
-  int dev = 0, cu = 256;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-    cu = prop.multiProcessorCount;
-  const long long want = (n + 255) / 256;
-  const int grid = (int)std::min<long long>(want, (long long)cu * 16);
-  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream),
+  const long long grid = (n + 255) / 256;
+  if (grid > 0x7fffffffLL) return fail(LBAXI_EINVAL, "copy larger than 2^31 workgroups of 4 KiB");
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)grid), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream),
                      static_cast<const u32x4*>(d_src), static_cast<u32x4*>(d_dst), n);
   HIPCHK(hipGetLastError());
   return LBAXI_OK;

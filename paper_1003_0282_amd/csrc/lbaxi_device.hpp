@@ -29,7 +29,8 @@ struct InstP {
   int wet;    // wall sides are wet-node walls (wall through the outer node row)
   int pitch;  // row length of a padded plane (a multiple of 128 bytes)
   int c0;     // column of node i = 0 (128 bytes in; the ghost column is c0 - 1)
-  int plane;  // (nr + 2) * pitch: elements per padded plane
+  int plane;  // elements per padded plane: (nr + 2) rows of pitch, then the two strips
+  int sw, se;  // element offsets in a plane of the west / east ghost-column strips
   double r0;
   double tau, tau_g, tau_h;  // paper convention: nu = tau / 3
   double rho0, mu0, nu_g;
@@ -307,6 +308,27 @@ __device__ inline void zseg(const InstP& P, const SideP& S, int j, int& kind, do
   }
 }
 
+// The same for a side chosen at run time, read field by field from the
+// lattice's parameter block: a whole-struct copy with a run-time choice
+// between its fields would be kept in scratch memory.
+__device__ inline void zseg_g(const InstP& P, const SideP* W, int j, int& kind, double& omega,
+                              int& thermal, double& T) {
+  const double rs = cload(&W->r_split);
+  const bool second = rs >= 0.0 && P.r0 + (double)j > rs;
+  kind = second ? cload(&W->kind2) : cload(&W->kind);
+  omega = second ? cload(&W->omega2) : cload(&W->omega);
+  thermal = second ? cload(&W->thermal2) : cload(&W->thermal);
+  T = second ? cload(&W->T2) : cload(&W->T);
+}
+
+// Ghost slot (element offset in a plane) of the upstream position (iu, ju)
+// outside the lattice: beyond a z-end, the west / east strip, which holds
+// the ghost column of rows -1..nr contiguously (so that filling it is a
+// coalesced write, not one element per row); else the ghost row.
+__device__ inline int ghost_slot(const InstP& P, int iu, int ju) {
+  return iu < 0 ? P.sw + ju + 1 : (iu >= P.nz ? P.se + ju + 1 : nidx(P, ju, iu));
+}
+
 // Boundary rules: the value node (i, j) receives in direction A when its
 // upstream node (i, j) - e_A lies outside the lattice.  A z-end is resolved
 // before the radial sides.  s points at the instance's first plane.
@@ -320,12 +342,12 @@ __device__ inline double rule_f(const InstP& P, const InstP* Pg, const S* s, int
   int iu = i - ez;
   const int ju = j - er;
   if (iu < 0 || iu >= nz) {
-    const SideP W = cload(&Pg->side[iu < 0 ? WEST : EAST]);  // run-time side: from memory
-    if (W.kind == SIDE_PERIODIC) {
+    const SideP* W = &Pg->side[iu < 0 ? WEST : EAST];  // run-time side: from memory
+    if (cload(&W->kind) == SIDE_PERIODIC) {
       iu += (iu < 0) ? nz : -nz;
     } else {
       int kind, th; double om, T;
-      zseg(P, W, j, kind, om, th, T);
+      zseg_g(P, W, j, kind, om, th, T);
       if (kind == SIDE_FREESLIP) {
         constexpr int b = mz9(A);
         if (ju >= 0 && ju < nr) return (double)s[b * pl + nidx(P, ju, i)];
@@ -333,7 +355,7 @@ __device__ inline double rule_f(const InstP& P, const InstP* Pg, const S* s, int
         return (double)s[opp9(A) * pl + nidx(P, j, i)];
       }
       return (double)s[opp9(A) * pl + nidx(P, j, i)] +
-             6.0 * w9(A) * P.rho0 * (ez * W.uz + er * W.ur);
+             6.0 * w9(A) * P.rho0 * (ez * cload(&W->uz) + er * cload(&W->ur));
     }
   }
   if (ju < 0) {
@@ -357,12 +379,12 @@ __device__ inline double rule_g(const InstP& P, const InstP* Pg, const S* s, int
   int iu = i - ez;
   const int ju = j - er;
   if (iu < 0 || iu >= nz) {
-    const SideP W = cload(&Pg->side[iu < 0 ? WEST : EAST]);  // run-time side: from memory
-    if (W.kind == SIDE_PERIODIC) {
+    const SideP* W = &Pg->side[iu < 0 ? WEST : EAST];  // run-time side: from memory
+    if (cload(&W->kind) == SIDE_PERIODIC) {
       iu += (iu < 0) ? nz : -nz;
     } else {
       int kind, th; double om, T;
-      zseg(P, W, j, kind, om, th, T);
+      zseg_g(P, W, j, kind, om, th, T);
       if (kind == SIDE_FREESLIP) return (double)s[opp4(A) * pl + nidx(P, j, i)];
       return -(double)s[opp4(A) * pl + nidx(P, j, i)] + 0.5 * P.rho0 * om * (P.r0 + (double)j);
     }
@@ -389,12 +411,12 @@ __device__ inline double rule_h(const InstP& P, const InstP* Pg, const S* s, int
   int iu = i - ez;
   const int ju = j - er;
   if (iu < 0 || iu >= nz) {
-    const SideP W = cload(&Pg->side[iu < 0 ? WEST : EAST]);  // run-time side: from memory
-    if (W.kind == SIDE_PERIODIC) {
+    const SideP* W = &Pg->side[iu < 0 ? WEST : EAST];  // run-time side: from memory
+    if (cload(&W->kind) == SIDE_PERIODIC) {
       iu += (iu < 0) ? nz : -nz;
     } else {
       int kind, th; double om, T;
-      zseg(P, W, j, kind, om, th, T);
+      zseg_g(P, W, j, kind, om, th, T);
       if (kind == SIDE_WALL && th)
         return -(double)s[opp4(A) * pl + nidx(P, j, i)] + 0.5 * (T - P.T_ref);
       return (double)s[opp4(A) * pl + nidx(P, j, i)];
@@ -414,37 +436,73 @@ __device__ inline double rule_h(const InstP& P, const InstP* Pg, const S* s, int
   return (double)s[A * pl + nidx(P, ju, iu)];
 }
 
-// Fill, for boundary node (i, j), every ghost slot it pulls from.  Sources
-// are always real nodes, so ghost writes never race with the reads.
+// Ghost slots that boundary node (i, j) pulls from, with their values:
+// at[k] is the slot of plane k (f, g, h in storage order) or -1 where the
+// upstream node is a real one.
 template <typename S, int F, int A>
-struct HaloFill {
-  __device__ static inline void run(const InstP& P, const InstP* Pg, S* s, int i, int j) {
-    const int pl = P.plane;
-    {
-      const int iu = i - ez9(A), ju = j - er9(A);
-      if (iu < 0 || iu >= P.nz || ju < 0 || ju >= P.nr)
-        s[A * pl + nidx(P, ju, iu)] = (S)rule_f<S, A>(P, Pg, s, i, j);
-    }
-    if constexpr (A < 4) {
-      const int iu = i - ez4(A), ju = j - er4(A);
-      if (iu < 0 || iu >= P.nz || ju < 0 || ju >= P.nr) {
-        if (F & F_SWIRL) {
-          S* sg = s + 9 * pl;
-          sg[A * pl + nidx(P, ju, iu)] = (S)rule_g<S, A>(P, Pg, sg, i, j);
-        }
-        if (F & F_THERMAL) {
-          S* sh = s + ((F & F_SWIRL) ? 13 : 9) * pl;
-          sh[A * pl + nidx(P, ju, iu)] = (S)rule_h<S, A>(P, Pg, sh, i, j);
-        }
-      }
-    }
-    if constexpr (A + 1 < 9) HaloFill<S, F, A + 1>::run(P, Pg, s, i, j);
+__device__ inline void halo_gather(const InstP& P, const InstP* Pg, const S* s, int i, int j,
+                                   S* v, int* at) {
+  const int pl = P.plane;
+  {
+    const int iu = i - ez9(A), ju = j - er9(A);
+    const bool out = iu < 0 || iu >= P.nz || ju < 0 || ju >= P.nr;
+    at[A] = out ? A * pl + ghost_slot(P, iu, ju) : -1;
+    if (out) v[A] = (S)rule_f<S, A>(P, Pg, s, i, j);
   }
-};
+  if constexpr (A < 4) {
+    const int iu = i - ez4(A), ju = j - er4(A);
+    const bool out = iu < 0 || iu >= P.nz || ju < 0 || ju >= P.nr;
+    if (F & F_SWIRL) {
+      at[9 + A] = out ? (9 + A) * pl + ghost_slot(P, iu, ju) : -1;
+      if (out) v[9 + A] = (S)rule_g<S, A>(P, Pg, s + 9 * pl, i, j);
+    }
+    if (F & F_THERMAL) {
+      constexpr int hb = (F & F_SWIRL) ? 13 : 9;
+      at[hb + A] = out ? (hb + A) * pl + ghost_slot(P, iu, ju) : -1;
+      if (out) v[hb + A] = (S)rule_h<S, A>(P, Pg, s + hb * pl, i, j);
+    }
+  }
+  if constexpr (A + 1 < 9) halo_gather<S, F, A + 1>(P, Pg, s, i, j, v, at);
+}
+
+// Fill, for boundary node (i, j), every ghost slot it pulls from.  Sources
+// are always real nodes and targets ghost slots, so every value is read
+// before the first write: the loads of a node stay in flight together
+// instead of waiting one by one behind stores to the same buffer.
+template <typename S, int F>
+__device__ inline void halo_fill(const InstP& P, const InstP* Pg, S* s, int i, int j) {
+  constexpr int NQ = 9 + ((F & F_SWIRL) ? 4 : 0) + ((F & F_THERMAL) ? 4 : 0);
+  S v[NQ];
+  int at[NQ];
+  halo_gather<S, F, 0>(P, Pg, s, i, j, v, at);
+#pragma unroll
+  for (int k = 0; k < NQ; ++k)
+    if (at[k] >= 0) s[at[k]] = v[k];
+}
+
+// Populations that node (WEST ? 0 : nz - 1, j) receives across its z-end,
+// from the ghost-column strip of that end (rows j - e_r, slot row + 1).
+template <typename S, typename R, int F, bool WEST_END>
+__device__ inline void zend_pull(const InstP& P, const S* __restrict__ s, int j, R* f, R* g, R* h) {
+  const int pl = P.plane;
+  constexpr int dir = WEST_END ? 1 : -1;  // e_z of the populations that cross it
+  const unsigned b = (unsigned)((WEST_END ? P.sw : P.se) + j + 1);
+  constexpr unsigned es = sizeof(S);
+#pragma unroll
+  for (int a = 0; a < 9; ++a)
+    if (ez9(a) == dir) f[a] = (R)ldb(s + a * pl, (b - er9(a)) * es);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+    if (ez4(a) == dir) {
+      if (F & F_SWIRL) g[a] = (R)ldb(s + (9 + a) * pl, (b - er4(a)) * es);
+      if (F & F_THERMAL) h[a] = (R)ldb(s + (((F & F_SWIRL) ? 13 : 9) + a) * pl, (b - er4(a)) * es);
+    }
+}
 
 // Populations arriving at node (i, j): a plain pull through the padded
-// planes.  pre: the buffer holds f^ itself (right after seeding), so the node
-// reads its own slots.
+// planes; an end column takes what crosses its z-end from that end's strip.
+// pre: the buffer holds f^ itself (right after seeding), so the node reads
+// its own slots.
 template <typename S, typename R, int F>
 __device__ inline void load_node(const InstP& P, const S* __restrict__ s, int i, int j, bool pre,
                                  R* f, R* g, R* h) {
@@ -472,6 +530,11 @@ __device__ inline void load_node(const InstP& P, const S* __restrict__ s, int i,
       if (F & F_SWIRL) g[a] = (R)ldb(sg + a * pl, q);
       if (F & F_THERMAL) h[a] = (R)ldb(sh + a * pl, q);
     }
+    // an end column takes what crosses its z-end from that end's strip
+    // (re-read after the plain pull, which keeps the interior's immediate
+    // load offsets and registers as they are)
+    if (i == 0) zend_pull<S, R, F, true>(P, s, j, f, g, h);
+    if (i == P.nz - 1) zend_pull<S, R, F, false>(P, s, j, f, g, h);
   }
 }
 
