@@ -28,7 +28,7 @@ struct InstP {
   int nz, nr, cart;
   int wet;    // wall sides are wet-node walls (wall through the outer node row)
   int pitch;  // row length of a padded plane (a multiple of 128 bytes)
-  int c0;     // column of node i = 0 (128 bytes in; the ghost column is c0 - 1)
+  int c0;     // column of node i = 0 (128 bytes into the row)
   int plane;  // elements per padded plane: (nr + 2) rows of pitch, then the two strips
   int sw, se;  // element offsets in a plane of the west / east ghost-column strips
   double r0;
@@ -259,14 +259,14 @@ __device__ inline void collide(const PR<R>& p, const Row<R>& w, const Mac<R>& m,
 }
 
 // ---- streaming ---------------------------------------------------------------
-// Each population plane is padded by one ghost node on every side: node
-// (i, j), i in [-1, nz], j in [-1, nr], lives at (j + 1) * pitch + c0 + i,
-// with rows starting on 128-byte boundaries so that a wave's stores are
-// aligned.
-// The step kernel pulls f_a(x) from x - e_a for every node without any test;
-// the ghost slots a real node pulls from are filled after every step by the
-// halo kernel with the boundary rules below, evaluated on the post-collision
-// values of real nodes.
+// Each population plane holds rows j in [-1, nr] (the two ghost rows
+// included) of pitch elements, node (i, j) at (j + 1) * pitch + c0 + i with
+// rows starting on 128-byte boundaries so that a wave's stores are aligned,
+// then one strip per z-end holding that end's ghost column for rows -1..nr.
+// The step kernel pulls f_a(x) from x - e_a for every node without any test
+// (the end columns then re-read from the strips what crosses a z-end); the
+// ghost slots are filled after every step by the halo kernel with the
+// boundary rules below, evaluated on the post-collision values of real nodes.
 
 __device__ inline int nidx(const InstP& P, int j, int i) { return (j + 1) * P.pitch + P.c0 + i; }
 
