@@ -107,6 +107,18 @@ CASES = {
                                        tau_h=0.9, gbeta=2e-4, T_ref=0.5),
     "planar_wet": lambda: W.base_case(65, 10, 0.7, cartesian=True, wet=True, south=W.wall(),
                                       east=W.wall(), west=W.wall(ur=1e-3), a0=2e-5),
+    # narrow lattices: both z-ends in one wave, each column an end column
+    # (nz = 2, periodic), wet walls around a single interior column
+    "narrow_nz2_periodic": lambda: W.base_case(2, 12, 0.8, a0=1e-5),
+    "narrow_nz2": lambda: W.base_case(2, 9, 0.7, west=W.wall(omega=1e-3),
+                                      east=W.wall(uz=0.0, ur=1e-3), swirl=True),
+    "narrow_nz3_freeslip": lambda: W.base_case(3, 10, 0.75, west=W.freeslip(),
+                                               east=W.split_wall(W.wall(omega=2e-3, thermal=1,
+                                                                        T=1.0), W.freeslip(), 4.0),
+                                               swirl=True, thermal=True, tau_h=0.8, T_ref=0.5,
+                                               gbeta=1e-4),
+    "narrow_nz3_wet": lambda: W.base_case(3, 10, 0.75, wet=True, west=W.wall(omega=1e-3),
+                                          east=W.wall(omega=-1e-3), swirl=True),
 }
 
 
