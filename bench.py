@@ -12,11 +12,17 @@ oracle timed on a bounded sample of the same workload.
 
 Workloads (synthetic, seeded):
   batch256   256 rotating-lid cavities, Nr ~ U{64..512}, H/R ~ U[1,3],
-             Re ~ U[500,2500], FP32 f + g, one launch per step (default)
+             Re ~ U[500,2500] (tau_s >= 0.52), FP32 f + g, one launch per
+             step (default)
   pipe_fp32 / pipe_fp64   16384 x 2048 body-force pipe, f only
   womersley  64 x 128 Womersley pipe, FP32
   cavity     256 x 384 rotating-lid cavity at Re 990, FP32 f + g
   melt512    512 crystal/crucible melts 128 x 256, FP32 f + g + h
+  copy       the library's plain copy kernel (the streaming ceiling)
+  unet       warm-start U-Net on 128 x 256 inputs: training steps (batch 8)
+             and forward passes (batch 16), TFLOP/s against the BF16 MFMA peak
+  warmstart  the learned warm start end to end: time to residual 1e-8
+  batch256_sequential   the 256 cavities one handle after another
 """
 from __future__ import annotations
 
@@ -206,6 +212,95 @@ def warmstart_probe():
     }
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16
+
+
+def unet_flops(H, W, c_in, widths, c_out):
+    """Algorithmic FLOPs per sample of the warm-start U-Net: (forward, one
+    training step).  Forward: 2 x the multiply-adds of every 3 x 3
+    convolution at its level's resolution plus the 1 x 1 head; a training
+    step adds the input gradient of every convolution but the first and the
+    weight gradient of every one (the same multiply-adds each)."""
+    w = widths
+    layers = []  # (level, c_in, c_out)
+    prev = c_in
+    for l in range(4):
+        layers += [(l, prev, w[l]), (l, w[l], w[l])]
+        prev = w[l]
+    for l in (2, 1, 0):
+        layers += [(l, w[l + 1] + w[l], w[l]), (l, w[l], w[l])]
+    macs = [(H >> l) * (W >> l) * 9 * ci * co for l, ci, co in layers]
+    head = H * W * w[0] * c_out
+    fwd = 2.0 * (sum(macs) + head)
+    train = fwd + 2.0 * (sum(macs) - macs[0] + head) + 2.0 * (sum(macs) + head)
+    return fwd, train
+
+
+def nn_probe(steps: int, warmup: int, batch: int = 8):
+    """Training and inference throughput of the warm-start U-Net on 128 x 256
+    inputs (8 channels in, 5 out), BF16 MFMA with FP32 accumulation: whole
+    training steps (forward, backward, Adam) timed with HIP events, no host
+    synchronisation inside the timed region."""
+    import ctypes as C
+    import torch
+    from paper_1003_0282_amd import lbnn as N
+    from paper_1003_0282_amd import warmstart as WS
+    H, W = 128, 256
+    torch.cuda.set_device(0)
+    net = WS.make_net(H, W, max_batch=2 * batch)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn((2 * batch, H, W, WS.C_IN), device="cuda", generator=g)
+    y = torch.randn((2 * batch, H, W, WS.C_OUT), device="cuda", generator=g)
+    xb, yb = x[:batch].contiguous(), y[:batch].contiguous()
+    call = lambda: N._check(N._L.lbnn_train_step(net.h, C.c_void_p(xb.data_ptr()),
+                                                   C.c_void_p(yb.data_ptr()), batch, 1e-4, None),
+                            "lbnn_train_step")
+    for _ in range(warmup):
+        call()
+    s = net.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(steps):
+        call()
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms_train = e0.elapsed_time(e1) / steps
+    yo = torch.empty((2 * batch, H, W, WS.C_OUT), device="cuda")
+    fcall = lambda: N._check(N._L.lbnn_forward(net.h, C.c_void_p(x.data_ptr()),
+                                                 C.c_void_p(yo.data_ptr()), 2 * batch),
+                             "lbnn_forward")
+    for _ in range(warmup):
+        fcall()
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(steps):
+        fcall()
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms_fwd = e0.elapsed_time(e1) / steps
+    fwd, train = unet_flops(H, W, WS.C_IN, WS.WIDTHS, WS.C_OUT)
+    tf_train = batch * train / ms_train / 1e9
+    tf_fwd = 2 * batch * fwd / ms_fwd / 1e9
+    net.close()
+    return {
+        "metric": "U-Net training throughput (forward + backward + Adam, BF16 MFMA, FP32 accumulation)",
+        "value": round(tf_train, 2), "unit": "TFLOP/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": round(ms_train, 4), "higher_is_better": True,
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "unet_train_128x256", "batch": batch, "H": H, "W": W,
+                   "c_in": WS.C_IN, "c_out": WS.C_OUT, "widths": list(WS.WIDTHS),
+                   "gflop_per_sample_forward": round(fwd / 1e9, 3),
+                   "gflop_per_sample_train": round(train / 1e9, 3)},
+        "roofline": {"bound": "mfma", "achieved": round(tf_train, 2),
+                     "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf_train / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel": "whole training step (every lbnn kernel of it)"},
+        "inference": {"batch": 2 * batch, "ms": round(ms_fwd, 4), "tflops": round(tf_fwd, 2),
+                      "frac": round(tf_fwd / MFMA_BF16_PEAK_TFLOPS, 4)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +328,9 @@ def main():
         return
     if args.workload == "warmstart":
         print(json.dumps(warmstart_probe()))
+        return
+    if args.workload == "unet":
+        print(json.dumps(nn_probe(args.steps, args.warmup)))
         return
     if args.workload == "batch256_sequential":
         print(json.dumps(sequential_probe(args.steps)))

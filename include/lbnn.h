@@ -42,8 +42,9 @@ typedef struct {
   int32_t H, W;         /* image size; both multiples of 8 */
   int32_t c_in;         /* input channels, <= 16 */
   int32_t c_out;        /* output channels, <= 8 */
-  int32_t widths[4];    /* channel widths, multiples of 32 */
-  int32_t max_batch;    /* largest batch passed to forward/backward */
+  int32_t widths[4];    /* channel widths, multiples of 32 in 32..256 */
+  int32_t max_batch;    /* largest batch passed to forward/backward;
+                           max_batch * H * W < 2^22 */
 } lbnn_desc;
 
 typedef struct lbnn_s lbnn_t;

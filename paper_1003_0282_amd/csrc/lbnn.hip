@@ -2,14 +2,16 @@
 // convolution kernels (forward, backward-data, backward-weight), the glue
 // kernels of the U-Net, MSE loss, Adam, and the C ABI of include/lbnn.h.
 //
-// Every 3x3 convolution is an implicit GEMM on v_mfma_f32_32x32x16_bf16:
-// one wave owns a 32 (pixels) x 32 (output channels) block of the output and
-// walks K = 9 taps x input channels in steps of 16, reading its A fragment
-// (8 consecutive channels of one neighbour pixel, 16 bytes) and B fragment
-// (8 consecutive K of one output channel, 16 bytes) straight from memory.
-// Any K order shared by A and B gives the same sum, so the only layout the
-// code relies on is the accumulator's (checked by lbnn_mfma_selftest):
-// register r of lane l holds row (r/4)*8 + (l/32)*4 + r%4, column l%32.
+// Every 3x3 convolution is an implicit GEMM on v_mfma_f32_32x32x16_bf16
+// (M = pixels, N = output channels, K = 9 taps x input channels): a
+// workgroup stages tiles of the shifted input rows and the weight rows in
+// LDS and each wave multiplies 32 x 32 blocks out of them; the weight
+// gradient stages pixel-major tiles through LDS transposed, since its K is
+// the pixel index.  A lane's A fragment is 8 consecutive K of one row (16
+// bytes), its B fragment 8 consecutive K of one column.  Any K order shared
+// by A and B gives the same sum, so the only layout the code relies on is the
+// accumulator's (checked by lbnn_mfma_selftest): register r of lane l holds
+// row (r/4)*8 + (l/32)*4 + r%4, column l%32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,6 +43,15 @@ __device__ inline f32x16 mfma(u16x8 a, u16x8 b, f32x16 c) {
                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
+// Workgroup b of a grid of G runs on XCD b % 8; map it to tile
+// xcd * (G / 8) + b / 8 (the first G % 8 XCDs take one tile more) so that
+// neighbouring pixel tiles, which re-read each other's rows for the taps of
+// a 3 x 3 convolution, share one L2.  A bijection on [0, G).
+__device__ inline int xcd_tile(int b, int G) {
+  const int x = b & 7, i = b >> 3, q = G >> 3, rem = G & 7;
+  return x < rem ? x * (q + 1) + i : rem * (q + 1) + (x - rem) * q + i;
+}
+
 // Row of the 32x32 output block held by accumulator r of a lane in half g.
 __device__ inline int acc_row(int r, int g) { return (r >> 2) * 8 + g * 4 + (r & 3); }
 
@@ -58,110 +69,295 @@ struct ConvArgs {
   int B, H, W, Ck, Cn, sign, relu;
 };
 
+// Workgroup tile: PT pixels x NT output channels, 4 waves in a WPX x WCH
+// grid, each wave MW x NW blocks of 32 x 32.  K (9 taps x Ck input channels,
+// tap-major) is walked in stages of CV_KST: thread t loads row t of the
+// stage (a pixel row, shifted by each chunk's tap and zero outside the
+// image, or a weight row), eight 16-byte chunks, into LDS (rows padded to
+// 144 bytes: conflict-free fragment reads); every wave then reads its
+// fragments from LDS and runs 4 MW NW MFMAs while the next stage's loads are
+// in flight in registers.  Several taps share a stage when Ck is small.
+constexpr int CV_KST = 64;              // flattened K per stage
+constexpr int CV_RS = CV_KST + 8;       // LDS row stride (elements)
+
+template <int PT, int NT, int MW, int NW>
 __global__ void __launch_bounds__(256) k_conv(ConvArgs A) {
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int m = l & 31, g = l >> 5;
+  constexpr int WPX = PT / (32 * MW), WCH = NT / (32 * NW);
+  static_assert(WPX * WCH == 4, "4 waves per workgroup");
+  constexpr int ROWS = PT + NT, RPT = (ROWS + 255) / 256;  // rows per thread
+  constexpr int NCH = CV_KST / 8;                          // chunks per row
+  __shared__ __attribute__((aligned(16))) bf16s sa[PT * CV_RS];
+  __shared__ __attribute__((aligned(16))) bf16s sb[NT * CV_RS];
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, m = l & 31, g = l >> 5;
   const long long npix = (long long)A.B * A.H * A.W;
-  const long long pix0 = ((long long)blockIdx.x * 4 + wave) * 32;
-  if (pix0 >= npix) return;
-  const int n0 = blockIdx.y * 32;
-  const long long p = pix0 + m;
-  const bool pin = p < npix;
-  int n = 0, y = 0, x = 0;
-  if (pin) {
-    const long long hw = (long long)A.H * A.W;
-    n = (int)(p / hw);
-    const int rem = (int)(p - (long long)n * hw);
-    y = rem / A.W;
-    x = rem - y * A.W;
-  }
-  f32x16 acc = {};
-  const u16x8 zero = {};
-  for (int t = 0; t < 9; ++t) {
-    const int dy = t / 3 - 1, dx = t % 3 - 1;
-    const int yy = y + A.sign * dy, xx = x + A.sign * dx;
-    const bool ok = pin && yy >= 0 && yy < A.H && xx >= 0 && xx < A.W;
-    const bf16s* ap = A.in + (((long long)n * A.H + (ok ? yy : 0)) * A.W + (ok ? xx : 0)) * A.Ck + 8 * g;
-    const bf16s* bp = A.wt + ((long long)t * A.Cn + n0 + m) * A.Ck + 8 * g;
-    for (int c = 0; c < A.Ck; c += 16) {
-      const u16x8 a = ok ? *reinterpret_cast<const u16x8*>(ap + c) : zero;
-      const u16x8 b = *reinterpret_cast<const u16x8*>(bp + c);
-      acc = mfma(a, b, acc);
+  const long long pix0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * PT;
+  const int n0 = blockIdx.y * NT;
+  const long long hw = (long long)A.H * A.W;
+  int ln[RPT], ly[RPT], lx[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int row = tid + 256 * k;
+    ln[k] = ly[k] = lx[k] = -1;
+    const long long p = pix0 + row;
+    if (row < PT && p < npix) {
+      ln[k] = (int)(p / hw);
+      const int rem = (int)(p - (long long)ln[k] * hw);
+      ly[k] = rem / A.W;
+      lx[k] = rem - ly[k] * A.W;
     }
   }
-  const int col = n0 + m;
-  const float bias = A.bias ? A.bias[col] : 0.0f;
+  const int KT = 9 * A.Ck, S = (KT + CV_KST - 1) / CV_KST;
+  u16x8 r[RPT][NCH];
+  auto load = [&](int st) {
+    const int k0 = st * CV_KST;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const long long q = pix0 + acc_row(r, g);
-    if (q >= npix) continue;
-    float v = acc[r] + bias;
-    if (A.relu && v < 0.0f) v = 0.0f;
-    const long long o = q * A.Cn + col;
-    if (A.mask && !(bf2f(A.mask[o]) > 0.0f)) v = 0.0f;
-    A.out[o] = f2bf(v);
+    for (int k = 0; k < RPT; ++k) {
+      const int row = tid + 256 * k;
+      int t = k0 / A.Ck, c = k0 - t * A.Ck;
+#pragma unroll
+      for (int q = 0; q < NCH; ++q) {
+        r[k][q] = u16x8{};
+        if (row < ROWS && t < 9) {
+          if (row < PT) {
+            const int yy = ly[k] + A.sign * (t / 3 - 1), xx = lx[k] + A.sign * (t % 3 - 1);
+            if (ln[k] >= 0 && yy >= 0 && yy < A.H && xx >= 0 && xx < A.W)
+              r[k][q] = *reinterpret_cast<const u16x8*>(
+                  A.in + (((long long)ln[k] * A.H + yy) * A.W + xx) * A.Ck + c);
+          } else {
+            r[k][q] = *reinterpret_cast<const u16x8*>(
+                A.wt + ((long long)t * A.Cn + n0 + row - PT) * A.Ck + c);
+          }
+        }
+        c += 8;
+        if (c == A.Ck) {
+          c = 0;
+          ++t;
+        }
+      }
+    }
+  };
+  f32x16 acc[MW][NW];
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int j = 0; j < NW; ++j) acc[i][j] = f32x16{};
+  const int wpx = wave % WPX, wch = wave / WPX;
+  load(0);
+  for (int st = 0; st < S; ++st) {
+    __syncthreads();  // the previous stage's fragments have been read
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int row = tid + 256 * k;
+      if (row < ROWS) {
+        bf16s* dst = row < PT ? sa + row * CV_RS : sb + (row - PT) * CV_RS;
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) *reinterpret_cast<u16x8*>(dst + 8 * q) = r[k][q];
+      }
+    }
+    __syncthreads();
+    if (st + 1 < S) load(st + 1);
+#pragma unroll
+    for (int kk = 0; kk < CV_KST / 16; ++kk) {
+      if (st * CV_KST + 16 * kk >= KT) break;
+      u16x8 af[MW], bf[NW];
+#pragma unroll
+      for (int i = 0; i < MW; ++i)
+        af[i] = *reinterpret_cast<const u16x8*>(sa + ((wpx * MW + i) * 32 + m) * CV_RS + 16 * kk + 8 * g);
+#pragma unroll
+      for (int j = 0; j < NW; ++j)
+        bf[j] = *reinterpret_cast<const u16x8*>(sb + ((wch * NW + j) * 32 + m) * CV_RS + 16 * kk + 8 * g);
+#pragma unroll
+      for (int i = 0; i < MW; ++i)
+#pragma unroll
+        for (int j = 0; j < NW; ++j) acc[i][j] = mfma(af[i], bf[j], acc[i][j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const int col = n0 + (wch * NW + j) * 32 + m;
+    const float bias = A.bias ? A.bias[col] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < MW; ++i)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const long long px = pix0 + (wpx * MW + i) * 32 + acc_row(q, g);
+        if (px >= npix) continue;
+        float v = acc[i][j][q] + bias;
+        if (A.relu && v < 0.0f) v = 0.0f;
+        const long long o = px * A.Cn + col;
+        if (A.mask && !(bf2f(A.mask[o]) > 0.0f)) v = 0.0f;
+        A.out[o] = f2bf(v);
+      }
   }
 }
 
-// Weight gradient dW[t][ci][co] += sum_p x[p + off_t][ci] gz[p][co]: GEMM
-// with M = ci, N = co, K = pixels.  One wave per (tap, 32 ci, 32 co, chunk
-// of pixels), FP32 atomic accumulation into dW.  x has Cx channels (the
-// padded input of the first layer); only ci < Ci are real.
+// Weight gradient dW[t][ci][co] += sum_p x[p + off_t][ci] gz[p][co]: for
+// each tap a GEMM with M = ci, N = co, K = pixels.  Both operands are stored
+// pixel-major (channels contiguous) while the MFMA wants K-contiguous
+// fragments, so the pixels are staged through LDS transposed: a loading
+// thread reads an 8-pixel x 8-channel block (eight 16-byte loads), transposes
+// it in registers and writes eight 16-byte rows [channel][8 pixels]; each
+// wave then reads its fragments as single 16-byte LDS reads.
+//
+// Workgroup: 4 waves, one tap, a (32 MB) ci x (32 NB) co tile, a chunk of
+// pixels walked in stages of WG_SP = 64 (four K-steps of 16); wave w owns
+// block (w % MB, (w / MB) % NB) and the K-steps kk with kk % KS = w / (MB NB),
+// KS = 4 / (MB NB).  Partial sums go to dW with FP32 atomics.  x has Cx
+// channels (the padded input of the first layer); only ci < Ci are written.
 struct WgradArgs {
   const bf16s* x;   // [B][H][W][Cx]
   const bf16s* gz;  // [B][H][W][Co]
   float* dW;        // [9][Ci][Co]
   int B, H, W, Cx, Ci, Co, chunk;
+  int cib, cob;     // ci / co tiles per tap
 };
 
-__global__ void __launch_bounds__(64) k_wgrad(WgradArgs A) {
-  const int l = threadIdx.x, m = l & 31, g = l >> 5;
-  const int cib = (A.Ci + 31) / 32;
-  const int blk = blockIdx.y;
-  const int t = blk % 9;
-  const int ci0 = ((blk / 9) % cib) * 32;
-  const int co0 = (blk / 9 / cib) * 32;
-  const bool row_ok = ci0 + m < A.Ci;
-  const int dy = t / 3 - 1, dx = t % 3 - 1;
-  const long long npix = (long long)A.B * A.H * A.W, hw = (long long)A.H * A.W;
-  const long long p_beg = (long long)blockIdx.x * A.chunk;
-  const long long p_end = std::min<long long>(p_beg + A.chunk, npix);
-  f32x16 acc = {};
-  for (long long p0 = p_beg; p0 < p_end; p0 += 16) {
-    u16x8 a, b;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const long long p = p0 + 8 * g + e;
-      bf16s av = 0, bv = 0;
-      if (p < p_end) {
-        const int n = (int)(p / hw);
-        const int rem = (int)(p - (long long)n * hw);
-        const int y = rem / A.W, x = rem - (rem / A.W) * A.W;
-        const int yy = y + dy, xx = x + dx;
-        if (row_ok && yy >= 0 && yy < A.H && xx >= 0 && xx < A.W)
-          av = A.x[(((long long)n * A.H + yy) * A.W + xx) * A.Cx + ci0 + m];
-        bv = A.gz[p * A.Co + co0 + m];
-      }
-      a[e] = av;
-      b[e] = bv;
+constexpr int WG_SP = 64;       // pixels per stage
+constexpr int WG_RS = WG_SP + 8;  // LDS row stride (elements): 144 bytes, conflict-free reads
+
+// Pixel q = p0 + k of a stage, walked incrementally: (n, y, x).
+struct PixCursor {
+  int n, y, x;
+};
+__device__ inline PixCursor pix_at(long long p, int H, int W) {
+  const long long hw = (long long)H * W;
+  PixCursor c;
+  c.n = (int)(p / hw);
+  const int rem = (int)(p - (long long)c.n * hw);
+  c.y = rem / W;
+  c.x = rem - c.y * W;
+  return c;
+}
+__device__ inline void pix_next(PixCursor& c, int H, int W) {
+  if (++c.x == W) {
+    c.x = 0;
+    if (++c.y == H) {
+      c.y = 0;
+      ++c.n;
     }
-    acc = mfma(a, b, acc);
-  }
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int ci = ci0 + acc_row(r, g);
-    if (ci < A.Ci) atomicAdd(A.dW + ((long long)t * A.Ci + ci) * A.Co + co0 + m, acc[r]);
   }
 }
 
-// Bias gradient db[c] += sum over a chunk of 256 pixels of gz[p][c].
+// 8 x 8 transpose of 16-bit elements: out[j][k] = in[k][j].
+__device__ inline void transpose8(const u16x8* in, u16x8* out) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[j][k] = in[k][j];
+}
+
+template <int MB, int NB>
+__global__ void __launch_bounds__(256) k_wgrad(WgradArgs A) {
+  constexpr int KS = 4 / (MB * NB);
+  constexpr int XT = 4 * MB * (WG_SP / 8);  // loading threads of the x tile (8 px x 8 ch each)
+  constexpr int GT = 4 * NB * (WG_SP / 8);
+  __shared__ __attribute__((aligned(16))) bf16s sx[32 * MB * WG_RS];
+  __shared__ __attribute__((aligned(16))) bf16s sg[32 * NB * WG_RS];
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, m = l & 31, g = l >> 5;
+  int blk = blockIdx.y;
+  const int t = blk % 9;
+  blk /= 9;
+  const int ci0 = (blk % A.cib) * 32 * MB, co0 = (blk / A.cib) * 32 * NB;
+  const int dy = t / 3 - 1, dx = t % 3 - 1;
+  const long long npix = (long long)A.B * A.H * A.W;
+  const long long p_beg = (long long)xcd_tile(blockIdx.x, gridDim.x) * A.chunk;
+  const long long p_end = std::min<long long>(p_beg + A.chunk, npix);
+  // this thread's loading role: an 8-pixel group and an 8-channel group
+  const bool ldx = tid < XT, ldg = tid >= XT && tid < XT + GT;
+  const int lt = ldx ? tid : tid - XT;
+  const int pg = lt % (WG_SP / 8), cg = lt / (WG_SP / 8);
+  const int mb = wave % MB, nb = (wave / MB) % NB, ks = wave / (MB * NB);
+  u16x8 r[8];
+  auto load = [&](long long p0) {
+    const u16x8 zero = {};
+    if (!ldx && !ldg) return;
+    long long p = p0 + 8 * pg;
+    PixCursor c = pix_at(p < npix ? p : 0, A.H, A.W);
+#pragma unroll
+    for (int k = 0; k < 8; ++k, ++p) {
+      r[k] = zero;
+      if (p < p_end) {
+        if (ldx) {
+          const int ch = ci0 + 8 * cg, yy = c.y + dy, xx = c.x + dx;
+          if (ch < A.Cx && yy >= 0 && yy < A.H && xx >= 0 && xx < A.W)
+            r[k] = *reinterpret_cast<const u16x8*>(
+                A.x + (((long long)c.n * A.H + yy) * A.W + xx) * A.Cx + ch);
+        } else {
+          r[k] = *reinterpret_cast<const u16x8*>(A.gz + p * A.Co + co0 + 8 * cg);
+        }
+      }
+      pix_next(c, A.H, A.W);
+    }
+  };
+  f32x16 acc = {};
+  load(p_beg);
+  for (long long p0 = p_beg; p0 < p_end; p0 += WG_SP) {
+    __syncthreads();  // the previous stage's fragments have been read
+    if (ldx || ldg) {
+      u16x8 tr[8];
+      transpose8(r, tr);
+      bf16s* base = (ldx ? sx : sg) + (8 * cg) * WG_RS + 8 * pg;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) *reinterpret_cast<u16x8*>(base + j * WG_RS) = tr[j];
+    }
+    __syncthreads();
+    if (p0 + WG_SP < p_end) load(p0 + WG_SP);  // next stage in flight during the MFMAs
+#pragma unroll
+    for (int kk = 0; kk < WG_SP / 16; ++kk) {
+      if (kk % KS != ks) continue;
+      const u16x8 a = *reinterpret_cast<const u16x8*>(sx + (32 * mb + m) * WG_RS + 16 * kk + 8 * g);
+      const u16x8 b = *reinterpret_cast<const u16x8*>(sg + (32 * nb + m) * WG_RS + 16 * kk + 8 * g);
+      acc = mfma(a, b, acc);
+    }
+  }
+  const int co = co0 + 32 * nb + m;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int ci = ci0 + 32 * mb + acc_row(q, g);
+    if (ci < A.Ci) atomicAdd(A.dW + ((long long)t * A.Ci + ci) * A.Co + co, acc[q]);
+  }
+}
+
+// Bias gradient db[c] += sum over a chunk of pixels of gz[p][c].  Thread t
+// owns channels 8 (t % G) .. + 7 (G = C / 8, one 16-byte load per pixel) and
+// every (256 / G)-th pixel of the chunk, with four independent partial sums
+// per channel so that four loads are in flight; the partial sums meet in
+// LDS and one atomic add per channel and chunk remains.  The chunk holds
+// 64 (256 / G) pixels (64 loads per thread).  C <= 256, a multiple of 8.
 __global__ void __launch_bounds__(256) k_bgrad(const bf16s* gz, float* db, long long npix, int C) {
-  const long long p0 = (long long)blockIdx.x * 256;
-  const long long p1 = std::min<long long>(p0 + 256, npix);
-  for (int c = threadIdx.x; c < C; c += 256) {
-    float s = 0.0f;
-    for (long long p = p0; p < p1; ++p) s += bf2f(gz[p * C + c]);
-    atomicAdd(db + c, s);
+  __shared__ float red[256 * 8];
+  const int G = C / 8, nq = 256 / G;
+  const int cg = threadIdx.x % G, q = threadIdx.x / G;
+  const long long chunk = 64LL * nq;
+  const long long p0 = (long long)blockIdx.x * chunk;
+  const long long p1 = std::min<long long>(p0 + chunk, npix);
+  float s[4][8] = {};
+  if (q < nq) {
+    long long p = p0 + q;
+    for (; p + 3 * nq < p1; p += 4 * nq) {
+      u16x8 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        v[u] = *reinterpret_cast<const u16x8*>(gz + (p + u * nq) * C + 8 * cg);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[u][e] += bf2f(v[u][e]);
+    }
+    for (; p < p1; p += nq) {
+      const u16x8 v = *reinterpret_cast<const u16x8*>(gz + p * C + 8 * cg);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) s[0][e] += bf2f(v[e]);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) red[threadIdx.x * 8 + e] = (s[0][e] + s[1][e]) + (s[2][e] + s[3][e]);
+  __syncthreads();
+  if (threadIdx.x < C) {
+    const int c = threadIdx.x, g = c / 8, e = c % 8;
+    float t = 0.0f;
+    for (int k = 0; k < nq; ++k) t += red[(k * G + g) * 8 + e];
+    atomicAdd(db + c, t);
   }
 }
 
@@ -169,99 +365,108 @@ __global__ void __launch_bounds__(256) k_bgrad(const bf16s* gz, float* db, long 
 
 // FP32 [B][H][W][c_in] -> BF16 [B][H][W][16], zero channels beyond c_in.
 __global__ void k_input(const float* x, bf16s* out, long long npix, int c_in) {
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= npix * 16) return;
-  const long long p = k >> 4;
-  const int c = (int)(k & 15);
-  out[k] = c < c_in ? f2bf(x[p * c_in + c]) : (bf16s)0;
+  const unsigned p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  u16x8 o[2];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) o[c >> 3][c & 7] = c < c_in ? f2bf(x[(long long)p * c_in + c]) : (bf16s)0;
+  *reinterpret_cast<u16x8*>(out + 16LL * p) = o[0];
+  *reinterpret_cast<u16x8*>(out + 16LL * p + 8) = o[1];
 }
+
+// The glue kernels below move 8 channels (16 bytes) per thread and index
+// with 32-bit arithmetic (the plan bounds every tensor below 2^31 vectors).
 
 // 2x2 average pooling: out [B][H/2][W/2][C].
 __global__ void k_pool(const bf16s* in, bf16s* out, int B, int H, int W, int C) {
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int h = H / 2, w = W / 2;
-  const long long total = (long long)B * h * w * C;
-  if (k >= total) return;
-  const int c = (int)(k % C);
-  long long q = k / C;
-  const int x = (int)(q % w);
-  q /= w;
-  const int y = (int)(q % h);
-  const int n = (int)(q / h);
-  const long long b = (((long long)n * H + 2 * y) * W + 2 * x) * C + c;
-  const float s = bf2f(in[b]) + bf2f(in[b + C]) + bf2f(in[b + (long long)W * C]) +
-                  bf2f(in[b + (long long)W * C + C]);
-  out[k] = f2bf(0.25f * s);
+  const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned G = C / 8, h = H / 2, w = W / 2;
+  if (v >= (unsigned)B * h * w * G) return;
+  const unsigned cg = v % G, q = v / G, x = q % w, r = q / w, y = r % h, n = r / h;
+  const long long b = (((long long)n * H + 2 * y) * W + 2 * x) * C + 8 * cg;
+  const u16x8 a = *reinterpret_cast<const u16x8*>(in + b);
+  const u16x8 c = *reinterpret_cast<const u16x8*>(in + b + C);
+  const u16x8 d = *reinterpret_cast<const u16x8*>(in + b + (long long)W * C);
+  const u16x8 e = *reinterpret_cast<const u16x8*>(in + b + (long long)W * C + C);
+  u16x8 o;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) o[k] = f2bf(0.25f * (bf2f(a[k]) + bf2f(c[k]) + bf2f(d[k]) + bf2f(e[k])));
+  *reinterpret_cast<u16x8*>(out + 8LL * v) = o;
 }
 
 // Gradient into an encoder output e [B][H][W][C]: a quarter of the pooled
 // gradient of its 2x2 parent plus the skip gradient, zeroed where e <= 0.
 __global__ void k_pool_back(const bf16s* gp, const bf16s* gskip, const bf16s* e, bf16s* ge,
                             int B, int H, int W, int C) {
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long total = (long long)B * H * W * C;
-  if (k >= total) return;
-  const int c = (int)(k % C);
-  long long q = k / C;
-  const int x = (int)(q % W);
-  q /= W;
-  const int y = (int)(q % H);
-  const int n = (int)(q / H);
-  const float v = 0.25f * bf2f(gp[(((long long)n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c]) +
-                  bf2f(gskip[k]);
-  ge[k] = bf2f(e[k]) > 0.0f ? f2bf(v) : (bf16s)0;
+  const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned G = C / 8;
+  if (v >= (unsigned)B * H * W * G) return;
+  const unsigned cg = v % G, q = v / G, x = q % W, r = q / W, y = r % H, n = r / H;
+  const u16x8 pg = *reinterpret_cast<const u16x8*>(
+      gp + (((long long)n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + 8 * cg);
+  const u16x8 sk = *reinterpret_cast<const u16x8*>(gskip + 8LL * v);
+  const u16x8 ev = *reinterpret_cast<const u16x8*>(e + 8LL * v);
+  u16x8 o;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float t = 0.25f * bf2f(pg[k]) + bf2f(sk[k]);
+    o[k] = bf2f(ev[k]) > 0.0f ? f2bf(t) : (bf16s)0;
+  }
+  *reinterpret_cast<u16x8*>(ge + 8LL * v) = o;
 }
 
 // cat [B][H][W][Cu + Cs] = (nearest 2x upsample of u [B][H/2][W/2][Cu], s).
 __global__ void k_upcat(const bf16s* u, const bf16s* s, bf16s* cat, int B, int H, int W, int Cu,
                         int Cs) {
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int C = Cu + Cs;
-  const long long total = (long long)B * H * W * C;
-  if (k >= total) return;
-  const int c = (int)(k % C);
-  const long long p = k / C;
-  if (c < Cs + Cu && c >= Cu) {
-    cat[k] = s[p * Cs + (c - Cu)];
-    return;
+  const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned G = (Cu + Cs) / 8, Gu = Cu / 8;
+  if (v >= (unsigned)B * H * W * G) return;
+  const unsigned cg = v % G, p = v / G;
+  u16x8 o;
+  if (cg >= Gu) {
+    o = *reinterpret_cast<const u16x8*>(s + (long long)p * Cs + 8 * (cg - Gu));
+  } else {
+    const unsigned x = p % W, r = p / W, y = r % H, n = r / H;
+    o = *reinterpret_cast<const u16x8*>(u + (((long long)n * (H / 2) + y / 2) * (W / 2) + x / 2) * Cu +
+                                        8 * cg);
   }
-  const int x = (int)(p % W);
-  const long long q = p / W;
-  const int y = (int)(q % H);
-  const int n = (int)(q / H);
-  cat[k] = u[(((long long)n * (H / 2) + y / 2) * (W / 2) + x / 2) * Cu + c];
+  *reinterpret_cast<u16x8*>(cat + 8LL * v) = o;
 }
 
 // Backward of k_upcat: gu [B][H/2][W/2][Cu] = sum of the 2x2 children,
 // zeroed where the upsampled tensor u <= 0 (it is a ReLU output); the skip
-// part is copied to gskip [B][H][W][Cs].
+// part is copied to gskip [B][H][W][Cs].  Threads [0, nu) cover gu, the next
+// ns threads gskip (8 channels each).
 __global__ void k_upcat_back(const bf16s* gcat, const bf16s* u, bf16s* gu, bf16s* gskip, int B,
                              int H, int W, int Cu, int Cs) {
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
   const int C = Cu + Cs;
-  const int h = H / 2, w = W / 2;
-  const long long nu = (long long)B * h * w * Cu;
-  const long long ns = (long long)B * H * W * Cs;
-  if (k < nu) {
-    const int c = (int)(k % Cu);
-    long long q = k / Cu;
-    const int x = (int)(q % w);
-    q /= w;
-    const int y = (int)(q % h);
-    const int n = (int)(q / h);
-    const long long b = (((long long)n * H + 2 * y) * W + 2 * x) * C + c;
-    const float v = bf2f(gcat[b]) + bf2f(gcat[b + C]) + bf2f(gcat[b + (long long)W * C]) +
-                    bf2f(gcat[b + (long long)W * C + C]);
-    gu[k] = bf2f(u[k]) > 0.0f ? f2bf(v) : (bf16s)0;
-  } else if (k < nu + ns) {
-    const long long j = k - nu;
-    const int c = (int)(j % Cs);
-    const long long p = j / Cs;
-    gskip[j] = gcat[p * C + Cu + c];
+  const unsigned h = H / 2, w = W / 2, Gu = Cu / 8, Gs = Cs / 8;
+  const unsigned nu = (unsigned)B * h * w * Gu, ns = (unsigned)B * H * W * Gs;
+  if (v < nu) {
+    const unsigned cg = v % Gu, q = v / Gu, x = q % w, r = q / w, y = r % h, n = r / h;
+    const long long b = (((long long)n * H + 2 * y) * W + 2 * x) * C + 8 * cg;
+    const u16x8 a = *reinterpret_cast<const u16x8*>(gcat + b);
+    const u16x8 c = *reinterpret_cast<const u16x8*>(gcat + b + C);
+    const u16x8 d = *reinterpret_cast<const u16x8*>(gcat + b + (long long)W * C);
+    const u16x8 e = *reinterpret_cast<const u16x8*>(gcat + b + (long long)W * C + C);
+    const u16x8 uv = *reinterpret_cast<const u16x8*>(u + 8LL * v);
+    u16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float t = bf2f(a[k]) + bf2f(c[k]) + bf2f(d[k]) + bf2f(e[k]);
+      o[k] = bf2f(uv[k]) > 0.0f ? f2bf(t) : (bf16s)0;
+    }
+    *reinterpret_cast<u16x8*>(gu + 8LL * v) = o;
+  } else if (v < nu + ns) {
+    const unsigned j = v - nu, cg = j % Gs, p = j / Gs;
+    *reinterpret_cast<u16x8*>(gskip + 8LL * j) =
+        *reinterpret_cast<const u16x8*>(gcat + (long long)p * C + Cu + 8 * cg);
   }
 }
 
-// Head: y[p][k] = sum_c d0[p][c] Wh[c][k] + bh[k] (FP32 parameters).  With a
+// Head: y[p][k] = sum_c d0[p][c] Wh[c][k] + bh[k] (FP32 parameters, K <= 8,
+// C a multiple of 8: the row of d0 is read 16 bytes at a time).  With a
 // target: gy = 2 (y - t) / N into gy and the squared error summed into loss.
 __global__ void __launch_bounds__(256) k_head(const bf16s* d0, const float* Wh, const float* bh,
                                               float* y, const float* tgt, float* gy, double* loss,
@@ -270,12 +475,25 @@ __global__ void __launch_bounds__(256) k_head(const bf16s* d0, const float* Wh, 
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   float se = 0.0f;
   if (p < npix) {
-    for (int k = 0; k < K; ++k) {
-      float s = bh[k];
-      for (int c = 0; c < C; ++c) s += bf2f(d0[p * C + c]) * Wh[c * K + k];
-      y[p * K + k] = s;
+    float acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = k < K ? bh[k] : 0.0f;
+    for (int c0 = 0; c0 < C; c0 += 8) {
+      const u16x8 v = *reinterpret_cast<const u16x8*>(d0 + p * C + c0);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float d = bf2f(v[e]);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (k < K) acc[k] += d * Wh[(c0 + e) * K + k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k >= K) break;
+      y[p * K + k] = acc[k];
       if (tgt) {
-        const float dlt = s - tgt[p * K + k];
+        const float dlt = acc[k] - tgt[p * K + k];
         se += dlt * dlt;
         gy[p * K + k] = (float)(2.0 * inv_n) * dlt;
       }
@@ -292,40 +510,54 @@ __global__ void __launch_bounds__(256) k_head(const bf16s* d0, const float* Wh, 
 }
 
 // Head backward, input side: gd0[p][c] = (sum_k gy[p][k] Wh[c][k]) where
-// d0 > 0 (d0 is a ReLU output).
+// d0 > 0 (d0 is a ReLU output); 8 channels per 16-byte load and store.
 __global__ void __launch_bounds__(256) k_head_back(const bf16s* d0, const float* gy,
                                                    const float* Wh, bf16s* gd0, long long npix,
                                                    int C, int K) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npix) return;
-  for (int c = 0; c < C; ++c) {
-    float s = 0.0f;
-    for (int k = 0; k < K; ++k) s += gy[p * K + k] * Wh[c * K + k];
-    gd0[p * C + c] = bf2f(d0[p * C + c]) > 0.0f ? f2bf(s) : (bf16s)0;
+  float g[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) g[k] = k < K ? gy[p * K + k] : 0.0f;
+  for (int c0 = 0; c0 < C; c0 += 8) {
+    const u16x8 v = *reinterpret_cast<const u16x8*>(d0 + p * C + c0);
+    u16x8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float s = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k < K) s += g[k] * Wh[(c0 + e) * K + k];
+      o[e] = bf2f(v[e]) > 0.0f ? f2bf(s) : (bf16s)0;
+    }
+    *reinterpret_cast<u16x8*>(gd0 + p * C + c0) = o;
   }
 }
 
-// Head backward, parameter side: block c < C sums dWh[c][k] = sum_p d0[p][c]
-// gy[p][k], block C sums dbh[k] = sum_p gy[p][k] (K <= 8).
+// Head backward, parameter side, over a chunk of 64 pixels per workgroup:
+// the chunk's d0 rows and gy rows are staged in LDS, thread t < C K sums
+// dWh[c][k] (c = t / K, k = t % K) and the next K threads dbh[k] over the
+// chunk, then one atomic add each.  C <= 256, K <= 8.
 __global__ void __launch_bounds__(256) k_head_wgrad(const bf16s* d0, const float* gy, float* dWh,
                                                     float* dbh, long long npix, int C, int K) {
-  __shared__ float red[8][256];
-  const int c = blockIdx.x;
-  float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (long long p = threadIdx.x; p < npix; p += blockDim.x) {
-    const float d = c < C ? bf2f(d0[p * C + c]) : 1.0f;
-    for (int k = 0; k < K; ++k) acc[k] += d * gy[p * K + k];
-  }
-  for (int k = 0; k < K; ++k) red[k][threadIdx.x] = acc[k];
+  __shared__ bf16s sd[64 * 256];
+  __shared__ float sg[64 * 8];
+  const long long p0 = (long long)blockIdx.x * 64;
+  const int n = (int)std::min<long long>(64, npix - p0);
+  for (int e = threadIdx.x; e < n * C; e += 256) sd[e] = d0[p0 * C + e];
+  for (int e = threadIdx.x; e < n * K; e += 256) sg[e] = gy[p0 * K + e];
   __syncthreads();
-  for (int sz = 128; sz > 0; sz >>= 1) {
-    if (threadIdx.x < sz)
-      for (int k = 0; k < K; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + sz];
-    __syncthreads();
-  }
-  if (threadIdx.x < K) {
-    if (c < C) dWh[c * K + threadIdx.x] = red[threadIdx.x][0];
-    else dbh[threadIdx.x] = red[threadIdx.x][0];
+  for (int t = threadIdx.x; t < C * K + K; t += 256) {
+    float acc = 0.0f;
+    if (t < C * K) {
+      const int c = t / K, k = t % K;
+      for (int q = 0; q < n; ++q) acc += bf2f(sd[q * C + c]) * sg[q * K + k];
+      atomicAdd(dWh + c * K + k, acc);
+    } else {
+      const int k = t - C * K;
+      for (int q = 0; q < n; ++q) acc += sg[q * K + k];
+      atomicAdd(dbh + k, acc);
+    }
   }
 }
 
@@ -538,8 +770,12 @@ lbaxi_status validate(const lbnn_desc* d) {
   if (d->c_in < 1 || d->c_in > 16) return nfail(LBAXI_EINVAL, "c_in must be in 1..16");
   if (d->c_out < 1 || d->c_out > 8) return nfail(LBAXI_EINVAL, "c_out must be in 1..8");
   for (int k = 0; k < 4; ++k)
-    if (d->widths[k] < 32 || d->widths[k] % 32) return nfail(LBAXI_EINVAL, "widths must be multiples of 32");
+    if (d->widths[k] < 32 || d->widths[k] > 256 || d->widths[k] % 32)
+      return nfail(LBAXI_EINVAL, "widths must be multiples of 32 in 32..256");
   if (d->max_batch < 1) return nfail(LBAXI_EINVAL, "max_batch must be >= 1");
+  // every tensor stays below 2^31 elements / 8-channel vectors (32-bit indexing)
+  if ((long long)d->max_batch * d->H * d->W * 512 >= (1LL << 31))
+    return nfail(LBAXI_EINVAL, "max_batch * H * W must be below 2^22");
   return LBAXI_OK;
 }
 
@@ -601,9 +837,20 @@ lbaxi_status conv(lbnn_t* h, const Conv& c, const bf16s* in, bf16s* out, int lvl
     A.relu = 0;
   }
   const long long npix = (long long)B * A.H * A.W;
-  dim3 grid(blocks(npix, 128), A.Cn / 32);
-  hipLaunchKernelGGL(k_conv, grid, dim3(256), 0, h->stream, A);
-  NCHK(hipGetLastError());
+  // 2 x 2 blocks per wave where the output width allows, else 4 x 1
+  // tile by output width: 128 x 128, 128 x 64 or 256 x 32
+  int PT, NT;
+  void* fn;
+  if (A.Cn % 128 == 0) {
+    PT = 128; NT = 128; fn = (void*)&k_conv<128, 128, 2, 2>;
+  } else if (A.Cn % 64 == 0) {
+    PT = 128; NT = 64; fn = (void*)&k_conv<128, 64, 2, 1>;
+  } else {
+    PT = 256; NT = 32; fn = (void*)&k_conv<256, 32, 2, 1>;
+  }
+  dim3 grid(blocks(npix, PT), A.Cn / NT);
+  void* args[] = {&A};
+  NCHK(hipLaunchKernel(fn, grid, dim3(256), args, 0, h->stream));
   return LBAXI_OK;
 }
 
@@ -618,12 +865,22 @@ lbaxi_status wgrad(lbnn_t* h, const Conv& c, const bf16s* x, const bf16s* gz, in
   A.Cx = c.Ck;
   A.Ci = c.ci;
   A.Co = c.co;
-  A.chunk = 1024;
+  const int MB = c.Ck >= 64 && c.Ck % 64 == 0 ? 2 : 1;
+  const int NB = c.co % 64 == 0 ? 2 : 1;
+  A.cib = (c.Ck + 32 * MB - 1) / (32 * MB);
+  A.cob = c.co / (32 * NB);
   const long long npix = (long long)B * A.H * A.W;
-  dim3 grid(blocks(npix, A.chunk), 9 * ((A.Ci + 31) / 32) * (A.Co / 32));
-  hipLaunchKernelGGL(k_wgrad, grid, dim3(64), 0, h->stream, A);
-  NCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_bgrad, dim3(blocks(npix)), dim3(256), 0, h->stream, gz,
+  const long long tiles = 9LL * A.cib * A.cob;
+  // about 2048 workgroups, each at least one and at most 64 stages long
+  long long ch = (npix * tiles + 2047) / 2048;
+  ch = std::max<long long>(WG_SP, std::min<long long>(64LL * WG_SP, ch));
+  A.chunk = (int)((ch + WG_SP - 1) / WG_SP * WG_SP);
+  dim3 grid(blocks(npix, A.chunk), (unsigned)tiles);
+  void* fn = MB == 2 ? (NB == 2 ? (void*)&k_wgrad<2, 2> : (void*)&k_wgrad<2, 1>)
+                     : (NB == 2 ? (void*)&k_wgrad<1, 2> : (void*)&k_wgrad<1, 1>);
+  void* args[] = {&A};
+  NCHK(hipLaunchKernel(fn, grid, dim3(256), args, 0, h->stream));
+  hipLaunchKernelGGL(k_bgrad, dim3(blocks(npix, 64 * (256 / (c.co / 8)))), dim3(256), 0, h->stream, gz,
                      h->grads() + c.off_b, npix, c.co);
   NCHK(hipGetLastError());
   return LBAXI_OK;
@@ -707,14 +964,14 @@ lbaxi_status lbnn_forward(lbnn_t* h, const float* d_x, float* d_y, int32_t B) {
   const int c0 = P.d.widths[0], c1 = P.d.widths[1], c2 = P.d.widths[2], c3 = P.d.widths[3];
   const int cw[4] = {c0, c1, c2, c3};
   const long long np0 = (long long)B * npix_lvl(P.d, 0);
-  hipLaunchKernelGGL(k_input, dim3(blocks(np0 * 16)), dim3(256), 0, h->stream, d_x,
+  hipLaunchKernelGGL(k_input, dim3(blocks(np0)), dim3(256), 0, h->stream, d_x,
                      h->act(P.xin), np0, P.d.c_in);
   NCHK(hipGetLastError());
   const bf16s* x = h->act(P.xin);
   for (int l = 0; l < 4; ++l) {
     if (l > 0) {
       const int Hh = P.d.H >> (l - 1), Ww = P.d.W >> (l - 1);
-      hipLaunchKernelGGL(k_pool, dim3(blocks((long long)B * (Hh / 2) * (Ww / 2) * cw[l - 1])),
+      hipLaunchKernelGGL(k_pool, dim3(blocks((long long)B * (Hh / 2) * (Ww / 2) * cw[l - 1] / 8)),
                          dim3(256), 0, h->stream, h->act(P.e_b[l - 1]), h->act(P.pool[l - 1]), B,
                          Hh, Ww, cw[l - 1]);
       NCHK(hipGetLastError());
@@ -728,7 +985,7 @@ lbaxi_status lbnn_forward(lbnn_t* h, const float* d_x, float* d_y, int32_t B) {
   const bf16s* below = h->act(P.e_b[3]);
   for (int l = 2; l >= 0; --l) {
     const int Hl = P.d.H >> l, Wl = P.d.W >> l;
-    const long long tot = (long long)B * Hl * Wl * (cw[l + 1] + cw[l]);
+    const long long tot = (long long)B * Hl * Wl * (cw[l + 1] + cw[l]) / 8;
     hipLaunchKernelGGL(k_upcat, dim3(blocks(tot)), dim3(256), 0, h->stream, below,
                        h->act(P.e_b[l]), h->act(P.cat[l]), B, Hl, Wl, cw[l + 1], cw[l]);
     NCHK(hipGetLastError());
@@ -773,7 +1030,7 @@ lbaxi_status lbnn_backward(lbnn_t* h, const float* d_target, float* d_grads, dou
   hipLaunchKernelGGL(k_head_back, dim3(blocks(np0)), dim3(256), 0, h->stream, h->act(P.d_b[0]),
                      h->at<float>(P.gy), h->params() + P.off_hW, h->act(P.gbig1[0]), np0, c0,
                      P.d.c_out);
-  hipLaunchKernelGGL(k_head_wgrad, dim3(c0 + 1), dim3(256), 0, h->stream, h->act(P.d_b[0]),
+  hipLaunchKernelGGL(k_head_wgrad, dim3(blocks(np0, 64)), dim3(256), 0, h->stream, h->act(P.d_b[0]),
                      h->at<float>(P.gy), h->grads() + P.off_hW, h->grads() + P.off_hb, np0, c0,
                      P.d.c_out);
   NCHK(hipGetLastError());
@@ -794,7 +1051,7 @@ lbaxi_status lbnn_backward(lbnn_t* h, const float* d_target, float* d_grads, dou
     const bf16s* u = l < 2 ? h->act(P.d_b[l + 1]) : h->act(P.e_b[3]);
     bf16s* gu = h->act(P.gbig1[l + 1]);
     const long long tot =
-        (long long)B * (Hl / 2) * (Wl / 2) * cw[l + 1] + (long long)B * Hl * Wl * cw[l];
+        ((long long)B * (Hl / 2) * (Wl / 2) * cw[l + 1] + (long long)B * Hl * Wl * cw[l]) / 8;
     hipLaunchKernelGGL(k_upcat_back, dim3(blocks(tot)), dim3(256), 0, h->stream,
                        h->act(P.gcat[l]), u, gu, h->act(P.gskip[l]), B, Hl, Wl, cw[l + 1], cw[l]);
     NCHK(hipGetLastError());
@@ -818,7 +1075,7 @@ lbaxi_status lbnn_backward(lbnn_t* h, const float* d_target, float* d_grads, dou
     bf16s* gp = h->act(P.gbig1[l]);  // gzb is dead now
     if ((s = conv(h, ca, gza, gp, l, B, true, nullptr)) != LBAXI_OK) return s;
     const int Hh = P.d.H >> (l - 1), Ww = P.d.W >> (l - 1);
-    hipLaunchKernelGGL(k_pool_back, dim3(blocks((long long)B * Hh * Ww * cw[l - 1])), dim3(256), 0,
+    hipLaunchKernelGGL(k_pool_back, dim3(blocks((long long)B * Hh * Ww * cw[l - 1] / 8)), dim3(256), 0,
                        h->stream, gp, h->act(P.gskip[l - 1]), h->act(P.e_b[l - 1]),
                        h->act(P.gbig1[l - 1]), B, Hh, Ww, cw[l - 1]);
     NCHK(hipGetLastError());

@@ -80,6 +80,30 @@ def test_gradients_match_oracle():
     print("worst gradient", max(worst))
 
 
+@pytest.mark.parametrize("H,W,B,c_in,c_out", [(40, 72, 3, 5, 5), (128, 256, 2, 8, 5)])
+def test_forward_and_gradients_other_shapes(H, W, B, c_in, c_out):
+    """Odd level sizes (5 x 9 at the deepest level, so pixel groups straddle
+    rows), padded input channels, several pixel chunks per weight-gradient
+    workgroup, and the 128 x 256 shape of the warm start."""
+    from paper_1003_0282_amd import lbnn
+    net, p, names, x, t, xd, td = _setup(H, W, B, c_in, c_out, seed=4)
+    y = net.forward(xd).double().cpu().numpy()
+    y_ref, cache = N.forward(p, x)
+    assert _rel(y, y_ref) < 3e-2, _rel(y, y_ref)
+    loss, g = net.backward(td)
+    g_ref = N.backward(p, cache, y_ref, t)
+    assert abs(loss - N.loss(y_ref, t)) / N.loss(y_ref, t) < 3e-2
+    gd = lbnn.unflatten(g.double().cpu().numpy(), N.layer_shapes(c_in, WIDTHS, c_out))
+    worst = []
+    for name in names:
+        a, b = gd[name].reshape(-1), g_ref[name].reshape(-1)
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+        rel = _rel(a, b)
+        worst.append((rel, cos, name))
+        assert cos > 0.99 and rel < 0.15, (name, cos, rel)
+    print("worst gradient", max(worst))
+
+
 def test_training_reduces_loss():
     import torch
     net, p, names, x, t, xd, td = _setup(seed=2)
