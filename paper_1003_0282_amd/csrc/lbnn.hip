@@ -200,8 +200,9 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs A) {
 // wave then reads its fragments as single 16-byte LDS reads.
 //
 // Workgroup: 4 waves, one tap, a (32 MB) ci x (32 NB) co tile, a chunk of
-// pixels walked in stages of WG_SP = 64 (four K-steps of 16); wave w owns
-// block (w % MB, (w / MB) % NB) and the K-steps kk with kk % KS = w / (MB NB),
+// pixels walked in stages of SP = wg_sp(MB, NB) pixels (SP / 16 K-steps, as
+// many as the 256 threads can load in one round); wave w owns block
+// (w % MB, (w / MB) % NB) and the K-steps kk with kk % KS = w / (MB NB),
 // KS = 4 / (MB NB).  Partial sums go to dW with FP32 atomics.  x has Cx
 // channels (the padded input of the first layer); only ci < Ci are written.
 struct WgradArgs {
@@ -212,8 +213,8 @@ struct WgradArgs {
   int cib, cob;     // ci / co tiles per tap
 };
 
-constexpr int WG_SP = 64;       // pixels per stage
-constexpr int WG_RS = WG_SP + 8;  // LDS row stride (elements): 144 bytes, conflict-free reads
+// Pixels per stage: the x and g tiles take (MB + NB) SP / 2 loading threads.
+__host__ __device__ constexpr int wg_sp(int mb, int nb) { return mb + nb == 2 ? 256 : 128; }
 
 // Pixel q = p0 + k of a stage, walked incrementally: (n, y, x).
 struct PixCursor {
@@ -249,8 +250,11 @@ __device__ inline void transpose8(const u16x8* in, u16x8* out) {
 template <int MB, int NB>
 __global__ void __launch_bounds__(256) k_wgrad(WgradArgs A) {
   constexpr int KS = 4 / (MB * NB);
+  constexpr int WG_SP = wg_sp(MB, NB);
+  constexpr int WG_RS = WG_SP + 8;          // LDS row stride: an odd multiple of 16 bytes
   constexpr int XT = 4 * MB * (WG_SP / 8);  // loading threads of the x tile (8 px x 8 ch each)
   constexpr int GT = 4 * NB * (WG_SP / 8);
+  static_assert(XT + GT <= 256, "one load round per stage");
   __shared__ __attribute__((aligned(16))) bf16s sx[32 * MB * WG_RS];
   __shared__ __attribute__((aligned(16))) bf16s sg[32 * NB * WG_RS];
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, m = l & 31, g = l >> 5;
@@ -534,28 +538,52 @@ __global__ void __launch_bounds__(256) k_head_back(const bf16s* d0, const float*
   }
 }
 
-// Head backward, parameter side, over a chunk of 64 pixels per workgroup:
-// the chunk's d0 rows and gy rows are staged in LDS, thread t < C K sums
-// dWh[c][k] (c = t / K, k = t % K) and the next K threads dbh[k] over the
-// chunk, then one atomic add each.  C <= 256, K <= 8.
+// Head backward, parameter side: dWh[c][k] = sum_p d0[p][c] gy[p][k] and
+// dbh[k] = sum_p gy[p][k].  As in k_bgrad, thread t owns channels
+// 8 (t % G) .. + 7 (one 16-byte load of d0 per pixel) and every (256 / G)-th
+// pixel of a chunk of 64 (256 / G) pixels, accumulating 8 x K products in
+// registers; the partial sums meet in LDS and one atomic add per weight and
+// chunk remains (few chunks: same-address atomics serialise).  C <= 256 a
+// multiple of 8, K <= 8.
 __global__ void __launch_bounds__(256) k_head_wgrad(const bf16s* d0, const float* gy, float* dWh,
                                                     float* dbh, long long npix, int C, int K) {
-  __shared__ bf16s sd[64 * 256];
-  __shared__ float sg[64 * 8];
-  const long long p0 = (long long)blockIdx.x * 64;
-  const int n = (int)std::min<long long>(64, npix - p0);
-  for (int e = threadIdx.x; e < n * C; e += 256) sd[e] = d0[p0 * C + e];
-  for (int e = threadIdx.x; e < n * K; e += 256) sg[e] = gy[p0 * K + e];
+  __shared__ float red[8 * 256 * 8];  // [k][thread][e]
+  __shared__ float redb[256 * 8];     // [thread][k]
+  const int G = C / 8, nq = 256 / G;
+  const int cg = threadIdx.x % G, q = threadIdx.x / G;
+  const long long chunk = 64LL * nq;
+  const long long p0 = (long long)blockIdx.x * chunk;
+  const long long p1 = std::min<long long>(p0 + chunk, npix);
+  float s[8][8] = {}, sb[8] = {};
+  if (q < nq)
+    for (long long p = p0 + q; p < p1; p += nq) {
+      const u16x8 v = *reinterpret_cast<const u16x8*>(d0 + p * C + 8 * cg);
+      float gk[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) gk[k] = k < K ? gy[p * K + k] : 0.0f;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        sb[k] += gk[k];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[k][e] += bf2f(v[e]) * gk[k];
+      }
+    }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[(k * 256 + threadIdx.x) * 8 + e] = s[k][e];
+    redb[threadIdx.x * 8 + k] = cg == 0 ? sb[k] : 0.0f;
+  }
   __syncthreads();
   for (int t = threadIdx.x; t < C * K + K; t += 256) {
     float acc = 0.0f;
     if (t < C * K) {
-      const int c = t / K, k = t % K;
-      for (int q = 0; q < n; ++q) acc += bf2f(sd[q * C + c]) * sg[q * K + k];
+      const int c = t / K, k = t % K, g = c / 8, e = c % 8;
+      for (int j = 0; j < nq; ++j) acc += red[(k * 256 + j * G + g) * 8 + e];
       atomicAdd(dWh + c * K + k, acc);
     } else {
       const int k = t - C * K;
-      for (int q = 0; q < n; ++q) acc += sg[q * K + k];
+      for (int j = 0; j < nq; ++j) acc += redb[(j * G) * 8 + k];
       atomicAdd(dbh + k, acc);
     }
   }
@@ -838,13 +866,17 @@ lbaxi_status conv(lbnn_t* h, const Conv& c, const bf16s* in, bf16s* out, int lvl
   }
   const long long npix = (long long)B * A.H * A.W;
   // 2 x 2 blocks per wave where the output width allows, else 4 x 1
-  // tile by output width: 128 x 128, 128 x 64 or 256 x 32
+  // tile by output width, largest first, down to 64 x 64 while the grid
+  // would leave CUs idle (deep levels have few pixels)
   int PT, NT;
   void* fn;
-  if (A.Cn % 128 == 0) {
+  auto wgs = [&](int pt, int nt) { return (long long)blocks(npix, pt) * (A.Cn / nt); };
+  if (A.Cn % 128 == 0 && wgs(128, 128) >= 1024) {
     PT = 128; NT = 128; fn = (void*)&k_conv<128, 128, 2, 2>;
-  } else if (A.Cn % 64 == 0) {
+  } else if (A.Cn % 64 == 0 && wgs(128, 64) >= 1024) {
     PT = 128; NT = 64; fn = (void*)&k_conv<128, 64, 2, 1>;
+  } else if (A.Cn % 64 == 0) {
+    PT = 64; NT = 64; fn = (void*)&k_conv<64, 64, 1, 1>;
   } else {
     PT = 256; NT = 32; fn = (void*)&k_conv<256, 32, 2, 1>;
   }
@@ -872,9 +904,10 @@ lbaxi_status wgrad(lbnn_t* h, const Conv& c, const bf16s* x, const bf16s* gz, in
   const long long npix = (long long)B * A.H * A.W;
   const long long tiles = 9LL * A.cib * A.cob;
   // about 2048 workgroups, each at least one and at most 64 stages long
+  const int sp = wg_sp(MB, NB);
   long long ch = (npix * tiles + 2047) / 2048;
-  ch = std::max<long long>(WG_SP, std::min<long long>(64LL * WG_SP, ch));
-  A.chunk = (int)((ch + WG_SP - 1) / WG_SP * WG_SP);
+  ch = std::max<long long>(sp, std::min<long long>(64LL * sp, ch));
+  A.chunk = (int)((ch + sp - 1) / sp * sp);
   dim3 grid(blocks(npix, A.chunk), (unsigned)tiles);
   void* fn = MB == 2 ? (NB == 2 ? (void*)&k_wgrad<2, 2> : (void*)&k_wgrad<2, 1>)
                      : (NB == 2 ? (void*)&k_wgrad<1, 2> : (void*)&k_wgrad<1, 1>);
@@ -1030,7 +1063,8 @@ lbaxi_status lbnn_backward(lbnn_t* h, const float* d_target, float* d_grads, dou
   hipLaunchKernelGGL(k_head_back, dim3(blocks(np0)), dim3(256), 0, h->stream, h->act(P.d_b[0]),
                      h->at<float>(P.gy), h->params() + P.off_hW, h->act(P.gbig1[0]), np0, c0,
                      P.d.c_out);
-  hipLaunchKernelGGL(k_head_wgrad, dim3(blocks(np0, 64)), dim3(256), 0, h->stream, h->act(P.d_b[0]),
+  hipLaunchKernelGGL(k_head_wgrad, dim3(blocks(np0, 64 * (256 / (c0 / 8)))), dim3(256), 0, h->stream,
+                     h->act(P.d_b[0]),
                      h->at<float>(P.gy), h->grads() + P.off_hW, h->grads() + P.off_hb, np0, c0,
                      P.d.c_out);
   NCHK(hipGetLastError());
