@@ -191,6 +191,104 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs A) {
   }
 }
 
+// Row-segment variant (W a multiple of TW): the workgroup owns TW pixels of
+// one image row x NT output channels.  Per stage of 32 input channels it
+// stages the three input rows y - 1 .. y + 1 over x0 - 1 .. x0 + TW (a
+// one-pixel halo) and the weights of all nine taps in LDS, so every input
+// row is read from memory once per stage instead of once per tap.  The 4
+// waves form a (TW / 32) x WCH grid, each owning 32 pixels x NW blocks of 32
+// channels, and run 9 taps x 2 K-steps x NW MFMAs per stage.
+constexpr int RW_KC = 32;               // input channels per stage
+constexpr int RW_RS = RW_KC + 8;        // LDS row stride (elements): 80 bytes
+
+template <int TW, int NT>
+__global__ void __launch_bounds__(256) k_conv_row(ConvArgs A) {
+  constexpr int WPX = TW / 32, WCH = 4 / WPX, NW = NT / (32 * WCH);
+  static_assert(WPX * WCH == 4 && NW * 32 * WCH == NT, "wave grid");
+  constexpr int HX = TW + 2;                      // halo row length (pixels)
+  constexpr int NH = 3 * HX * (RW_KC / 8);        // 16-byte loads of the halo
+  constexpr int NWT = 9 * NT * (RW_KC / 8);       // 16-byte loads of the weights
+  constexpr int LPT = (NH + NWT + 255) / 256;
+  __shared__ __attribute__((aligned(16))) bf16s sh[3 * HX * RW_RS];
+  __shared__ __attribute__((aligned(16))) bf16s sw[9 * NT * RW_RS];
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, m = l & 31, g = l >> 5;
+  const int wp = wave % WPX, wc = wave / WPX;
+  const int segs = A.W / TW;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int seg = tile % segs, rowi = tile / segs;  // rowi = n * H + y
+  const int n = rowi / A.H, y = rowi - n * A.H, x0 = seg * TW;
+  const int n0 = blockIdx.y * NT;
+  const int S = (A.Ck + RW_KC - 1) / RW_KC;
+  u16x8 r[LPT];
+  auto load = [&](int st) {
+    const int c0 = st * RW_KC;
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) {
+      const int e = tid + 256 * k;
+      r[k] = u16x8{};
+      if (e < NH) {
+        const int hr = e / (HX * 4), rem = e - hr * (HX * 4), hx = rem >> 2, q = rem & 3;
+        const int yy = y + hr - 1, xx = x0 + hx - 1, c = c0 + 8 * q;
+        if (c < A.Ck && yy >= 0 && yy < A.H && xx >= 0 && xx < A.W)
+          r[k] = *reinterpret_cast<const u16x8*>(
+              A.in + (((long long)n * A.H + yy) * A.W + xx) * A.Ck + c);
+      } else if (e < NH + NWT) {
+        const int f = e - NH, t = f / (NT * 4), rem = f - t * (NT * 4), nn = rem >> 2, q = rem & 3;
+        const int c = c0 + 8 * q;
+        if (c < A.Ck)
+          r[k] = *reinterpret_cast<const u16x8*>(A.wt + ((long long)t * A.Cn + n0 + nn) * A.Ck + c);
+      }
+    }
+  };
+  f32x16 acc[NW];
+#pragma unroll
+  for (int j = 0; j < NW; ++j) acc[j] = f32x16{};
+  load(0);
+  for (int st = 0; st < S; ++st) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) {
+      const int e = tid + 256 * k;
+      if (e < NH)
+        *reinterpret_cast<u16x8*>(sh + (e >> 2) * RW_RS + 8 * (e & 3)) = r[k];
+      else if (e < NH + NWT)
+        *reinterpret_cast<u16x8*>(sw + ((e - NH) >> 2) * RW_RS + 8 * ((e - NH) & 3)) = r[k];
+    }
+    __syncthreads();
+    if (st + 1 < S) load(st + 1);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int dy = A.sign * (t / 3 - 1), dx = A.sign * (t % 3 - 1);
+      const bf16s* ap = sh + ((1 + dy) * HX + 1 + 32 * wp + m + dx) * RW_RS + 8 * g;
+#pragma unroll
+      for (int kk = 0; kk < RW_KC / 16; ++kk) {
+        if (st * RW_KC + 16 * kk >= A.Ck) break;
+        const u16x8 a = *reinterpret_cast<const u16x8*>(ap + 16 * kk);
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+          const bf16s* bp = sw + (t * NT + (wc * NW + j) * 32 + m) * RW_RS + 8 * g + 16 * kk;
+          acc[j] = mfma(a, *reinterpret_cast<const u16x8*>(bp), acc[j]);
+        }
+      }
+    }
+  }
+  const long long prow = (long long)rowi * A.W + x0 + 32 * wp;
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const int col = n0 + (wc * NW + j) * 32 + m;
+    const float bias = A.bias ? A.bias[col] : 0.0f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const long long px = prow + acc_row(q, g);
+      float v = acc[j][q] + bias;
+      if (A.relu && v < 0.0f) v = 0.0f;
+      const long long o = px * A.Cn + col;
+      if (A.mask && !(bf2f(A.mask[o]) > 0.0f)) v = 0.0f;
+      A.out[o] = f2bf(v);
+    }
+  }
+}
+
 // Weight gradient dW[t][ci][co] += sum_p x[p + off_t][ci] gz[p][co]: for
 // each tap a GEMM with M = ci, N = co, K = pixels.  Both operands are stored
 // pixel-major (channels contiguous) while the MFMA wants K-contiguous
@@ -866,8 +964,31 @@ lbaxi_status conv(lbnn_t* h, const Conv& c, const bf16s* in, bf16s* out, int lvl
   }
   const long long npix = (long long)B * A.H * A.W;
   // 2 x 2 blocks per wave where the output width allows, else 4 x 1
-  // tile by output width, largest first, down to 64 x 64 while the grid
-  // would leave CUs idle (deep levels have few pixels)
+  // Image rows wide enough for a row segment: the halo variant (every input
+  // row read once per stage rather than once per tap).
+  {
+    void* rf = nullptr;
+    int tw = 0, nt = 0;
+    if (A.W % 128 == 0 && A.Cn % 64 == 0) {
+      rf = (void*)&k_conv_row<128, 64>; tw = 128; nt = 64;
+    } else if (A.W % 128 == 0 && A.Cn % 32 == 0) {
+      rf = (void*)&k_conv_row<128, 32>; tw = 128; nt = 32;
+    } else if (A.W % 64 == 0 && A.Cn % 128 == 0) {
+      rf = (void*)&k_conv_row<64, 128>; tw = 64; nt = 128;
+    } else if (A.W % 64 == 0 && A.Cn % 64 == 0) {
+      rf = (void*)&k_conv_row<64, 64>; tw = 64; nt = 64;
+    } else if (A.W % 32 == 0 && A.Cn % 128 == 0) {
+      rf = (void*)&k_conv_row<32, 128>; tw = 32; nt = 128;
+    }
+    if (rf) {
+      dim3 grid((unsigned)((long long)B * A.H * (A.W / tw)), A.Cn / nt);
+      void* args[] = {&A};
+      NCHK(hipLaunchKernel(rf, grid, dim3(256), args, 0, h->stream));
+      return LBAXI_OK;
+    }
+  }
+  // otherwise a flat pixel tile, largest first, down to 64 x 64 while the
+  // grid would leave CUs idle
   int PT, NT;
   void* fn;
   auto wgs = [&](int pt, int nt) { return (long long)blocks(npix, pt) * (A.Cn / nt); };
