@@ -420,6 +420,104 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs A) {
   }
 }
 
+// Row-segment weight gradient (W a multiple of WR_TW): a workgroup owns a
+// 32 ci x 32 co tile and a run of row segments of WR_TW pixels.  Per segment
+// it stages, transposed to [channel][pixel] (8 x 8 register transposes, rows
+// padded to an odd multiple of 16 bytes), the three input rows y - 1 .. y + 1
+// over x0 - 8 .. x0 + WR_TW + 7 (zero outside the image) and the gradient row
+// y over x0 .. x0 + WR_TW - 1; all nine taps then read the same staged rows,
+// the tap's x shift being an offset into the row (one 16-byte LDS read for
+// dx = 0, eight 2-byte reads otherwise).  Wave w owns the taps t = w mod 4
+// over all WR_TW / 16 K-steps; one atomic add per weight and workgroup.
+constexpr int WR_TW = 128;                 // pixels per row segment
+constexpr int WR_XS = WR_TW + 16 + 8;      // x row: 8-pixel pads each side + 8 (152 el.)
+constexpr int WR_GS = WR_TW + 8;           // g row stride (136 elements)
+
+__global__ void __launch_bounds__(256) k_wgrad_row(WgradArgs A) {
+  constexpr int XG = WR_TW / 8 + 2;            // 8-pixel groups of an x row (with pads)
+  constexpr int NXB = 3 * XG * 4;              // 8 x 8 blocks of the x rows (32 ci)
+  constexpr int NGB = (WR_TW / 8) * 4;         // 8 x 8 blocks of the g row (32 co)
+  __shared__ __attribute__((aligned(16))) bf16s sx[3 * 32 * WR_XS];
+  __shared__ __attribute__((aligned(16))) bf16s sg[32 * WR_GS];
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, m = l & 31, g = l >> 5;
+  const int blk = blockIdx.y;
+  const int ci0 = (blk % A.cib) * 32, co0 = (blk / A.cib) * 32;
+  const int segs = A.W / WR_TW;
+  const long long nseg = (long long)A.B * A.H * segs;
+  const long long s_beg = (long long)xcd_tile(blockIdx.x, gridDim.x) * A.chunk;
+  const long long s_end = std::min<long long>(s_beg + A.chunk, nseg);
+  f32x16 acc[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) acc[k] = f32x16{};
+  const u16x8 zero = {};
+  for (long long sgi = s_beg; sgi < s_end; ++sgi) {
+    const int seg = (int)(sgi % segs);
+    const long long rowi = sgi / segs;
+    const int n = (int)(rowi / A.H), y = (int)(rowi - (long long)n * A.H), x0 = seg * WR_TW;
+    __syncthreads();  // the previous segment's fragments have been read
+    for (int b = tid; b < NXB + NGB; b += 256) {
+      u16x8 v[8], tv[8];
+      if (b < NXB) {
+        const int hr = b / (XG * 4), rem = b - hr * (XG * 4), xg = rem >> 2, cg = rem & 3;
+        const int yy = y + hr - 1, ch = ci0 + 8 * cg;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int xx = x0 - 8 + 8 * xg + k;
+          v[k] = (ch < A.Cx && yy >= 0 && yy < A.H && xx >= 0 && xx < A.W)
+                     ? *reinterpret_cast<const u16x8*>(
+                           A.x + (((long long)n * A.H + yy) * A.W + xx) * A.Cx + ch)
+                     : zero;
+        }
+        transpose8(v, tv);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          *reinterpret_cast<u16x8*>(sx + (hr * 32 + 8 * cg + j) * WR_XS + 8 * xg) = tv[j];
+      } else {
+        const int f = b - NXB, xg = f >> 2, cg = f & 3;
+        const long long p = rowi * A.W + x0 + 8 * xg;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          v[k] = *reinterpret_cast<const u16x8*>(A.gz + (p + k) * A.Co + co0 + 8 * cg);
+        transpose8(v, tv);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          *reinterpret_cast<u16x8*>(sg + (8 * cg + j) * WR_GS + 8 * xg) = tv[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < WR_TW / 16; ++kk) {
+      const u16x8 bfr = *reinterpret_cast<const u16x8*>(sg + m * WR_GS + 16 * kk + 8 * g);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int t = wave + 4 * k;
+        if (t >= 9) break;
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        const bf16s* ap = sx + ((1 + dy) * 32 + m) * WR_XS + 8 + 16 * kk + 8 * g + dx;
+        u16x8 afr;
+        if (dx == 0) {
+          afr = *reinterpret_cast<const u16x8*>(ap);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) afr[e] = ap[e];
+        }
+        acc[k] = mfma(afr, bfr, acc[k]);
+      }
+    }
+  }
+  const int co = co0 + m;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int t = wave + 4 * k;
+    if (t >= 9) break;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int ci = ci0 + acc_row(q, g);
+      if (ci < A.Ci) atomicAdd(A.dW + ((long long)t * A.Ci + ci) * A.Co + co, acc[k][q]);
+    }
+  }
+}
+
 // Bias gradient db[c] += sum over a chunk of pixels of gz[p][c].  Thread t
 // owns channels 8 (t % G) .. + 7 (G = C / 8, one 16-byte load per pixel) and
 // every (256 / G)-th pixel of the chunk, with four independent partial sums
@@ -1018,11 +1116,24 @@ lbaxi_status wgrad(lbnn_t* h, const Conv& c, const bf16s* x, const bf16s* gz, in
   A.Cx = c.Ck;
   A.Ci = c.ci;
   A.Co = c.co;
+  const long long npix = (long long)B * A.H * A.W;
+  if (A.W % WR_TW == 0 && c.co % 64 != 0) {
+    // narrow outputs on wide rows: row segments, every input row staged once
+    // for all nine taps
+    A.cib = (c.Ck + 31) / 32;
+    A.cob = c.co / 32;
+    const long long nseg = (long long)B * A.H * (A.W / WR_TW);
+    const long long tiles = (long long)A.cib * A.cob;
+    // about 1024 workgroups, each at least 4 segments long
+    A.chunk = (int)std::max<long long>(4, (nseg * tiles + 1023) / 1024);
+    dim3 grid((unsigned)((nseg + A.chunk - 1) / A.chunk), (unsigned)tiles);
+    void* args[] = {&A};
+    NCHK(hipLaunchKernel((void*)&k_wgrad_row, grid, dim3(256), args, 0, h->stream));
+  } else {
   const int MB = c.Ck >= 64 && c.Ck % 64 == 0 ? 2 : 1;
   const int NB = c.co % 64 == 0 ? 2 : 1;
   A.cib = (c.Ck + 32 * MB - 1) / (32 * MB);
   A.cob = c.co / (32 * NB);
-  const long long npix = (long long)B * A.H * A.W;
   const long long tiles = 9LL * A.cib * A.cob;
   // about 2048 workgroups, each at least one and at most 64 stages long
   const int sp = wg_sp(MB, NB);
@@ -1034,6 +1145,7 @@ lbaxi_status wgrad(lbnn_t* h, const Conv& c, const bf16s* x, const bf16s* gz, in
                      : (NB == 2 ? (void*)&k_wgrad<1, 2> : (void*)&k_wgrad<1, 1>);
   void* args[] = {&A};
   NCHK(hipLaunchKernel(fn, grid, dim3(256), args, 0, h->stream));
+  }
   hipLaunchKernelGGL(k_bgrad, dim3(blocks(npix, 64 * (256 / (c.co / 8)))), dim3(256), 0, h->stream, gz,
                      h->grads() + c.off_b, npix, c.co);
   NCHK(hipGetLastError());
