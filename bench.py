@@ -181,14 +181,14 @@ def sequential_probe(steps: int):
 def warmstart_probe():
     """Time to the Eq. (57) residual 1e-8 of 16 held-out 128 x 256 melts
     (wet-node walls, FP32 storage) from rest and from the learned warm start,
-    with the network trained here on 128 solver-generated steady fields; the
+    with the network trained here on 256 solver-generated steady fields; the
     distance of both end states to FP64 reference fields (residual 1e-10)."""
     import numpy as np
     from paper_1003_0282_amd import warmstart as WS
     t0 = time.perf_counter()
-    r = WS.experiment(n_train=128, n_eval=16, nr=128, nz=256, re_max=1000.0, tol=1e-8,
-                      gen_steps=1_000_000, eval_steps=2_000_000, train_steps=2500, batch=8,
-                      lr=1e-3, gen_budget_s=150, train_budget_s=40, eval_budget_s=100,
+    r = WS.experiment(n_train=256, n_eval=16, nr=128, nz=256, re_max=1000.0, tol=1e-8,
+                      gen_steps=1_000_000, eval_steps=2_000_000, train_steps=5000, batch=8,
+                      lr=1e-3, gen_budget_s=200, train_budget_s=60, eval_budget_s=100,
                       ref_budget_s=100, wet=True,
                       log=lambda m: print(m, file=sys.stderr, flush=True))
     e, n = r["eval"], r["eval"]["nn_smooth"]
