@@ -1071,8 +1071,6 @@ lbaxi_status conv(lbnn_t* h, const Conv& c, const bf16s* in, bf16s* out, int lvl
       rf = (void*)&k_conv_row<128, 64>; tw = 128; nt = 64;
     } else if (A.W % 128 == 0 && A.Cn % 32 == 0) {
       rf = (void*)&k_conv_row<128, 32>; tw = 128; nt = 32;
-    } else if (A.W % 64 == 0 && A.Cn % 128 == 0) {
-      rf = (void*)&k_conv_row<64, 128>; tw = 64; nt = 128;
     } else if (A.W % 64 == 0 && A.Cn % 64 == 0) {
       rf = (void*)&k_conv_row<64, 64>; tw = 64; nt = 64;
     } else if (A.W % 32 == 0 && A.Cn % 128 == 0) {
