@@ -58,6 +58,13 @@ def test_nn_workspace_and_validation():
     assert b.value > 4 * 4 * 1.9e6
     d.widths[1] = 48
     assert lbnn._L.lbnn_workspace_bytes(C2.byref(d), C2.byref(b)) == -1
+    d.widths[1] = 288  # a multiple of 32 above the 256 the kernels stage
+    assert lbnn._L.lbnn_workspace_bytes(C2.byref(d), C2.byref(b)) == -1
+    d.widths[1] = 64
+    d.max_batch = 128  # 128 x 128 x 256 pixels: the 32-bit indexing bound
+    assert lbnn._L.lbnn_workspace_bytes(C2.byref(d), C2.byref(b)) == -1
+    d.max_batch = 127
+    assert lbnn._L.lbnn_workspace_bytes(C2.byref(d), C2.byref(b)) == 0
 
 
 def test_desc_layout(L):
