@@ -26,6 +26,11 @@
  *   node_macros  Eqs. (14)-(17) with mu -> mu0, body force added to F_i
  *   node_source  Eq. (12) (+ centrifugal force rho0 u_th^2 / r, Sec. III C)
  *   node_collide Eq. (13) for f, Eq. (53) for g, its analogue for h
+ *   mrt_basis, mrt_source_moments, node_collide_f_mrt
+ *                the MRT model of Sec. III B: moments Eq. (38)-(39),
+ *                collision Eq. (41) on f-bar = f - S/2 (Eq. 40), source
+ *                Eq. (51) plus the mass source, momentum rows modified by
+ *                Eqs. (49)-(50); macros are Eqs. (16)-(17) with f-bar
  *   stream       the left-hand side of Eq. (13) / (53): pull streaming, with
  *                periodic ends, specular reflection on the axis (Sec. IV A),
  *                halfway bounce-back / moving walls, free slip
@@ -99,6 +104,9 @@ typedef struct {
   double gbeta, T_ref;      /* Boussinesq buoyancy rho0*g*beta*(T - T_ref) */
   orc_side side[4];         /* 0 south (r = r0 - 1/2 or axis), 1 north,
                                2 west (z = -1/2), 3 east (z = nz - 1/2) */
+  int mrt;                  /* 1: f collides with the MRT model (Sec. III B) */
+  double s_e, s_eps, s_q;   /* MRT rates of e, epsilon and q (s_v = 1/(tau+1/2)) */
+  double s_rho, s_j;        /* rates of the conserved moments (they drop out) */
 } orc_params;
 
 typedef struct {
@@ -206,18 +214,37 @@ void orc_node_macros(const orc_params* p, int j, int64_t t, const double* fh,
   out[4] = T;
 }
 
-/* Eq. (12): S_a = [(e_ai - u_i) F_i / (rho cs^2) - u_r / r] f_eq_a with
- * F_r = -2 mu0 u_r / r^2 + rho0 u_th^2 / r and F_z = a(t) (+ buoyancy). */
-void orc_node_source(const orc_params* p, int j, int64_t t, const double* m,
-                     const double* feq, double* S) {
+/* Force of Eq. (12) at a node with macros m: F_z = a(t) (+ buoyancy) and
+ * F_r = -2 mu0 u_r / r^2 + rho0 u_th^2 / r. */
+static void node_force(const orc_params* p, int j, int64_t t, const double* m,
+                       double* Fz, double* Fr) {
   double ir = inv_r(p, j);
   double mu0 = p->rho0 * p->tau / 3.0;
+  double uz = m[1], ur = m[2], uth = m[3], T = m[4];
+  (void)uz;
+  *Fz = orc_force_a(p, t);
+  if (p->thermal) *Fz += p->rho0 * p->gbeta * (T - p->T_ref);
+  *Fr = -2.0 * mu0 * ur * ir * ir;
+  if (p->swirl) *Fr += p->rho0 * uth * uth * ir;
+}
+
+static void node_source_mrt(const orc_params* p, int j, int64_t t,
+                            const double* m, const double* feq, double* S);
+
+/* Eq. (12): S_a = [(e_ai - u_i) F_i / (rho cs^2) - u_r / r] f_eq_a with
+ * F_r = -2 mu0 u_r / r^2 + rho0 u_th^2 / r and F_z = a(t) (+ buoyancy).
+ * With the MRT model the source is the one of Sec. III B instead. */
+void orc_node_source(const orc_params* p, int j, int64_t t, const double* m,
+                     const double* feq, double* S) {
+  if (p->mrt) {
+    node_source_mrt(p, j, t, m, feq, S);
+    return;
+  }
+  double ir = inv_r(p, j);
   const double cs2 = 1.0 / 3.0;
-  double rho = m[0], uz = m[1], ur = m[2], uth = m[3], T = m[4];
-  double Fz = orc_force_a(p, t);
-  if (p->thermal) Fz += p->rho0 * p->gbeta * (T - p->T_ref);
-  double Fr = -2.0 * mu0 * ur * ir * ir;
-  if (p->swirl) Fr += p->rho0 * uth * uth * ir;
+  double rho = m[0], uz = m[1], ur = m[2];
+  double Fz, Fr;
+  node_force(p, j, t, m, &Fz, &Fr);
   for (int a = 0; a < 9; ++a) {
     double eF = (EZ9[a] - uz) * Fz + (ER9[a] - ur) * Fr;
     S[a] = (eF / (rho * cs2) - ur * ir) * feq[a];
@@ -236,22 +263,123 @@ static void node_axis_g(const orc_params* p, int64_t t, const double* f1,
   for (int a = 0; a < 4; ++a) g0[a] = g1[a] - geq1[a];
 }
 
-/* Eq. (13) for f, Eq. (53) for g and the analogous rule for h, at one node.
- * Inputs are the pre-collision populations (g already axis-substituted);
- * outputs are the post-collision populations and the macros m[5].          */
+/* ---- MRT collision (Sec. III B) ----------------------------------------------
+ * The moments of Eq. (38) with x = r and y = z (the paper pairs (r, z) with
+ * (x, y)).  Row k of M is a polynomial in the velocity components evaluated on
+ * the nine D2Q9 velocities:
+ *   rho  1                      e    -4 + 3|e|^2
+ *   eps  4 - 21|e|^2/2 + 9|e|^4/2
+ *   j_x  e_x                    q_x  (-5 + 3|e|^2) e_x
+ *   j_y  e_y                    q_y  (-5 + 3|e|^2) e_y
+ *   p_xx e_x^2 - e_y^2          p_xy e_x e_y
+ * The rows are mutually orthogonal (the basis of the paper's Ref. 9), so
+ * M^-1 = M^T diag(1 / |row k|^2).  M is row-major [k][a], M^-1 [a][k].     */
+void orc_mrt_basis(double* M, double* Minv) {
+  for (int a = 0; a < 9; ++a) {
+    double ex = ER9[a], ey = EZ9[a], e2 = ex * ex + ey * ey;
+    double row[9] = {1.0,
+                     -4.0 + 3.0 * e2,
+                     4.0 - 10.5 * e2 + 4.5 * e2 * e2,
+                     ex,
+                     (-5.0 + 3.0 * e2) * ex,
+                     ey,
+                     (-5.0 + 3.0 * e2) * ey,
+                     ex * ex - ey * ey,
+                     ex * ey};
+    for (int k = 0; k < 9; ++k) M[k * 9 + a] = row[k];
+  }
+  for (int k = 0; k < 9; ++k) {
+    double n2 = 0.0;
+    for (int a = 0; a < 9; ++a) n2 += M[k * 9 + a] * M[k * 9 + a];
+    for (int a = 0; a < 9; ++a) Minv[a * 9 + k] = M[k * 9 + a] / n2;
+  }
+}
+
+static void matvec9(const double* A, const double* x, double* y) {
+  for (int r = 0; r < 9; ++r) {
+    double s = 0.0;
+    for (int c = 0; c < 9; ++c) s += A[r * 9 + c] * x[c];
+    y[r] = s;
+  }
+}
+
+/* Source in moment space: S~ = -(u_r / r) m_eq + S~' with S~' of Eq. (51),
+ * F_x = F_r and F_y = F_z of Eq. (12).  The mass part carries the sign of
+ * Eq. (12)'s -(u_r / r) f_eq, so that the zeroth moment of the source is the
+ * continuity source -rho u_r / r of Eq. (1).  m holds the macros {rho, u_z,
+ * u_r, u_th, T} and meq = M f_eq. */
+void orc_mrt_source_moments(const orc_params* p, int j, int64_t t,
+                            const double* m, const double* meq, double* St) {
+  double ir = inv_r(p, j);
+  double Fz, Fr;
+  node_force(p, j, t, m, &Fz, &Fr);
+  double ux = m[2], uy = m[1], Fx = Fr, Fy = Fz;
+  double uF = ux * Fx + uy * Fy;
+  double Sp[9] = {0.0,  6.0 * uF, -6.0 * uF, Fx, -Fx, Fy, -Fy,
+                  2.0 * (ux * Fx - uy * Fy), ux * Fy + uy * Fx};
+  for (int k = 0; k < 9; ++k) St[k] = -m[2] * ir * meq[k] + Sp[k];
+}
+
+/* The source in velocity space, S = M^-1 S~: the equilibrium of the f-bar
+ * variables is f_eq - S/2 (f-bar = f - S/2, Eq. 40). */
+static void node_source_mrt(const orc_params* p, int j, int64_t t,
+                            const double* m, const double* feq, double* S) {
+  double M[81], Minv[81], meq[9], St[9];
+  orc_mrt_basis(M, Minv);
+  matvec9(M, feq, meq);
+  orc_mrt_source_moments(p, j, t, m, meq, St);
+  matvec9(Minv, St, S);
+}
+
+/* Collision of f-bar in moment space, Eq. (41), with the momentum rows
+ * modified by Eqs. (49)-(50); the result f-bar+ = M^-1 m-bar+ is what Eq.
+ * (42) streams.  Lambda = diag(s_rho, s_e, s_eps, s_j, s_q, s_j, s_q, s_v,
+ * s_v) with s_v = 1 / (tau + 1/2) (mu = (1/s_v - 1/2) rho / 3).  In Eqs.
+ * (49)-(50) m^(1) = (m-bar - m_eq) + S~/2 and gamma = (1 - s_v/2) / r, which
+ * is zero wherever 1/r is taken as zero.                                    */
+static void node_collide_f_mrt(const orc_params* p, int j, int64_t t,
+                               const double* fb, const double* m, double* fo) {
+  double M[81], Minv[81], feq[9], meq[9], mb[9], St[9], mp[9];
+  orc_mrt_basis(M, Minv);
+  orc_feq9(m[0], m[1], m[2], feq);
+  matvec9(M, feq, meq);
+  matvec9(M, fb, mb);
+  orc_mrt_source_moments(p, j, t, m, meq, St);
+  double sv = 1.0 / (p->tau + 0.5);
+  double s[9] = {p->s_rho, p->s_e, p->s_eps, p->s_j, p->s_q,
+                 p->s_j,   p->s_q, sv,       sv};
+  for (int k = 0; k < 9; ++k)
+    mp[k] = mb[k] - s[k] * (mb[k] - meq[k]) + (1.0 - 0.5 * s[k]) * St[k];
+  double e1 = mb[1] - meq[1] + 0.5 * St[1];
+  double pxx1 = mb[7] - meq[7] + 0.5 * St[7];
+  double pxy1 = mb[8] - meq[8] + 0.5 * St[8];
+  double gam = (1.0 - 0.5 * sv) * inv_r(p, j);
+  mp[3] -= gam * (p->s_e / (6.0 * sv) * e1 + 0.5 * pxx1); /* Eq. (49) */
+  mp[5] -= gam * pxy1;                                     /* Eq. (50) */
+  matvec9(Minv, mp, fo);
+}
+
+/* Eq. (13) for f (or the MRT collision above), Eq. (53) for g and the
+ * analogous rule for h, at one node.  Inputs are the pre-collision
+ * populations (g already axis-substituted); outputs are the post-collision
+ * populations and the macros m[5].                                          */
 void orc_node_collide(const orc_params* p, int j, int64_t t, const double* fh,
                       const double* g, const double* h, double* fo, double* go,
                       double* ho, double* m) {
   double ir = inv_r(p, j);
   orc_node_macros(p, j, t, fh, g, h, m);
   double rho = m[0], uz = m[1], ur = m[2], uth = m[3], T = m[4];
-  double feq[9], S[9];
-  orc_feq9(rho, uz, ur, feq);
-  orc_node_source(p, j, t, m, feq, S);
-  for (int a = 0; a < 9; ++a) {
-    /* omega_f = [1 + tau e_ar / r] / (tau + 0.5), after Eq. (13) */
-    double w = (1.0 + p->tau * ER9[a] * ir) / (p->tau + 0.5);
-    fo[a] = fh[a] - w * (fh[a] - feq[a]) + (1.0 - 0.5 * w) * S[a];
+  if (p->mrt) {
+    node_collide_f_mrt(p, j, t, fh, m, fo);
+  } else {
+    double feq[9], S[9];
+    orc_feq9(rho, uz, ur, feq);
+    orc_node_source(p, j, t, m, feq, S);
+    for (int a = 0; a < 9; ++a) {
+      /* omega_f = [1 + tau e_ar / r] / (tau + 0.5), after Eq. (13) */
+      double w = (1.0 + p->tau * ER9[a] * ir) / (p->tau + 0.5);
+      fo[a] = fh[a] - w * (fh[a] - feq[a]) + (1.0 - 0.5 * w) * S[a];
+    }
   }
   if (p->swirl) {
     double geq[4];

@@ -58,6 +58,12 @@ class _Params(C.Structure):
         ("gbeta", C.c_double),
         ("T_ref", C.c_double),
         ("side", _Side * 4),
+        ("mrt", C.c_int),
+        ("s_e", C.c_double),
+        ("s_eps", C.c_double),
+        ("s_q", C.c_double),
+        ("s_rho", C.c_double),
+        ("s_j", C.c_double),
     ]
 
 
@@ -99,6 +105,8 @@ def lib():
         L.orc_node_source.argtypes = [C.POINTER(_Params), C.c_int, C.c_int64, P, P, P]
         L.orc_node_collide.argtypes = [C.POINTER(_Params), C.c_int, C.c_int64, P, P, P,
                                        P, P, P, P]
+        L.orc_mrt_basis.argtypes = [P, P]
+        L.orc_mrt_source_moments.argtypes = [C.POINTER(_Params), C.c_int, C.c_int64, P, P, P]
         L.orc_force_a.restype = C.c_double
         L.orc_force_a.argtypes = [C.POINTER(_Params), C.c_int64]
         L.orc_set_threads.argtypes = [C.c_int]
@@ -154,6 +162,17 @@ def params(case: dict) -> _Params:
     p.T_ref = float(case.get("T_ref", 0.0))
     for k, name in enumerate(("south", "north", "west", "east")):
         p.side[k] = _side(case[name])
+    # MRT rates (Sec. III B): s_v = 1/(tau + 1/2); s_e = s_v as the paper
+    # requires for axisymmetric flow, s_eps = s_v (the even moments of a
+    # two-relaxation-time model) and s_q from (1/s_v - 1/2)(1/s_q - 1/2) =
+    # 3/16 unless the case gives them; the conserved-moment rates drop out.
+    p.mrt = int(bool(case.get("mrt", False)))
+    sv = 1.0 / (tau + 0.5)
+    p.s_e = float(case.get("s_e", 0.0)) or sv
+    p.s_eps = float(case.get("s_eps", 0.0)) or sv
+    p.s_q = float(case.get("s_q", 0.0)) or 1.0 / (0.5 + 3.0 / (16.0 * tau))
+    p.s_rho = float(case.get("s_rho", 1.0))
+    p.s_j = float(case.get("s_j", 1.0))
     return p
 
 
@@ -271,6 +290,22 @@ def node_collide(case, j, t, f, g=None, h=None):
     lib().orc_node_collide(C.byref(p), int(j), int(t), _ptr(f), _ptr(g), _ptr(h),
                            _ptr(fo), _ptr(go), _ptr(ho), _ptr(m))
     return fo, go, ho, m
+
+
+def mrt_basis():
+    """(M, M^-1) of the MRT moments, Eq. (38), rows in the order of m."""
+    M, Mi = np.empty((9, 9)), np.empty((9, 9))
+    lib().orc_mrt_basis(_ptr(M), _ptr(Mi))
+    return M, Mi
+
+
+def mrt_source_moments(case, j, t, m, meq):
+    """S~ = -(u_r / r) m_eq + S~' of Eq. (51) for macros m at row j."""
+    p = params(case)
+    St = np.empty(9)
+    lib().orc_mrt_source_moments(C.byref(p), int(j), int(t), _ptr(np.asarray(m, float)),
+                                 _ptr(np.asarray(meq, float)), _ptr(St))
+    return St
 
 
 def force_a(case, t):
