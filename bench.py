@@ -14,6 +14,7 @@ Workloads (synthetic, seeded):
   batch256   256 rotating-lid cavities, Nr ~ U{64..512}, H/R ~ U[1,3],
              Re ~ U[500,2500] (tau_s >= 0.52), FP32 f + g, one launch per
              step (default)
+  batch256_mrt   the same 256 cavities with the MRT collision of f
   pipe_fp32 / pipe_fp64   16384 x 2048 body-force pipe, f only
   womersley  64 x 128 Womersley pipe, FP32
   cavity     256 x 384 rotating-lid cavity at Re 990, FP32 f + g
@@ -43,6 +44,9 @@ def workload(name: str):
     from paper_1003_0282_amd import workloads as W
     if name == "batch256":
         return W.batch_cavities(256, seed=0), 1, "256 rotating-lid cavities (seed 0), FP32 f+g"
+    if name == "batch256_mrt":
+        cases = [dict(c, mrt=True) for c in W.batch_cavities(256, seed=0)]
+        return cases, 1, "256 rotating-lid cavities (seed 0), FP32 f+g, MRT collision of f"
     if name == "pipe_fp32":
         return [W.roofline_pipe()], 1, "16384x2048 body-force pipe, FP32 f"
     if name == "pipe_fp64":

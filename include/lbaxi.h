@@ -7,7 +7,11 @@
  *   f : D2Q9 populations of the improved BGK scheme, Eq. (13) with the
  *       gradient-free source of Eq. (12), the direction-dependent relaxation
  *       rate omega_f = (1 + tau e_r / r)/(tau + 1/2) and the macros of
- *       Eqs. (16)-(17) (Sec. III A);
+ *       Eqs. (16)-(17) (Sec. III A).  With LBAXI_MRT f collides instead with
+ *       the MRT model of Sec. III B: moments of Eq. (38), Eq. (41) on f-bar =
+ *       f - S/2 (Eq. 40) with the source of Eq. (51), and the momentum rows
+ *       modified by Eqs. (49)-(50) to carry the 1/r viscous terms; the
+ *       macros stay Eqs. (16)-(17);
  *   g : D2Q4 azimuthal-velocity populations, Eqs. (53)-(54) (Sec. III C),
  *       optional (LBAXI_SWIRL);
  *   h : D2Q4 temperature populations built like Eqs. (53)-(54) with source
@@ -74,8 +78,17 @@ enum { LBAXI_FP64 = 0, LBAXI_FP32 = 1, LBAXI_FP32_FAST = 2 };
  * wall treatment of its rotating flows (Sec. IV B); without it walls are
  * halfway links half a spacing outside the last node.  The wall node keeps
  * the mass it streamed in (no mass crosses the wall); its velocity, u_theta
- * and T (fixed-temperature walls) take the wall values.  Needs nz, nr >= 3. */
-enum { LBAXI_SWIRL = 1u, LBAXI_THERMAL = 2u, LBAXI_CARTESIAN = 4u, LBAXI_WET_WALLS = 8u };
+ * and T (fixed-temperature walls) take the wall values.  Needs nz, nr >= 3.
+ * LBAXI_MRT selects the MRT collision of f (Sec. III B; rates in
+ * lbaxi_desc.s_e, s_eps, s_q, with s_v = 1/tau fixed by the viscosity);
+ * seeding and wet-node walls then use its source, S = M^-1 S~. */
+enum {
+  LBAXI_SWIRL = 1u,
+  LBAXI_THERMAL = 2u,
+  LBAXI_CARTESIAN = 4u,
+  LBAXI_WET_WALLS = 8u,
+  LBAXI_MRT = 16u
+};
 enum {
   LBAXI_SIDE_AXIS = 0,     /* south side only, r0 = 0: specular axis */
   LBAXI_SIDE_WALL = 1,     /* halfway bounce-back wall */
@@ -107,7 +120,7 @@ typedef struct {
   int32_t nz, nr;   /* nodes along z and r, each >= 2 */
   double r0;        /* radius of node row 0; 0 with an axis south side */
   int32_t prec;     /* LBAXI_FP64 / _FP32 / _FP32_FAST (same for a whole batch) */
-  uint32_t fields;  /* LBAXI_SWIRL | LBAXI_THERMAL | LBAXI_CARTESIAN | LBAXI_WET_WALLS */
+  uint32_t fields;  /* LBAXI_SWIRL | _THERMAL | _CARTESIAN | _WET_WALLS | _MRT */
   double tau;       /* tau_s of f */
   double tau_g;     /* tau_s of g, 0 -> paper default */
   double tau_h;     /* tau_s of h, 0 -> tau */
@@ -116,6 +129,12 @@ typedef struct {
                                period <= 0: constant a0 */
   double gbeta, T_ref;      /* buoyancy rho0 * gbeta * (T - T_ref) along +z */
   lbaxi_side south, north, west, east;
+  /* MRT relaxation rates (used with LBAXI_MRT only) of the moments e,
+   * epsilon and q of Eq. (38); 0 selects the default: s_e = s_eps = s_v
+   * (the paper requires s_e = s_v, Sec. III B) and s_q from
+   * (1/s_v - 1/2)(1/s_q - 1/2) = 3/16.  The conserved moments need no rate:
+   * with f-bar = f - S/2 they leave the collision as m-bar + S~ for any. */
+  double s_e, s_eps, s_q;
 } lbaxi_desc;
 
 typedef struct lbaxi_s lbaxi_t; /* opaque handle */
@@ -129,20 +148,23 @@ const char* lbaxi_strerror(lbaxi_status s);
  * field per lattice for Eq. (57). */
 lbaxi_status lbaxi_workspace_bytes(int32_t n, const lbaxi_desc* descs, size_t* bytes);
 
-/* Create a handle over n lattices (all the same prec and field set), carving
+/* Create a handle over n lattices (all the same prec, the same SWIRL and
+ * THERMAL bits and the same collision model; CARTESIAN and WET_WALLS may
+ * differ between lattices), carving
  * d_workspace (>= lbaxi_workspace_bytes, 256-byte aligned) and enqueuing on
  * hip_stream (a hipStream_t; NULL = the null stream).  Validates every
  * descriptor: EINVAL for bad sizes or side combinations (axis only as south
  * with r0 = 0, periodic only on both z-ends together, free slip only on
  * z-ends), ERANGE when some relaxation rate (1 + tau e_r / r)/(tau + 1/2) of
- * f, g or h leaves (0, 2).  The lattices start at rest (lbaxi_seed with NULL
+ * f (BGK), g or h, or an MRT rate, leaves (0, 2).  The lattices start at rest (lbaxi_seed with NULL
  * fields). */
 lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace,
                           size_t bytes, void* hip_stream, lbaxi_t** out);
 void lbaxi_destroy(lbaxi_t* h);
 
 /* Equilibrium seeding of every lattice (Eq. 6 and Eq. 54; the paper starts
- * from rest): f^ = f_eq(rho, u) - S(rho, u)/2 with S of Eq. (12), g = g_eq,
+ * from rest): f^ = f_eq(rho, u) - S(rho, u)/2 with S of Eq. (12) (with
+ * LBAXI_MRT the velocity-space MRT source M^-1 S~), g = g_eq,
  * h = h_eq, so Eqs. (16)-(17) return the given fields.  Each d_ pointer is a
  * packed field set of the handle's precision (double for FP64, float for
  * FP32), or NULL for rho0 / zero velocity / T_ref.  u_r and u_theta are

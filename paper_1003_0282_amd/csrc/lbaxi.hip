@@ -156,15 +156,27 @@ __device__ inline bool wet_rule(const InstP& P, const InstP* Pg, int i, int j, W
   return true;
 }
 
-// E_a = f_eq - S/2 of direction a in deviation form (f_eq = w (drho + rho P),
-// S = w (1 + P) [3 (e - u).F - rho u_r / r]).
-template <typename R>
+// Source of direction a in velocity space with P = 3 e.u + 4.5 (e.u)^2 -
+// 1.5 u^2: Eq. (12), S = w (1 + P) [3 (e - u).F - rho u_r / r], or for the
+// MRT model S = M^-1 S~ = w [3 (e - u).F + 9 (e.u)(e.F)] - (u_r / r) f_eq,
+// the velocity-space form of Eq. (51) plus the mass source.
+template <typename R, int F>
+__device__ inline R src_a(int a, R rho, R uz, R ur, R Fz, R Fr, R ir, R Pa) {
+  const R ez = (R)ez9(a), er = (R)er9(a), w = (R)w9(a);
+  const R eF3 = (R)3 * ((ez - uz) * Fz + (er - ur) * Fr);
+  if (F & F_MRT)
+    return w * (eF3 + (R)9 * (ez * uz + er * ur) * (ez * Fz + er * Fr)) -
+           w * rho * ((R)1 + Pa) * ur * ir;
+  return w * ((R)1 + Pa) * (eF3 - rho * ur * ir);
+}
+
+// E_a = f_eq - S/2 of direction a in deviation form (f_eq = w (drho + rho P)).
+template <typename R, int F>
 __device__ inline R eq_hat(int a, R drho, R rho, R uz, R ur, R Fz, R Fr, R ir) {
   const R ez = (R)ez9(a), er = (R)er9(a), w = (R)w9(a);
   const R eu = ez * uz + er * ur;
   const R Pa = (R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * (uz * uz + ur * ur);
-  const R Sa = w * ((R)1 + Pa) * ((R)3 * ((ez - uz) * Fz + (er - ur) * Fr) - rho * ur * ir);
-  return w * (drho + rho * Pa) - (R)0.5 * Sa;
+  return w * (drho + rho * Pa) - (R)0.5 * src_a<R, F>(a, rho, uz, ur, Fz, Fr, ir, Pa);
 }
 
 template <typename S, typename R, int F>
@@ -197,8 +209,8 @@ __device__ inline void wall_state(const InstP& P, const PR<R>& p, const S* s, in
   if (F & F_SWIRL) Frb += p.rho0 * uthw * uthw * rb.ir;
 #pragma unroll
   for (int a = 0; a < 9; ++a)
-    f[a] = fn[a] + eq_hat<R>(a, drhob, rhob, uzw, urw, Fzb, Frb, rb.ir) -
-           eq_hat<R>(a, m.drho, m.rho, m.uz, m.ur, m.Fz, m.Fr, rn.ir);
+    f[a] = fn[a] + eq_hat<R, F>(a, drhob, rhob, uzw, urw, Fzb, Frb, rb.ir) -
+           eq_hat<R, F>(a, m.drho, m.rho, m.uz, m.ur, m.Fz, m.Fr, rn.ir);
   if (F & F_SWIRL) {
     const R qb = (R)0.25 * p.rho0 * uthw, qn = (R)0.25 * p.rho0 * m.uth;
 #pragma unroll
@@ -325,7 +337,8 @@ __global__ void __launch_bounds__(256) k_halo(const InstP* ip, const Tile* tiles
   halo_fill<S, F>(P, ip + T.inst, buf + P.off, i, j);
 }
 
-// Equilibrium seeding: f^ = f_eq - S/2 at rho = rho0, g = g_eq, h = h_eq.
+// Equilibrium seeding: f^ = f_eq - S/2 (S of the collision model), g = g_eq,
+// h = h_eq.
 template <typename S, typename R, int F>
 __global__ void __launch_bounds__(1024) k_seed(const InstP* ip, const Tile* tiles,
                                                const int* ntiles, S* buf, const S* rho_in,
@@ -361,7 +374,7 @@ __global__ void __launch_bounds__(1024) k_seed(const InstP* ip, const Tile* tile
     const R ez = (R)ez9(a), er = (R)er9(a), w = (R)w9(a);
     const R eu = ez * uz + er * ur;
     const R Pa = (R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * usq;
-    const R Sa = w * ((R)1 + Pa) * ((R)3 * ((ez - uz) * Fz + (er - ur) * Fr) - rho * ur * ir);
+    const R Sa = src_a<R, F>(a, rho, uz, ur, Fz, Fr, ir, Pa);
     d[a * pl + o] = (S)(w * (drho + rho * Pa) - (R)0.5 * Sa);
   }
   if (F & F_SWIRL) {
@@ -602,7 +615,7 @@ lbaxi_status validate(const lbaxi_desc& d, int k) {
     return bad(LBAXI_EINVAL, "lattice too large for 32-bit in-lattice offsets");
   if (d.prec != LBAXI_FP64 && d.prec != LBAXI_FP32 && d.prec != LBAXI_FP32_FAST)
     return bad(LBAXI_EINVAL, "bad prec");
-  if (d.fields & ~15u) return bad(LBAXI_EINVAL, "unknown field bits");
+  if (d.fields & ~31u) return bad(LBAXI_EINVAL, "unknown field bits");
   if ((d.fields & LBAXI_WET_WALLS) && (d.nz < 3 || d.nr < 3))
     return bad(LBAXI_EINVAL, "wet-node walls need nz and nr >= 3");
   if (!(d.rho0 > 0)) return bad(LBAXI_EINVAL, "rho0 must be positive");
@@ -628,11 +641,19 @@ lbaxi_status validate(const lbaxi_desc& d, int k) {
     return bad(LBAXI_EINVAL, "an annulus needs r0 >= 1");
   double tau, tg, th;
   taus(d, tau, tg, th);
+  const bool mrt = (d.fields & LBAXI_MRT) != 0;
+  if (mrt) {
+    const double sr[3] = {d.s_e, d.s_eps, d.s_q};
+    for (int q = 0; q < 3; ++q)
+      if (!(sr[q] == 0.0 || (sr[q] > 0.0 && sr[q] < 2.0)))
+        return bad(LBAXI_ERANGE, "an MRT rate leaves (0, 2)");
+  }
   const double tt[3] = {tau, tg, th};
   const bool used[3] = {true, (d.fields & LBAXI_SWIRL) != 0, (d.fields & LBAXI_THERMAL) != 0};
   for (int q = 0; q < 3; ++q) {
     if (!used[q]) continue;
     if (!(tt[q] > 0)) return bad(LBAXI_ERANGE, "relaxation time must exceed 1/2");
+    if (q == 0 && mrt) continue;  // the MRT rates of f do not depend on r
     for (int j = 0; j < d.nr; ++j) {
       const double r = d.r0 + j;
       const double ir = ((d.fields & LBAXI_CARTESIAN) || r <= 0) ? 0.0 : 1.0 / r;
@@ -666,6 +687,10 @@ InstP make_inst(const lbaxi_desc& d, long long off, long long off_fld) {
   P.om0 = 1.0 / (P.tau + 0.5);
   P.omg0 = 1.0 / (P.tau_g + 0.5);
   P.omh0 = 1.0 / (P.tau_h + 0.5);
+  // MRT rates: s_e = s_eps = s_v and (1/s_v - 1/2)(1/s_q - 1/2) = 3/16 unless given
+  P.s_e = d.s_e > 0 ? d.s_e : P.om0;
+  P.s_eps = d.s_eps > 0 ? d.s_eps : P.om0;
+  P.s_q = d.s_q > 0 ? d.s_q : 1.0 / (0.5 + 3.0 / (16.0 * P.tau));
   P.a0 = d.a0;
   P.period = d.period;
   P.phase = d.phase;
@@ -798,7 +823,7 @@ lbaxi_status upload_dyn(lbaxi_t* h) {
 template <typename S, typename R, int F>
 void* step_fn() { return reinterpret_cast<void*>(&k_step<S, R, F>); }
 template <typename S, typename R, int F>
-void* halo_fn() { return reinterpret_cast<void*>(&k_halo<S, F>); }
+void* halo_fn() { return reinterpret_cast<void*>(&k_halo<S, F & 3>); }  // no collision
 template <typename S, typename R, int F>
 void* wall_fn() { return reinterpret_cast<void*>(&k_wall<S, R, F>); }
 template <typename S, typename R, int F>
@@ -810,11 +835,14 @@ void* resid_fn() { return reinterpret_cast<void*>(&k_residual<S, R, F>); }
 
 // Kernel instance for (precision, field set): FP64 stores and computes in
 // double, FP32 stores float and computes in double, FP32_FAST is float only.
-#define PICK_F(name, S, R, fields)                    \
-  (((fields) & 3) == 0   ? name<S, R, 0>()            \
-   : ((fields) & 3) == 1 ? name<S, R, 1>()            \
-   : ((fields) & 3) == 2 ? name<S, R, 2>()            \
-                         : name<S, R, 3>())
+#define PICK_B(name, S, R, fields, M)         \
+  (((fields) & 3) == 0   ? name<S, R, 0 | M>()  \
+   : ((fields) & 3) == 1 ? name<S, R, 1 | M>()  \
+   : ((fields) & 3) == 2 ? name<S, R, 2 | M>()  \
+                         : name<S, R, 3 | M>())
+#define PICK_F(name, S, R, fields)                                \
+  (((fields) & LBAXI_MRT) ? PICK_B(name, S, R, fields, F_MRT)     \
+                          : PICK_B(name, S, R, fields, 0))
 #define PICK(name, prec, fields)                                   \
   ((prec) == LBAXI_FP64   ? PICK_F(name, double, double, fields)   \
    : (prec) == LBAXI_FP32 ? PICK_F(name, float, double, fields)    \
@@ -1107,8 +1135,10 @@ lbaxi_status lbaxi_workspace_bytes(int32_t n, const lbaxi_desc* descs, size_t* b
   for (int k = 0; k < n; ++k) {
     lbaxi_status s = validate(d[k], k);
     if (s != LBAXI_OK) return s;
-    if (d[k].prec != d[0].prec || (d[k].fields & 3) != (d[0].fields & 3))
-      return fail(LBAXI_EINVAL, "all lattices of a batch need the same prec and field set");
+    const unsigned kset = LBAXI_SWIRL | LBAXI_THERMAL | LBAXI_MRT;  // picks the kernels
+    if (d[k].prec != d[0].prec || (d[k].fields & kset) != (d[0].fields & kset))
+      return fail(LBAXI_EINVAL,
+                  "all lattices of a batch need the same prec, field set and collision model");
   }
   *bytes = layout(d).total;
   return LBAXI_OK;

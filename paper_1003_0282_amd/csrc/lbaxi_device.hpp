@@ -15,7 +15,7 @@ namespace lbx {
 
 enum { SIDE_AXIS = 0, SIDE_WALL = 1, SIDE_PERIODIC = 2, SIDE_FREESLIP = 3 };
 enum { SOUTH = 0, NORTH = 1, WEST = 2, EAST = 3 };
-enum { F_SWIRL = 1, F_THERMAL = 2 };
+enum { F_SWIRL = 1, F_THERMAL = 2, F_MRT = 4 };
 enum { MODE_PRE = 1, MODE_SPEED = 2 };
 
 struct SideP {
@@ -34,7 +34,8 @@ struct InstP {
   double r0;
   double tau, tau_g, tau_h;  // paper convention: nu = tau / 3
   double rho0, mu0, nu_g;
-  double om0, omg0, omh0;  // 1 / (tau + 1/2) of f, g, h
+  double om0, omg0, omh0;  // 1 / (tau + 1/2) of f, g, h (om0 is the MRT s_v)
+  double s_e, s_eps, s_q;  // MRT rates of the e, epsilon and q moments
   double a0, period, phase, gbeta, T_ref;
   long long off;      // element offset of the instance's population planes
   long long off_fld;  // element offset of its packed [nr][nz] fields
@@ -82,6 +83,7 @@ template <typename R>
 struct PR {
   R rho0, inv_rho0, mu0, tau, tau_g, tau_h, nu_g, om0, omg0, omh0, gbeta, T_ref, r0;
   R a_t;  // axial force density at the time level being processed
+  R se, seps, sq, ke, gfac;  // MRT: rates, s_e / (6 s_v), 1 - s_v / 2
   int cart;
 };
 
@@ -104,6 +106,11 @@ __device__ inline PR<R> make_pr(const InstP& P, long long t) {
   double a = P.a0;
   if (P.period > 0.0) a = P.a0 * cos(2.0 * M_PI * (double)t / P.period + P.phase);
   p.a_t = (R)a;
+  p.se = (R)P.s_e;
+  p.seps = (R)P.s_eps;
+  p.sq = (R)P.s_q;
+  p.ke = (R)(P.s_e / (6.0 * P.om0));
+  p.gfac = (R)(1.0 - 0.5 * P.om0);
   p.cart = P.cart;
   return p;
 }
@@ -129,7 +136,8 @@ __device__ inline float rcp(float x) {
 template <typename R>
 struct Row {
   R ir, ir2;
-  R omp, omm, c0, cp, cm;  // f
+  R omp, omm, c0, cp, cm;  // f (BGK)
+  R gam;                   // f (MRT): gamma = (1 - s_v / 2) / r of Eqs. (47)-(50)
   R gp, gm, gsk;           // g: rates and nu_g / r
   R hp, hm;                // h
 };
@@ -140,11 +148,15 @@ __device__ inline Row<R> make_row(const PR<R>& p, int j) {
   const R r = p.r0 + (R)j;
   w.ir = (p.cart || !(r > (R)0)) ? (R)0 : rcp(r);
   w.ir2 = w.ir * w.ir;
-  w.omp = p.om0 * ((R)1 + p.tau * w.ir);
-  w.omm = p.om0 * ((R)1 - p.tau * w.ir);
-  w.c0 = (R)1 - (R)0.5 * p.om0;
-  w.cp = (R)1 - (R)0.5 * w.omp;
-  w.cm = (R)1 - (R)0.5 * w.omm;
+  if (F & F_MRT) {
+    w.gam = p.gfac * w.ir;
+  } else {
+    w.omp = p.om0 * ((R)1 + p.tau * w.ir);
+    w.omm = p.om0 * ((R)1 - p.tau * w.ir);
+    w.c0 = (R)1 - (R)0.5 * p.om0;
+    w.cp = (R)1 - (R)0.5 * w.omp;
+    w.cm = (R)1 - (R)0.5 * w.omm;
+  }
   if (F & F_SWIRL) {
     w.gp = p.omg0 * ((R)1 + p.tau_g * w.ir);
     w.gm = p.omg0 * ((R)1 - p.tau_g * w.ir);
@@ -212,28 +224,104 @@ __device__ inline void collide_pair(R& fa, R& fb, R eu, R eF, R w, R oma, R omb,
   fb = fb - omb * (fb - (mid - odd)) + cb * Sb;
 }
 
-// Eq. (13) with the source of Eq. (12) for f; Eq. (53)-(54) for g; the
-// temperature analogue for h.  Updates the populations in place.
+// MRT collision of f (Sec. III B) with x = r, y = z.  Eq. (41) changes each
+// moment of Eq. (38) by dm_k = -s_k (m_k - m_eq_k) + (1 - s_k/2) S~_k, with
+// S~ = -(u_r / r) m_eq + S~' (Eq. 51); for the conserved moments this is
+// S~_k exactly (f-bar = f - S/2 and the macros of Eqs. 16-17 make
+// m_k - m_eq_k = -S~_k / 2), and Eqs. (49)-(50) subtract gamma [(s_e / 6 s_v)
+// e1 + p_xx1 / 2] and gamma p_xy1 from the momentum rows, m1 = (m - m_eq) +
+// S~/2.  The populations then change by M^-1 dm: the rows of M are
+// orthogonal with squared norms (9, 36, 36, 6, 12, 6, 12, 4, 4).  Moments of
+// the stored deviations d_a = f-bar_a - w_a rho0 differ from those of f-bar
+// only in rho, e and epsilon (by rho0, -2 rho0, rho0), which the
+// non-equilibrium parts below absorb.
+template <typename R>
+__device__ inline void collide_f_mrt(const PR<R>& p, const Row<R>& w, const Mac<R>& m, R* f) {
+  const R ux = m.ur, uy = m.uz, Fx = m.Fr, Fy = m.Fz, rho = m.rho;
+  const R u2 = ux * ux + uy * uy;
+  const R uF = ux * Fx + uy * Fy;
+  const R c = -ux * w.ir;  // mass-source factor -u_r / r
+  // moments of the deviations: axis directions 2 (+x) 4 (-x) 1 (+y) 3 (-y),
+  // diagonals 5 (+x+y) 6 (+x-y) 7 (-x-y) 8 (-x+y)
+  const R A = (f[1] + f[3]) + (f[2] + f[4]);
+  const R D = (f[5] + f[7]) + (f[6] + f[8]);
+  const R X1 = f[2] - f[4], Y1 = f[1] - f[3];
+  const R Xd = (f[5] + f[6]) - (f[7] + f[8]);
+  const R Yd = (f[5] + f[8]) - (f[6] + f[7]);
+  // non-equilibrium parts m_k - m_eq_k
+  const R r3u2 = (R)3 * rho * u2;
+  const R ne = ((R)-4 * f[0] - A + (R)2 * D) + (R)2 * m.drho - r3u2;
+  const R nps = ((R)4 * f[0] - (R)2 * A + D) - m.drho + r3u2;
+  const R nqx = ((R)-2 * X1 + Xd) + rho * ux;
+  const R nqy = ((R)-2 * Y1 + Yd) + rho * uy;
+  const R npxx = ((f[2] + f[4]) - (f[1] + f[3])) - rho * (ux * ux - uy * uy);
+  const R npxy = ((f[5] + f[7]) - (f[6] + f[8])) - rho * ux * uy;
+  // source moments
+  const R cr = c * rho;
+  const R Se = cr * ((R)-2 + (R)3 * u2) + (R)6 * uF;
+  const R Sps = cr * ((R)1 - (R)3 * u2) - (R)6 * uF;
+  const R Sjx = cr * ux + Fx, Sjy = cr * uy + Fy;  // S~_qx = -S~_jx, S~_qy = -S~_jy
+  const R Spxx = cr * (ux * ux - uy * uy) + (R)2 * (ux * Fx - uy * Fy);
+  const R Spxy = cr * ux * uy + (ux * Fy + uy * Fx);
+  const R sv = p.om0;
+  const R hv = (R)1 - (R)0.5 * sv;
+  const R dE = -p.se * ne + ((R)1 - (R)0.5 * p.se) * Se;
+  const R dP = -p.seps * nps + ((R)1 - (R)0.5 * p.seps) * Sps;
+  const R hq = (R)1 - (R)0.5 * p.sq;
+  const R dQx = -p.sq * nqx - hq * Sjx;
+  const R dQy = -p.sq * nqy - hq * Sjy;
+  const R dXX = -sv * npxx + hv * Spxx;
+  const R dXY = -sv * npxy + hv * Spxy;
+  const R dJx = Sjx - w.gam * (p.ke * (ne + (R)0.5 * Se) + (R)0.5 * (npxx + (R)0.5 * Spxx));
+  const R dJy = Sjy - w.gam * (npxy + (R)0.5 * Spxy);
+  // f += M^-1 dm
+  const R r0 = cr * (R)(1.0 / 9.0);
+  const R re = dE * (R)(1.0 / 36.0), rp = dP * (R)(1.0 / 36.0);
+  const R jx = dJx * (R)(1.0 / 6.0), jy = dJy * (R)(1.0 / 6.0);
+  const R qx = dQx * (R)(1.0 / 12.0), qy = dQy * (R)(1.0 / 12.0);
+  const R px = dXX * (R)0.25, pc = dXY * (R)0.25;
+  f[0] += r0 - (R)4 * re + (R)4 * rp;
+  const R b1 = r0 - re - (R)2 * rp;
+  const R ax = jx - (R)2 * qx, ay = jy - (R)2 * qy;
+  f[2] += (b1 + px) + ax;
+  f[4] += (b1 + px) - ax;
+  f[1] += (b1 - px) + ay;
+  f[3] += (b1 - px) - ay;
+  const R b2 = r0 + (R)2 * re + rp;
+  const R X = jx + qx, Y = jy + qy;
+  f[5] += (b2 + pc) + (X + Y);
+  f[7] += (b2 + pc) - (X + Y);
+  f[6] += (b2 - pc) + (X - Y);
+  f[8] += (b2 - pc) - (X - Y);
+}
+
+// Eq. (13) with the source of Eq. (12) for f (or the MRT collision above);
+// Eq. (53)-(54) for g; the temperature analogue for h.  Updates the
+// populations in place.
 template <typename R, int F>
 __device__ inline void collide(const PR<R>& p, const Row<R>& w, const Mac<R>& m, R* f, R* g,
                                R* h) {
   const R uz = m.uz, ur = m.ur;
-  const R k15 = (R)1.5 * (uz * uz + ur * ur);
-  const R C0 = -(R)3 * (uz * m.Fz + ur * m.Fr) - m.rho * ur * w.ir;
-  const R w1 = (R)(1.0 / 9.0), w5 = (R)(1.0 / 36.0);
-  {
-    const R w0 = (R)(4.0 / 9.0);
-    const R feqd = w0 * (m.drho - m.rho * k15);
-    const R S = w0 * ((R)1 - k15) * C0;
-    f[0] = f[0] - p.om0 * (f[0] - feqd) + w.c0 * S;
+  if (F & F_MRT) {
+    collide_f_mrt<R>(p, w, m, f);
+  } else {
+    const R k15 = (R)1.5 * (uz * uz + ur * ur);
+    const R C0 = -(R)3 * (uz * m.Fz + ur * m.Fr) - m.rho * ur * w.ir;
+    const R w1 = (R)(1.0 / 9.0), w5 = (R)(1.0 / 36.0);
+    {
+      const R w0 = (R)(4.0 / 9.0);
+      const R feqd = w0 * (m.drho - m.rho * k15);
+      const R S = w0 * ((R)1 - k15) * C0;
+      f[0] = f[0] - p.om0 * (f[0] - feqd) + w.c0 * S;
+    }
+    // e = (1,0) / (-1,0); (0,1) / (0,-1); (1,1) / (-1,-1); (1,-1) / (-1,1)
+    collide_pair(f[1], f[3], uz, m.Fz, w1, p.om0, p.om0, w.c0, w.c0, m.drho, m.rho, k15, C0);
+    collide_pair(f[2], f[4], ur, m.Fr, w1, w.omp, w.omm, w.cp, w.cm, m.drho, m.rho, k15, C0);
+    collide_pair(f[5], f[7], uz + ur, m.Fz + m.Fr, w5, w.omp, w.omm, w.cp, w.cm, m.drho, m.rho,
+                 k15, C0);
+    collide_pair(f[8], f[6], uz - ur, m.Fz - m.Fr, w5, w.omm, w.omp, w.cm, w.cp, m.drho, m.rho,
+                 k15, C0);
   }
-  // e = (1,0) / (-1,0); (0,1) / (0,-1); (1,1) / (-1,-1); (1,-1) / (-1,1)
-  collide_pair(f[1], f[3], uz, m.Fz, w1, p.om0, p.om0, w.c0, w.c0, m.drho, m.rho, k15, C0);
-  collide_pair(f[2], f[4], ur, m.Fr, w1, w.omp, w.omm, w.cp, w.cm, m.drho, m.rho, k15, C0);
-  collide_pair(f[5], f[7], uz + ur, m.Fz + m.Fr, w5, w.omp, w.omm, w.cp, w.cm, m.drho, m.rho,
-               k15, C0);
-  collide_pair(f[8], f[6], uz - ur, m.Fz - m.Fr, w5, w.omm, w.omp, w.cm, w.cp, m.drho, m.rho,
-               k15, C0);
   if (F & F_SWIRL) {
     // g_eq = (rho0 u_th / 4)(1 + 2 e.u), S^g = -(1/r)(2 u_r + nu / r) g_eq
     const R q = (R)0.25 * p.rho0 * m.uth;

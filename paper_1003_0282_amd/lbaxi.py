@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
                       "(the HIP library has no CPU fallback)")
 
 FP64, FP32, FP32_FAST = 0, 1, 2
-SWIRL, THERMAL, CARTESIAN, WET_WALLS = 1, 2, 4, 8
+SWIRL, THERMAL, CARTESIAN, WET_WALLS, MRT = 1, 2, 4, 8, 16
 SIDE = {"axis": 0, "wall": 1, "periodic": 2, "freeslip": 3}
 RUNNING, CONVERGED, DIVERGED, CAPPED = 0, 1, 2, 3
 STATUS_NAMES = {RUNNING: "running", CONVERGED: "converged", DIVERGED: "diverged",
@@ -41,7 +41,8 @@ class Desc(C.Structure):
                 ("tau_g", C.c_double), ("tau_h", C.c_double), ("rho0", C.c_double),
                 ("a0", C.c_double), ("period", C.c_double), ("phase", C.c_double),
                 ("gbeta", C.c_double), ("T_ref", C.c_double), ("south", Side),
-                ("north", Side), ("west", Side), ("east", Side)]
+                ("north", Side), ("west", Side), ("east", Side), ("s_e", C.c_double),
+                ("s_eps", C.c_double), ("s_q", C.c_double)]
 
 
 # torch's HIP runtime is loaded before the library so that both use the
@@ -124,7 +125,7 @@ def make_desc(case: dict, prec: int) -> Desc:
     d.prec = int(prec)
     d.fields = ((SWIRL if case.get("swirl") else 0) | (THERMAL if case.get("thermal") else 0)
                 | (CARTESIAN if case.get("cartesian") else 0)
-                | (WET_WALLS if case.get("wet") else 0))
+                | (WET_WALLS if case.get("wet") else 0) | (MRT if case.get("mrt") else 0))
     d.tau = float(case["tau"])
     d.tau_g = float(case.get("tau_g", 0.0))
     d.tau_h = float(case.get("tau_h", 0.0))
@@ -136,6 +137,9 @@ def make_desc(case: dict, prec: int) -> Desc:
     d.T_ref = float(case.get("T_ref", 0.0))
     d.south, d.north = _side(case["south"]), _side(case["north"])
     d.west, d.east = _side(case["west"]), _side(case["east"])
+    d.s_e = float(case.get("s_e", 0.0))
+    d.s_eps = float(case.get("s_eps", 0.0))
+    d.s_q = float(case.get("s_q", 0.0))
     return d
 
 

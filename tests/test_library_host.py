@@ -95,6 +95,17 @@ def test_validation(L):
     assert _status(L, [dict(ok, swirl=True, tau_g=1.6)]) == -2
     assert _status(L, [ok, W.cavity(8, 8, 10.0)]) == -1  # mixed field sets
     assert _status(L, [ok], prec=7) == -1
+    # MRT: rates in (0, 2) or 0 for the default; the BGK row check of f does
+    # not apply (tau_s = 1.55 is allowed); one collision model per batch
+    mrt = dict(ok, mrt=True)
+    assert _status(L, [mrt]) == 0
+    assert _status(L, [dict(mrt, tau=1.55)]) == 0
+    assert _status(L, [dict(mrt, s_q=2.0)]) == -2
+    assert _status(L, [dict(mrt, s_eps=-0.1)]) == -2
+    assert _status(L, [dict(mrt, s_e=1.9, s_eps=0.3, s_q=1.99)]) == 0
+    assert _status(L, [dict(mrt, tau=0.5)]) == -2
+    assert _status(L, [mrt, ok]) == -1
+    assert _status(L, [mrt, dict(mrt, wet=True), dict(mrt, cartesian=True, r0=0.0)]) == 0
 
 
 def test_workspace_grows_with_batch(L):
