@@ -24,6 +24,9 @@ Workloads (synthetic, seeded):
              and forward passes (batch 16), TFLOP/s against the BF16 MFMA peak
   warmstart  the learned warm start end to end: time to residual 1e-8
   batch256_sequential   the 256 cavities one handle after another
+  fig7       the paper's Fig. 7 run (100 x 150 rotating-lid cylinder, Re 1290,
+             tau = 0.005, wet-node walls, FP64): BGK until it diverges, MRT
+             to the Eq. 57 residual 1e-10, the axis maximum against Table 2
 """
 from __future__ import annotations
 
@@ -216,6 +219,53 @@ def warmstart_probe():
     }
 
 
+def fig7_probe(budget_s: float = 240.0):
+    """Fig. 7: the rotating-lid cylinder of Table 2 at Re = 1290 with nu =
+    0.005 / 3 (tau_s = 0.505).  The BGK handle runs until its residual turns
+    NaN; the MRT handle runs to the Eq. (57) residual 1e-10 (the paper's
+    criterion for this run) within a wall-clock budget, and the magnitude and
+    height of the largest axial velocity on the axis are read off."""
+    import numpy as np
+    import torch
+    from paper_1003_0282_amd import lbaxi as L
+    from paper_1003_0282_amd import steady as ST
+    from paper_1003_0282_amd import workloads as W
+    nu = 0.005 / 3.0
+
+    def case(mrt):
+        c = W.cavity_paper(1290.0, wet=True)
+        R = c["nr"] - 1.0
+        return dict(c, tau=0.505, east=W.wall(omega=1290.0 * nu / (R * R)), mrt=mrt,
+                    name="fig7_%s" % ("mrt" if mrt else "bgk"))
+
+    bgk = ST.solve([case(False)], tol=1e-10, max_steps=200_000, check_every=500, prec=L.FP64)
+    c = case(True)
+    torch.cuda.synchronize()
+    r = ST.solve([c], tol=1e-10, max_steps=40_000_000, check_every=20_000, prec=L.FP64,
+                 budget_s=budget_s, log=lambda m: print(m, file=sys.stderr, flush=True),
+                 tag="fig7 mrt", log_every_s=20.0)
+    nr, nz = c["nr"], c["nz"]
+    axis = r.fields["uz"][:nr * nz].reshape(nr, nz)[0]
+    Ut = c["east"]["omega"] * (nr - 1.0)
+    i = int(np.argmax(np.abs(axis)))
+    reversed_ = int((axis * np.sign(axis[i]) < -1e-6 * Ut).sum())
+    steps = int(r.steps[0])
+    return {"metric": "Fig. 7 (tau = 0.005): MRT wall time to the Eq. 57 residual 1e-10; "
+                      "BGK divergence",
+            "value": round(r.wall_s, 2), "unit": "s", "n_gpus": 1, "higher_is_better": False,
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "fig7_cylinder_100x150_Re1290_tau0.005", "walls": "wet-node",
+                       "population_storage": "f64", "nodes": nr * nz},
+            "bgk": {"status": L.STATUS_NAMES[int(bgk.status[0])], "steps": int(bgk.steps[0])},
+            "mrt": {"status": L.STATUS_NAMES[int(r.status[0])], "steps": steps,
+                    "residual": float(r.residual[0]),
+                    "mlups": round(nr * nz * steps / r.wall_s / 1e6, 1),
+                    "uz_max_over_Ut": round(abs(float(axis[i])) / Ut, 4),
+                    "h_max_over_H": round(i / (nz - 1.0), 4),
+                    "reversed_axis_nodes": reversed_},
+            "table2_re1290_tau0.02": {"uz_max_over_Ut": 0.0716, "h_max_over_H": 0.147}}
+
+
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16
 
 
@@ -335,6 +385,9 @@ def main():
         return
     if args.workload == "unet":
         print(json.dumps(nn_probe(args.steps, args.warmup)))
+        return
+    if args.workload == "fig7":
+        print(json.dumps(fig7_probe()))
         return
     if args.workload == "batch256_sequential":
         print(json.dumps(sequential_probe(args.steps)))
