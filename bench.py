@@ -24,6 +24,9 @@ Workloads (synthetic, seeded):
              and forward passes (batch 16), TFLOP/s against the BF16 MFMA peak
   warmstart  the learned warm start end to end: time to residual 1e-8
   batch256_sequential   the 256 cavities one handle after another
+  wheeler    Wheeler's crystal/crucible benchmark, both Table 1 cases (100 x 100
+             and the second also at 200 x 200,
+             wet-node walls, FP64) to the Eq. 57 residual 1e-8, psi extrema
   fig7       the paper's Fig. 7 run (100 x 150 rotating-lid cylinder, Re 1290,
              tau = 0.005, wet-node walls, FP64): BGK until it diverges, MRT
              to the Eq. 57 residual 1e-10, the axis maximum against Table 2
@@ -219,6 +222,40 @@ def warmstart_probe():
     }
 
 
+def wheeler_probe():
+    """Both Table 1 cases of Wheeler's benchmark in one batched FP64 handle
+    from rest to the Eq. (57) residual 1e-8; the stream-function extrema in
+    units of nu R_c next to the paper's."""
+    from paper_1003_0282_amd import lbaxi as L
+    from paper_1003_0282_amd import steady as ST
+    from paper_1003_0282_amd import streamfn as SF
+    from paper_1003_0282_amd import workloads as W
+    table1 = {(100.0, -25.0): (-0.0494, 0.1180), (1000.0, -250.0): (-1.444, 1.128)}
+    cases = [W.wheeler(*k) for k in table1] + [W.wheeler(1000.0, -250.0, n=200)]
+    r = ST.solve(cases, tol=1e-8, max_steps=3_000_000, check_every=2000, prec=L.FP64)
+    per = []
+    off = 0
+    for k, c in enumerate(cases):
+        n = c["nr"] * c["nz"]
+        lo, hi = SF.wheeler_extrema(c, r.fields["uz"][off:off + n])
+        off += n
+        p = table1[(c["Re_x"], c["Re_c"])]
+        per.append({"grid": "%dx%d" % (c["nr"], c["nz"]), "Re_x": c["Re_x"], "Re_c": c["Re_c"],
+                    "tau_s": c["tau"],
+                    "status": L.STATUS_NAMES[int(r.status[k])], "steps": int(r.steps[k]),
+                    "psi_min": round(lo, 4), "psi_max": round(hi, 4),
+                    "paper_psi_min": p[0], "paper_psi_max": p[1]})
+    nodes = sum(c["nr"] * c["nz"] for c in cases)
+    return {"metric": "Wheeler benchmark: wall time to the Eq. 57 residual 1e-8 (both Table 1 "
+                      "cases at 100 x 100 and the second at 200 x 200, one handle)",
+            "value": round(r.wall_s, 2), "unit": "s", "n_gpus": 1, "higher_is_better": False,
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "wheeler_table1", "lattices": len(cases),
+                       "walls": "wet-node", "population_storage": "f64", "nodes": nodes},
+            "mlups": round(sum(c["nr"] * c["nz"] * float(s) for c, s in zip(cases, r.steps))
+                           / r.wall_s / 1e6, 1), "cases": per}
+
+
 def fig7_probe(budget_s: float = 240.0):
     """Fig. 7: the rotating-lid cylinder of Table 2 at Re = 1290 with nu =
     0.005 / 3 (tau_s = 0.505).  The BGK handle runs until its residual turns
@@ -385,6 +422,9 @@ def main():
         return
     if args.workload == "unet":
         print(json.dumps(nn_probe(args.steps, args.warmup)))
+        return
+    if args.workload == "wheeler":
+        print(json.dumps(wheeler_probe()))
         return
     if args.workload == "fig7":
         print(json.dumps(fig7_probe()))

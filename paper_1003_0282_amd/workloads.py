@@ -172,6 +172,26 @@ def melt(Re_c: float, Re_x: float, Gr: float, nr: int = 128, nz: int = 256,
                      Re_c=float(Re_c), Re_x=float(Re_x), Gr=float(Gr))
 
 
+def wheeler(Re_x: float, Re_c: float, n: int = 100, U_t: float = 0.1, beta: float = 0.4,
+            wet: bool = True) -> dict:
+    """Wheeler's Czochralski benchmark as the paper sets it up (Sec. IV B):
+    isothermal melt of height H = R_c in a crucible of radius R_c rotating at
+    Omega_c (side wall and bottom), a crystal disk r <= beta R_c on the top
+    rotating at Omega_x, a flat stress-free surface beside it; n x n nodes;
+    Re_c = R_c^2 Omega_c / nu, Re_x = R_c^2 Omega_x / nu; the lid speed
+    U_t = beta R_c Omega_x fixes nu = U_t R_c / (beta |Re_x|).  With wet-node
+    walls (the paper's treatment) R_c = H = n - 1."""
+    Rc = n - (1.0 if wet else 0.5)
+    nu = U_t * Rc / (beta * abs(Re_x))
+    om_x = Re_x * nu / Rc ** 2
+    om_c = Re_c * nu / Rc ** 2
+    top = split_wall(wall(omega=om_x), freeslip(), beta * Rc)
+    return base_case(n, n, 3.0 * nu + 0.5, swirl=True, south=axis(), north=wall(omega=om_c),
+                     west=wall(omega=om_c), east=top, wet=bool(wet),
+                     name="wheeler_Rex%g_Rec%g%s" % (Re_x, Re_c, "_wet" if wet else ""),
+                     Re_x=float(Re_x), Re_c=float(Re_c), nu=float(nu), R_c=float(Rc))
+
+
 def melt_set(n: int, seed: int, nr: int = 128, nz: int = 256, re_max: float = 1000.0,
              signed: bool = False, gr_range=(1e3, 1e5), nu: float = 0.0125,
              wet: bool = False) -> list[dict]:
