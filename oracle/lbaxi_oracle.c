@@ -35,6 +35,8 @@
  *                periodic ends, specular reflection on the axis (Sec. IV A),
  *                halfway bounce-back / moving walls, free slip
  *   residual     Eq. (57)
+ *   *_orig       the original scheme of Sec. II (Eqs. 7-10) that the paper
+ *                improves on, with lagged central-difference gradients
  * At r = 0 every term carrying 1/r is taken as zero (Sec. IV A).
  *
  * Parity of the temperature row is unpinned by the paper (it defines no
@@ -107,6 +109,7 @@ typedef struct {
   int mrt;                  /* 1: f collides with the MRT model (Sec. III B) */
   double s_e, s_eps, s_q;   /* MRT rates of e, epsilon and q (s_v = 1/(tau+1/2)) */
   double s_rho, s_j;        /* rates of the conserved moments (they drop out) */
+  int original;             /* 1: the original scheme of Eqs. (5)-(10), f only */
 } orc_params;
 
 typedef struct {
@@ -114,6 +117,8 @@ typedef struct {
   double *f, *g, *h;    /* state f^(t), g(t), h(t) */
   double *fs, *gs, *hs; /* post-collision f*, g*, h* (step scratch) */
   double *spd;          /* |u| at the previous time level */
+  double *uzp, *urp;    /* original scheme: velocity of the last collided level */
+  double *uzn, *urn;    /* (and of the level being collided) */
   int have_spd;
   int64_t t;
 } orc_state;
@@ -402,6 +407,69 @@ void orc_node_collide(const orc_params* p, int j, int64_t t, const double* fh,
   }
 }
 
+/* ---- the original scheme (Sec. II, Eqs. 5-10) ---------------------------------
+ * Premnath and Abraham's scheme as the paper restates it: f~ = f - Omega/2 -
+ * G/2 collides by Eq. (8) with the constant rate omega = 1/(tau + 1/2) and
+ * the source of Eq. (7),
+ *   G_a = -w_a rho u_r / r + (e_a - u).F / (rho cs^2) f_eq_a,
+ *   F_i = (mu / r) D_i - 2 mu u_i delta_ir / r^2 - rho u_i u_r / r
+ *         (+ the body force along z),
+ * with D_r = 2 d_r u_r and D_z = d_r u_z + d_z u_r; the macros are Eqs.
+ * (9)-(10).  mu -> mu0 as in the improved scheme.  The paper gives no
+ * stencil for D: D is supplied by the caller (see lagged_grad).  With D
+ * known, Eqs. (9)-(10) solve explicitly: s0 = sum f~ = rho (1 + u_r / 2r),
+ *   u_r = (sum e_r f~ + mu0 D_r / 2r) / (s0 + mu0 / r^2),
+ *   u_z = (sum e_z f~ + mu0 D_z / 2r + a / 2) / s0,  rho = s0 / (1 + u_r / 2r).
+ * Only f is modelled (no swirl or temperature fields in this scheme).       */
+void orc_node_macros_orig(const orc_params* p, int j, int64_t t,
+                          const double* fh, double Dr, double Dz, double* out) {
+  double ir = inv_r(p, j);
+  double mu0 = p->rho0 * p->tau / 3.0;
+  double s0 = 0, sz = 0, sr = 0;
+  for (int a = 0; a < 9; ++a) {
+    s0 += fh[a];
+    sz += EZ9[a] * fh[a];
+    sr += ER9[a] * fh[a];
+  }
+  double ur = (sr + 0.5 * mu0 * Dr * ir) / (s0 + mu0 * ir * ir);
+  double uz = (sz + 0.5 * (mu0 * Dz * ir + orc_force_a(p, t))) / s0;
+  out[0] = s0 / (1.0 + 0.5 * ur * ir);
+  out[1] = uz;
+  out[2] = ur;
+  out[3] = 0.0;
+  out[4] = p->T_ref;
+}
+
+/* Eq. (7) at a node with macros m and gradient terms D. */
+void orc_node_source_orig(const orc_params* p, int j, int64_t t,
+                          const double* m, double Dr, double Dz,
+                          const double* feq, double* G) {
+  double ir = inv_r(p, j);
+  double mu0 = p->rho0 * p->tau / 3.0;
+  const double cs2 = 1.0 / 3.0;
+  double rho = m[0], uz = m[1], ur = m[2];
+  double Fr = mu0 * ir * Dr - 2.0 * mu0 * ur * ir * ir - rho * ur * ur * ir;
+  double Fz = mu0 * ir * Dz - rho * uz * ur * ir + orc_force_a(p, t);
+  for (int a = 0; a < 9; ++a) {
+    double eF = (EZ9[a] - uz) * Fz + (ER9[a] - ur) * Fr;
+    G[a] = -W9[a] * rho * ur * ir + eF / (rho * cs2) * feq[a];
+  }
+}
+
+/* Eq. (8) at one node: macros (Eqs. 9-10), then the BGK update with the
+ * constant rate and the source of Eq. (7). */
+void orc_node_collide_orig(const orc_params* p, int j, int64_t t,
+                           const double* fh, double Dr, double Dz, double* fo,
+                           double* m) {
+  double feq[9], G[9];
+  orc_node_macros_orig(p, j, t, fh, Dr, Dz, m);
+  orc_feq9(m[0], m[1], m[2], feq);
+  orc_node_source_orig(p, j, t, m, Dr, Dz, feq, G);
+  double w = 1.0 / (p->tau + 0.5);
+  for (int a = 0; a < 9; ++a)
+    fo[a] = fh[a] - w * (fh[a] - feq[a]) + (1.0 - 0.5 * w) * G[a];
+}
+
 /* ---- boundaries ------------------------------------------------------------
  * A wall lies half a lattice spacing outside the last fluid node.  A
  * population whose upstream node lies outside the domain takes the rule of the
@@ -541,9 +609,15 @@ orc_state* orc_create(const orc_params* p) {
   s->h = (double*)calloc(4 * n, sizeof(double));
   s->hs = (double*)calloc(4 * n, sizeof(double));
   s->spd = (double*)calloc(n, sizeof(double));
-  if (!s->f || !s->fs || !s->g || !s->gs || !s->h || !s->hs || !s->spd) {
+  s->uzp = (double*)calloc(n, sizeof(double));
+  s->urp = (double*)calloc(n, sizeof(double));
+  s->uzn = (double*)calloc(n, sizeof(double));
+  s->urn = (double*)calloc(n, sizeof(double));
+  if (!s->f || !s->fs || !s->g || !s->gs || !s->h || !s->hs || !s->spd ||
+      !s->uzp || !s->urp || !s->uzn || !s->urn) {
     free(s->f); free(s->fs); free(s->g); free(s->gs); free(s->h);
-    free(s->hs); free(s->spd); free(s);
+    free(s->hs); free(s->spd); free(s->uzp); free(s->urp); free(s->uzn);
+    free(s->urn); free(s);
     return NULL;
   }
   return s;
@@ -552,7 +626,8 @@ orc_state* orc_create(const orc_params* p) {
 void orc_destroy(orc_state* s) {
   if (!s) return;
   free(s->f); free(s->fs); free(s->g); free(s->gs); free(s->h);
-  free(s->hs); free(s->spd); free(s);
+  free(s->hs); free(s->spd); free(s->uzp); free(s->urp); free(s->uzn);
+  free(s->urn); free(s);
 }
 
 int64_t orc_time(const orc_state* s) { return s->t; }
@@ -582,6 +657,73 @@ static void node_inputs(const orc_state* s, int i, int j, double* f, double* g,
   }
 }
 
+/* Velocity of node (i, j) of the field (uz, ur), for i in [-1, nz] and j in
+ * [-1, nr] (never both outside): ghost values are mirrored across the axis
+ * (u_r odd) and across a free-slip end (u_z odd), wrapped at periodic ends,
+ * and 2 u_w - u beyond a halfway wall (linear through the wall, which lies
+ * half a spacing out). */
+static void vel_at(const orc_params* p, const double* uz, const double* ur,
+                   int i, int j, double* vz, double* vr) {
+  if (i < 0 || i >= p->nz) {
+    const orc_side* s = &p->side[i < 0 ? 2 : 3];
+    int in = i < 0 ? 0 : p->nz - 1;
+    if (s->kind == ORC_PERIODIC) {
+      int iw = (i + p->nz) % p->nz;
+      *vz = uz[(size_t)j * p->nz + iw];
+      *vr = ur[(size_t)j * p->nz + iw];
+      return;
+    }
+    double z0 = uz[(size_t)j * p->nz + in], r0v = ur[(size_t)j * p->nz + in];
+    seg_t sg = zwall_segment(p, s, j);
+    if (sg.kind == ORC_FREESLIP) {
+      *vz = -z0;
+      *vr = r0v;
+    } else {
+      *vz = 2.0 * s->uz - z0;
+      *vr = 2.0 * s->ur - r0v;
+    }
+    return;
+  }
+  if (j < 0) {
+    const orc_side* s = &p->side[0];
+    if (s->kind == ORC_AXIS) {
+      *vz = uz[(size_t)1 * p->nz + i];
+      *vr = -ur[(size_t)1 * p->nz + i];
+    } else {
+      *vz = 2.0 * s->uz - uz[i];
+      *vr = 2.0 * s->ur - ur[i];
+    }
+    return;
+  }
+  if (j >= p->nr) {
+    const orc_side* s = &p->side[1];
+    size_t o = (size_t)(p->nr - 1) * p->nz + i;
+    *vz = 2.0 * s->uz - uz[o];
+    *vr = 2.0 * s->ur - ur[o];
+    return;
+  }
+  *vz = uz[(size_t)j * p->nz + i];
+  *vr = ur[(size_t)j * p->nz + i];
+}
+
+/* The gradient terms of Eq. (7), D_r = 2 d_r u_r and D_z = d_r u_z + d_z u_r,
+ * by second-order central differences of the given velocity field (the
+ * paper gives no stencil).  They enter only multiplied by 1/r, so they are
+ * zero where 1/r is taken as zero. */
+static void grad_terms(const orc_params* p, const double* uz, const double* ur,
+                       int i, int j, double* Dr, double* Dz) {
+  *Dr = 0.0;
+  *Dz = 0.0;
+  if (inv_r(p, j) == 0.0) return;
+  double zn, rn, zs, rs, ze, re, zw, rw;
+  vel_at(p, uz, ur, i, j + 1, &zn, &rn);
+  vel_at(p, uz, ur, i, j - 1, &zs, &rs);
+  vel_at(p, uz, ur, i + 1, j, &ze, &re);
+  vel_at(p, uz, ur, i - 1, j, &zw, &rw);
+  *Dr = rn - rs;                          /* 2 (rn - rs) / 2 */
+  *Dz = 0.5 * (zn - zs) + 0.5 * (re - rw);
+}
+
 /* Equilibrium seeding: f^ = f_eq(rho, u) - S(rho, u)/2 (the paper's
  * f^ = f - Omega/2 - S/2 with Omega = 0), g = g_eq, h = h_eq.  NULL fields
  * mean rho0 / zero velocity / T_ref.  On the axis row u_r and u_th are forced
@@ -592,6 +734,13 @@ void orc_seed(orc_state* s, const double* uz, const double* ur,
   const orc_params* p = &s->p;
   s->t = 0;
   s->have_spd = 0;
+  /* original scheme: the seeded velocity is the field its gradients start from */
+  for (int j = 0; j < p->nr; ++j)
+    for (int i = 0; i < p->nz; ++i) {
+      size_t n = (size_t)j * p->nz + i;
+      s->uzp[n] = uz ? uz[n] : 0.0;
+      s->urp[n] = (ur && !is_axis_row(p, j)) ? ur[n] : 0.0;
+    }
   for (int j = 0; j < p->nr; ++j)
     for (int i = 0; i < p->nz; ++i) {
       size_t n = (size_t)j * p->nz + i;
@@ -604,7 +753,14 @@ void orc_seed(orc_state* s, const double* uz, const double* ur,
       if (is_axis_row(p, j)) { m[2] = 0.0; m[3] = 0.0; }
       double feq[9], S[9], geq[4], heq[4];
       orc_feq9(m[0], m[1], m[2], feq);
-      orc_node_source(p, j, 0, m, feq, S);
+      if (p->original) {
+        /* f~ = f_eq - G/2 with D from the seeded velocity field */
+        double Dr, Dz;
+        grad_terms(p, s->uzp, s->urp, i, j, &Dr, &Dz);
+        orc_node_source_orig(p, j, 0, m, Dr, Dz, feq, S);
+      } else {
+        orc_node_source(p, j, 0, m, feq, S);
+      }
       for (int a = 0; a < 9; ++a) s->f[IDX(p, a, j, i)] = feq[a] - 0.5 * S[a];
       if (p->swirl) {
         orc_geq4(p->rho0, m[3], m[1], m[2], geq);
@@ -618,16 +774,29 @@ void orc_seed(orc_state* s, const double* uz, const double* ur,
 }
 
 /* Macroscopic fields of the current state; any output may be NULL. */
+/* Macros of node (i, j) at the current level (Eqs. 16-17, or Eqs. 9-10 of
+ * the original scheme with D from the last collided level's velocity). */
+static void state_macros(const orc_state* s, int i, int j, double* m) {
+  double f[9], g[4], h[4];
+  node_inputs(s, i, j, f, g, h);
+  if (s->p.original) {
+    double Dr, Dz;
+    grad_terms(&s->p, s->uzp, s->urp, i, j, &Dr, &Dz);
+    orc_node_macros_orig(&s->p, j, s->t, f, Dr, Dz, m);
+  } else {
+    orc_node_macros(&s->p, j, s->t, f, g, h, m);
+  }
+}
+
 void orc_macros(const orc_state* s, double* rho, double* uz, double* ur,
                 double* uth, double* T) {
   const orc_params* p = &s->p;
 #pragma omp parallel for schedule(static) if (par_ok(p))
   for (int j = 0; j < p->nr; ++j)
     for (int i = 0; i < p->nz; ++i) {
-      double f[9], g[4], h[4], m[5];
+      double m[5];
       size_t n = (size_t)j * p->nz + i;
-      node_inputs(s, i, j, f, g, h);
-      orc_node_macros(p, j, s->t, f, g, h, m);
+      state_macros(s, i, j, m);
       if (rho) rho[n] = m[0];
       if (uz) uz[n] = m[1];
       if (ur) ur[n] = m[2];
@@ -749,15 +918,29 @@ void orc_step(orc_state* s, int64_t n) {
     for (int j = 0; j < p->nr; ++j)
       for (int i = 0; i < p->nz; ++i) {
         double f[9], g[4], h[4], fo[9], go[4], ho[4], m[5];
+        size_t q = (size_t)j * p->nz + i;
         node_inputs(s, i, j, f, g, h);
-        orc_node_collide(p, j, s->t, f, g, h, fo, go, ho, m);
+        if (p->original) {
+          /* D lags one level: the velocity of the previous collision */
+          double Dr, Dz;
+          grad_terms(p, s->uzp, s->urp, i, j, &Dr, &Dz);
+          orc_node_collide_orig(p, j, s->t, f, Dr, Dz, fo, m);
+          s->uzn[q] = m[1];
+          s->urn[q] = m[2];
+        } else {
+          orc_node_collide(p, j, s->t, f, g, h, fo, go, ho, m);
+        }
         for (int a = 0; a < 9; ++a) s->fs[IDX(p, a, j, i)] = fo[a];
         if (p->swirl)
           for (int a = 0; a < 4; ++a) s->gs[IDX(p, a, j, i)] = go[a];
         if (p->thermal)
           for (int a = 0; a < 4; ++a) s->hs[IDX(p, a, j, i)] = ho[a];
-        s->spd[(size_t)j * p->nz + i] = sqrt(m[1] * m[1] + m[2] * m[2]);
+        s->spd[q] = sqrt(m[1] * m[1] + m[2] * m[2]);
       }
+    if (p->original) {
+      double* tz = s->uzp; s->uzp = s->uzn; s->uzn = tz;
+      double* tr = s->urp; s->urp = s->urn; s->urn = tr;
+    }
     s->have_spd = 1;
     stream_all(s);
     s->t += 1;
@@ -775,9 +958,8 @@ double orc_residual(const orc_state* s) {
   int bad = 0;
   for (int j = 0; j < p->nr; ++j)
     for (int i = 0; i < p->nz; ++i) {
-      double f[9], g[4], h[4], m[5];
-      node_inputs(s, i, j, f, g, h);
-      orc_node_macros(p, j, s->t, f, g, h, m);
+      double m[5];
+      state_macros(s, i, j, m);
       double d = fabs(sqrt(m[1] * m[1] + m[2] * m[2]) -
                       s->spd[(size_t)j * p->nz + i]);
       if (d != d) bad = 1;

@@ -64,6 +64,7 @@ class _Params(C.Structure):
         ("s_q", C.c_double),
         ("s_rho", C.c_double),
         ("s_j", C.c_double),
+        ("original", C.c_int),
     ]
 
 
@@ -173,6 +174,10 @@ def params(case: dict) -> _Params:
     p.s_q = float(case.get("s_q", 0.0)) or 1.0 / (0.5 + 3.0 / (16.0 * tau))
     p.s_rho = float(case.get("s_rho", 1.0))
     p.s_j = float(case.get("s_j", 1.0))
+    # the original scheme of Sec. II (Eqs. 5-10): f only, halfway walls
+    p.original = int(bool(case.get("original", False)))
+    if p.original and (p.swirl or p.thermal or p.wet or p.mrt):
+        raise ValueError("the original scheme models f only, with halfway walls and BGK")
     return p
 
 
