@@ -81,13 +81,20 @@ enum { LBAXI_FP64 = 0, LBAXI_FP32 = 1, LBAXI_FP32_FAST = 2 };
  * and T (fixed-temperature walls) take the wall values.  Needs nz, nr >= 3.
  * LBAXI_MRT selects the MRT collision of f (Sec. III B; rates in
  * lbaxi_desc.s_e, s_eps, s_q, with s_v = 1/tau fixed by the viscosity);
- * seeding and wet-node walls then use its source, S = M^-1 S~. */
+ * seeding and wet-node walls then use its source, S = M^-1 S~.
+ * LBAXI_ORIGINAL runs instead the original scheme the paper improves on
+ * (Sec. II): Eq. (8) with the constant rate 1/(tau + 1/2), the source of
+ * Eq. (7) and the macros of Eqs. (9)-(10), whose velocity-gradient terms are
+ * central differences of the previous level's velocity (the handle keeps
+ * that field: 2 values per node more in the workspace, read and written
+ * each step).  f only: not with SWIRL, THERMAL, WET_WALLS or MRT. */
 enum {
   LBAXI_SWIRL = 1u,
   LBAXI_THERMAL = 2u,
   LBAXI_CARTESIAN = 4u,
   LBAXI_WET_WALLS = 8u,
-  LBAXI_MRT = 16u
+  LBAXI_MRT = 16u,
+  LBAXI_ORIGINAL = 32u
 };
 enum {
   LBAXI_SIDE_AXIS = 0,     /* south side only, r0 = 0: specular axis */
@@ -120,7 +127,7 @@ typedef struct {
   int32_t nz, nr;   /* nodes along z and r, each >= 2 */
   double r0;        /* radius of node row 0; 0 with an axis south side */
   int32_t prec;     /* LBAXI_FP64 / _FP32 / _FP32_FAST (same for a whole batch) */
-  uint32_t fields;  /* LBAXI_SWIRL | _THERMAL | _CARTESIAN | _WET_WALLS | _MRT */
+  uint32_t fields;  /* LBAXI_SWIRL | _THERMAL | _CARTESIAN | _WET_WALLS | _MRT | _ORIGINAL */
   double tau;       /* tau_s of f */
   double tau_g;     /* tau_s of g, 0 -> paper default */
   double tau_h;     /* tau_s of h, 0 -> tau */
@@ -149,8 +156,8 @@ const char* lbaxi_strerror(lbaxi_status s);
 lbaxi_status lbaxi_workspace_bytes(int32_t n, const lbaxi_desc* descs, size_t* bytes);
 
 /* Create a handle over n lattices (all the same prec, the same SWIRL and
- * THERMAL bits and the same collision model; CARTESIAN and WET_WALLS may
- * differ between lattices), carving
+ * THERMAL bits and the same scheme (BGK, MRT or ORIGINAL); CARTESIAN and
+ * WET_WALLS may differ between lattices), carving
  * d_workspace (>= lbaxi_workspace_bytes, 256-byte aligned) and enqueuing on
  * hip_stream (a hipStream_t; NULL = the null stream).  Validates every
  * descriptor: EINVAL for bad sizes or side combinations (axis only as south

@@ -71,6 +71,19 @@ struct StepArgs {
   int tr;
   int xcd;
   int nt_store;
+  // original scheme: lagged velocity fields (u_z at +0, u_r at +lag_stride,
+  // packed [nr][nz] per lattice at its field offset), read and written
+  const S* lag_src;
+  S* lag_dst;
+  long long lag_stride;
+};
+
+// The two lagged velocity buffers of the original scheme, for the macro and
+// residual kernels (the one of parity D.cur holds the last collided level).
+struct Lag {
+  const void* A;
+  const void* B;
+  long long stride;
 };
 
 template <typename S>
@@ -237,8 +250,20 @@ __device__ inline void finish_node(const StepArgs<S>& A, const InstP& P, const P
                                    int j, R* f, R* g, R* h) {
   const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
   const Row<R> rw = make_row<R, F>(p, j);
-  const Mac<R> m = macros<R, F>(p, rw, axis_row, f, g, h);
-  collide<R, F>(p, rw, m, f, g, h);
+  Mac<R> m;
+  if (F & F_ORIG) {
+    R Dr, Dz;
+    const S* lz = A.lag_src + P.off_fld;
+    lag_grad<S, R>(P, rw, lz, lz + A.lag_stride, i, j, Dr, Dz);
+    m = macros_orig<R>(p, rw, f, Dr, Dz);
+    collide_f_orig<R>(p, rw, m, f);
+    S* ld = A.lag_dst + P.off_fld + (long long)j * P.nz + i;
+    ld[0] = (S)m.uz;
+    ld[A.lag_stride] = (S)m.ur;
+  } else {
+    m = macros<R, F>(p, rw, axis_row, f, g, h);
+    collide<R, F>(p, rw, m, f, g, h);
+  }
   S* d = A.dst + P.off;
   const int pl = P.plane;
   const unsigned ob = (unsigned)nidx(P, j, i) * (unsigned)sizeof(S);
@@ -344,7 +369,7 @@ __global__ void __launch_bounds__(1024) k_seed(const InstP* ip, const Tile* tile
                                                const int* ntiles, S* buf, const S* rho_in,
                                                const S* uz_in,
                                                const S* ur_in, const S* uth_in, const S* T_in,
-                                               int tzlog) {
+                                               int tzlog, const S* lag, long long lag_stride) {
   const int ti = blockIdx.x;
   if (ti >= *ntiles) return;
   const Tile T = cload(tiles + ti);
@@ -369,6 +394,25 @@ __global__ void __launch_bounds__(1024) k_seed(const InstP* ip, const Tile* tile
   const R usq = uz * uz + ur * ur;
   S* d = buf + P.off;
   const int pl = P.plane, o = nidx(P, j, i);
+  if (F & F_ORIG) {
+    // f~ = f_eq - G/2 with G of Eq. (7), D from the seeded velocity field
+    // (already in the lagged buffer)
+    const Row<R> rw = make_row<R, F>(p, j);
+    R Dr, Dz;
+    lag_grad<S, R>(P, rw, lag + P.off_fld, lag + P.off_fld + lag_stride, i, j, Dr, Dz);
+    const R Fro = p.mu0 * ir * Dr - (R)2 * p.mu0 * ur * rw.ir2 - rho * ur * ur * ir;
+    const R Fzo = p.mu0 * ir * Dz - rho * uz * ur * ir + p.a_t;
+    const R uF = uz * Fzo + ur * Fro;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      const R ez = (R)ez9(a), er = (R)er9(a), wa = (R)w9(a);
+      const R eu = ez * uz + er * ur;
+      const R Pa = (R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * usq;
+      const R G = wa * ((R)3 * ((R)1 + Pa) * (ez * Fzo + er * Fro - uF) - rho * ur * ir);
+      d[a * pl + o] = (S)(wa * (drho + rho * Pa) - (R)0.5 * G);
+    }
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
     const R ez = (R)ez9(a), er = (R)er9(a), w = (R)w9(a);
@@ -393,13 +437,41 @@ __global__ void __launch_bounds__(1024) k_seed(const InstP* ip, const Tile* tile
   }
 }
 
+// Original scheme: the seeded velocity written to the lagged buffer that the
+// first step (and the seeding of f~) takes its gradients from.
+template <typename S>
+__global__ void __launch_bounds__(1024) k_seed_lag(const InstP* ip, const Tile* tiles,
+                                                   const int* ntiles, const S* uz_in,
+                                                   const S* ur_in, S* lag, long long lag_stride,
+                                                   int tzlog) {
+  const int ti = blockIdx.x;
+  if (ti >= *ntiles) return;
+  const Tile T = cload(tiles + ti);
+  const InstP P = cload(ip + T.inst);
+  const int tz = 1 << tzlog;
+  const int i = T.z0 + (threadIdx.x & (tz - 1)), j = T.r0 + (threadIdx.x >> tzlog);
+  if (i >= P.nz || j >= P.nr) return;
+  const long long fo = P.off_fld + (long long)j * P.nz + i;
+  const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
+  lag[fo] = uz_in ? uz_in[fo] : (S)0;
+  lag[fo + lag_stride] = (ur_in && !axis_row) ? ur_in[fo] : (S)0;
+}
+
 // Macros at the current level of each lattice (own buffer parity and time).
 template <typename S, typename R, int F>
 __device__ inline Mac<R> node_macros(const InstP& P, const InstP* Pg, const InstDyn& D,
-                                     const S* bufA, const S* bufB, int i, int j) {
+                                     const S* bufA, const S* bufB, const Lag& lag, int i, int j) {
   const PR<R> p = make_pr<R>(P, D.t);
   const S* s = (D.cur ? bufB : bufA) + P.off;
   R f[9], g[4], h[4];
+  if (F & F_ORIG) {
+    load_node<S, R, F>(P, s, i, j, D.pre != 0, f, g, h);
+    const Row<R> rw = make_row<R, F>(p, j);
+    const S* lz = static_cast<const S*>(D.cur ? lag.B : lag.A) + P.off_fld;
+    R Dr, Dz;
+    lag_grad<S, R>(P, rw, lz, lz + lag.stride, i, j, Dr, Dz);
+    return macros_orig<R>(p, rw, f, Dr, Dz);
+  }
   WetRule w;
   if (P.wet && !D.pre && wet_rule(P, Pg, i, j, &w))
     wall_state<S, R, F>(P, p, s, i, j, w, f, g, h);
@@ -414,7 +486,7 @@ template <typename S, typename R, int F>
 __global__ void __launch_bounds__(1024) k_macros(const InstP* ip, const InstDyn* dyn,
                                                  const Tile* tiles, const int* ntiles,
                                                  const S* bufA, const S* bufB, S* rho, S* uz,
-                                                 S* ur, S* uth, S* T, int tzlog) {
+                                                 S* ur, S* uth, S* T, int tzlog, Lag lag) {
   const int ti = blockIdx.x;
   if (ti >= *ntiles) return;
   const Tile Tl = cload(tiles + ti);
@@ -422,7 +494,7 @@ __global__ void __launch_bounds__(1024) k_macros(const InstP* ip, const InstDyn*
   const int tz = 1 << tzlog;
   const int i = Tl.z0 + (threadIdx.x & (tz - 1)), j = Tl.r0 + (threadIdx.x >> tzlog);
   if (i >= P.nz || j >= P.nr) return;
-  const Mac<R> m = node_macros<S, R, F>(P, ip + Tl.inst, dyn[Tl.inst], bufA, bufB, i, j);
+  const Mac<R> m = node_macros<S, R, F>(P, ip + Tl.inst, dyn[Tl.inst], bufA, bufB, lag, i, j);
   const long long o = P.off_fld + (long long)j * P.nz + i;
   if (rho) rho[o] = (S)m.rho;
   if (uz) uz[o] = (S)m.uz;
@@ -443,7 +515,7 @@ __global__ void __launch_bounds__(1024) k_residual(const InstP* ip, const InstDy
                                                    const Tile* tiles, const int* ntiles,
                                                    const S* bufA, const S* bufB,
                                                    const double* spd, unsigned long long* res,
-                                                   int tzlog) {
+                                                   int tzlog, Lag lag) {
   __shared__ unsigned long long red[16];
   const int ti = blockIdx.x;
   if (ti >= *ntiles) return;  // uniform per workgroup
@@ -453,7 +525,7 @@ __global__ void __launch_bounds__(1024) k_residual(const InstP* ip, const InstDy
   const int i = Tl.z0 + (threadIdx.x & (tz - 1)), j = Tl.r0 + (threadIdx.x >> tzlog);
   unsigned long long v = 0;
   if (i < P.nz && j < P.nr) {
-    const Mac<R> m = node_macros<S, R, F>(P, ip + Tl.inst, dyn[Tl.inst], bufA, bufB, i, j);
+    const Mac<R> m = node_macros<S, R, F>(P, ip + Tl.inst, dyn[Tl.inst], bufA, bufB, lag, i, j);
     const double sp = (double)sqrt(m.uz * m.uz + m.ur * m.ur);
     v = key(sp - spd[P.off_fld + (long long)j * P.nz + i]);
   }
@@ -561,7 +633,9 @@ long long padded_plane(const lbaxi_desc& x) {
 // residual words, the time base, two padded population buffers and |u| of
 // Eq. (57).
 struct Layout {
-  size_t ip, dyn, tiles_all, tiles_run, tiles_halo, counts, res, tdev, bufA, bufB, spd, total;
+  size_t ip, dyn, tiles_all, tiles_run, tiles_halo, counts, res, tdev, bufA, bufB, spd, lagA, lagB,
+      total;
+  long long lag_stride;  // elements between the u_z and u_r parts of a lagged buffer
   std::vector<long long> off, off_fld;
   long long buf_elems, fld_elems;
 };
@@ -593,6 +667,10 @@ Layout layout(const std::vector<lbaxi_desc>& d) {
   L.bufA = o; o = align_up(o + es * (size_t)e, 256);
   L.bufB = o; o = align_up(o + es * (size_t)e, 256);
   L.spd = o; o = align_up(o + sizeof(double) * (size_t)align_up(fe, 64), 256);
+  // original scheme: two lagged velocity buffers (u_z and u_r of every node)
+  L.lag_stride = (d[0].fields & LBAXI_ORIGINAL) ? (long long)align_up(fe, 64) : 0;
+  L.lagA = o; o = align_up(o + es * 2 * (size_t)L.lag_stride, 256);
+  L.lagB = o; o = align_up(o + es * 2 * (size_t)L.lag_stride, 256);
   L.total = o;
   return L;
 }
@@ -615,7 +693,10 @@ lbaxi_status validate(const lbaxi_desc& d, int k) {
     return bad(LBAXI_EINVAL, "lattice too large for 32-bit in-lattice offsets");
   if (d.prec != LBAXI_FP64 && d.prec != LBAXI_FP32 && d.prec != LBAXI_FP32_FAST)
     return bad(LBAXI_EINVAL, "bad prec");
-  if (d.fields & ~31u) return bad(LBAXI_EINVAL, "unknown field bits");
+  if (d.fields & ~63u) return bad(LBAXI_EINVAL, "unknown field bits");
+  if ((d.fields & LBAXI_ORIGINAL) &&
+      (d.fields & (LBAXI_SWIRL | LBAXI_THERMAL | LBAXI_WET_WALLS | LBAXI_MRT)))
+    return bad(LBAXI_EINVAL, "the original scheme models f only, with halfway walls");
   if ((d.fields & LBAXI_WET_WALLS) && (d.nz < 3 || d.nr < 3))
     return bad(LBAXI_EINVAL, "wet-node walls need nz and nr >= 3");
   if (!(d.rho0 > 0)) return bad(LBAXI_EINVAL, "rho0 must be positive");
@@ -653,7 +734,8 @@ lbaxi_status validate(const lbaxi_desc& d, int k) {
   for (int q = 0; q < 3; ++q) {
     if (!used[q]) continue;
     if (!(tt[q] > 0)) return bad(LBAXI_ERANGE, "relaxation time must exceed 1/2");
-    if (q == 0 && mrt) continue;  // the MRT rates of f do not depend on r
+    // the MRT rates and the original scheme's rate of f do not depend on r
+    if (q == 0 && (mrt || (d.fields & LBAXI_ORIGINAL))) continue;
     for (int j = 0; j < d.nr; ++j) {
       const double r = d.r0 + j;
       const double ir = ((d.fields & LBAXI_CARTESIAN) || r <= 0) ? 0.0 : 1.0 / r;
@@ -745,6 +827,8 @@ struct lbaxi_s {
   void* bufA = nullptr;
   void* bufB = nullptr;
   void* spd = nullptr;
+  void* lagA = nullptr;  // original scheme: lagged velocity, by buffer parity
+  void* lagB = nullptr;
   // state of the running lattices (all share parity and time)
   int cur = 0;
   bool pre = true;
@@ -840,9 +924,10 @@ void* resid_fn() { return reinterpret_cast<void*>(&k_residual<S, R, F>); }
    : ((fields) & 3) == 1 ? name<S, R, 1 | M>()  \
    : ((fields) & 3) == 2 ? name<S, R, 2 | M>()  \
                          : name<S, R, 3 | M>())
-#define PICK_F(name, S, R, fields)                                \
-  (((fields) & LBAXI_MRT) ? PICK_B(name, S, R, fields, F_MRT)     \
-                          : PICK_B(name, S, R, fields, 0))
+#define PICK_F(name, S, R, fields)                                      \
+  (((fields) & LBAXI_ORIGINAL) ? name<S, R, F_ORIG>()                   \
+   : ((fields) & LBAXI_MRT)    ? PICK_B(name, S, R, fields, F_MRT)      \
+                               : PICK_B(name, S, R, fields, 0))
 #define PICK(name, prec, fields)                                   \
   ((prec) == LBAXI_FP64   ? PICK_F(name, double, double, fields)   \
    : (prec) == LBAXI_FP32 ? PICK_F(name, float, double, fields)    \
@@ -879,6 +964,9 @@ StepLaunch step_launch(lbaxi_t* h, int list, int from, long long t0, bool use_td
   a.tr = h->tr;
   a.xcd = h->xcd;
   a.nt_store = h->nt;
+  a.lag_src = (const double*)(from ? h->lagB : h->lagA);
+  a.lag_dst = (double*)(from ? h->lagA : h->lagB);
+  a.lag_stride = h->L.lag_stride;
   return L;
 }
 
@@ -1062,7 +1150,8 @@ lbaxi_status residuals(lbaxi_t* h, std::vector<double>& out) {
   const Tile* tl = h->d_tiles[LIST_ALL];
   const int* nt = h->d_counts + LIST_ALL;
   int tzlog = ilog2(h->tz);
-  void* args[] = {&ip, &dy, &tl, &nt, &A, &B, &S, &r, &tzlog};
+  Lag lag = {h->lagA, h->lagB, h->L.lag_stride};
+  void* args[] = {&ip, &dy, &tl, &nt, &A, &B, &S, &r, &tzlog, &lag};
   HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])), dim3(h->tz * h->tr), args,
                          0, h->stream));
   std::vector<unsigned long long> bits(h->n);
@@ -1135,7 +1224,7 @@ lbaxi_status lbaxi_workspace_bytes(int32_t n, const lbaxi_desc* descs, size_t* b
   for (int k = 0; k < n; ++k) {
     lbaxi_status s = validate(d[k], k);
     if (s != LBAXI_OK) return s;
-    const unsigned kset = LBAXI_SWIRL | LBAXI_THERMAL | LBAXI_MRT;  // picks the kernels
+    const unsigned kset = LBAXI_SWIRL | LBAXI_THERMAL | LBAXI_MRT | LBAXI_ORIGINAL;
     if (d[k].prec != d[0].prec || (d[k].fields & kset) != (d[0].fields & kset))
       return fail(LBAXI_EINVAL,
                   "all lattices of a batch need the same prec, field set and collision model");
@@ -1177,6 +1266,8 @@ lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace,
   h->bufA = h->ws + h->L.bufA;
   h->bufB = h->ws + h->L.bufB;
   h->spd = h->ws + h->L.spd;
+  h->lagA = h->ws + h->L.lagA;
+  h->lagB = h->ws + h->L.lagB;
   for (int k = 0; k < n; ++k)
     h->ip.push_back(make_inst(h->desc[k], h->L.off[k], h->L.off_fld[k]));
   h->status.assign(n, LBAXI_RUNNING);
@@ -1226,7 +1317,17 @@ lbaxi_status lbaxi_seed(lbaxi_t* h, const void* d_rho, const void* d_uz, const v
   const int* nt = h->d_counts + LIST_ALL;
   void* buf = h->bufA;
   int tzlog = ilog2(h->tz);
-  void* args[] = {&ip, &tl, &nt, &buf, &d_rho, &d_uz, &d_ur, &d_uth, &d_T, &tzlog};
+  void* lag = h->lagA;
+  long long lag_stride = h->L.lag_stride;
+  if (h->fields & LBAXI_ORIGINAL) {
+    void* lfn = h->prec == LBAXI_FP64 ? reinterpret_cast<void*>(&k_seed_lag<double>)
+                                      : reinterpret_cast<void*>(&k_seed_lag<float>);
+    void* largs[] = {&ip, &tl, &nt, &d_uz, &d_ur, &lag, &lag_stride, &tzlog};
+    HIPCHK(hipLaunchKernel(lfn, dim3(std::max(1, h->count[LIST_ALL])), dim3(h->tz * h->tr),
+                           largs, 0, h->stream));
+  }
+  void* args[] = {&ip, &tl, &nt, &buf, &d_rho, &d_uz, &d_ur, &d_uth, &d_T, &tzlog, &lag,
+                  &lag_stride};
   HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])), dim3(h->tz * h->tr), args,
                          0, h->stream));
   h->cur = 0;
@@ -1264,7 +1365,8 @@ lbaxi_status lbaxi_macros(lbaxi_t* h, void* d_rho, void* d_uz, void* d_ur, void*
   const void* A = h->bufA;
   const void* B = h->bufB;
   int tzlog = ilog2(h->tz);
-  void* args[] = {&ip, &dy, &tl, &nt, &A, &B, &d_rho, &d_uz, &d_ur, &d_uth, &d_T, &tzlog};
+  Lag lag = {h->lagA, h->lagB, h->L.lag_stride};
+  void* args[] = {&ip, &dy, &tl, &nt, &A, &B, &d_rho, &d_uz, &d_ur, &d_uth, &d_T, &tzlog, &lag};
   HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])), dim3(h->tz * h->tr), args,
                          0, h->stream));
   return LBAXI_OK;
@@ -1466,7 +1568,8 @@ lbaxi_status lbaxi_state_bytes(const lbaxi_t* h, size_t* bytes) {
   if (!bytes) return fail(LBAXI_EINVAL, "NULL bytes");
   *bytes = sizeof(SaveHeader) + sizeof(InstDyn) * h->n + sizeof(int32_t) * h->n +
            sizeof(char) * h->n + elem_size(h->prec) * (size_t)h->L.buf_elems +
-           sizeof(double) * (size_t)h->L.fld_elems;
+           sizeof(double) * (size_t)h->L.fld_elems +
+           elem_size(h->prec) * 2 * (size_t)h->L.lag_stride;
   return LBAXI_OK;
 }
 
@@ -1515,6 +1618,17 @@ lbaxi_status lbaxi_save(lbaxi_t* h, void* host_buf, size_t bytes) {
   p += es * (size_t)h->L.buf_elems;
   HIPCHK(hipMemcpyAsync(p, h->spd, sizeof(double) * (size_t)h->L.fld_elems,
                         hipMemcpyDeviceToHost, h->stream));
+  p += sizeof(double) * (size_t)h->L.fld_elems;
+  // original scheme: each lattice's lagged velocity (buffer of its parity)
+  const long long ls = h->L.lag_stride;
+  for (int k = 0; k < h->n && ls > 0; ++k) {
+    const char* src = static_cast<const char*>(h->dyn[k].cur ? h->lagB : h->lagA);
+    const size_t o = es * (size_t)h->L.off_fld[k];
+    const size_t nb = es * (size_t)h->desc[k].nz * h->desc[k].nr;
+    HIPCHK(hipMemcpyAsync(p + o, src + o, nb, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(p + es * ls + o, src + es * ls + o, nb, hipMemcpyDeviceToHost,
+                          h->stream));
+  }
   HIPCHK(hipStreamSynchronize(h->stream));
   return LBAXI_OK;
 }
@@ -1548,6 +1662,16 @@ lbaxi_status lbaxi_load(lbaxi_t* h, const void* host_buf, size_t bytes) {
   p += es * (size_t)h->L.buf_elems;
   HIPCHK(hipMemcpyAsync(h->spd, p, sizeof(double) * (size_t)h->L.fld_elems,
                         hipMemcpyHostToDevice, h->stream));
+  p += sizeof(double) * (size_t)h->L.fld_elems;
+  const long long ls = h->L.lag_stride;
+  for (int k = 0; k < h->n && ls > 0; ++k) {
+    char* dst = static_cast<char*>(h->dyn[k].cur ? h->lagB : h->lagA);
+    const size_t o = es * (size_t)h->L.off_fld[k];
+    const size_t nb = es * (size_t)h->desc[k].nz * h->desc[k].nr;
+    HIPCHK(hipMemcpyAsync(dst + o, p + o, nb, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(dst + es * ls + o, p + es * ls + o, nb, hipMemcpyHostToDevice,
+                          h->stream));
+  }
   HIPCHK(hipStreamSynchronize(h->stream));
   h->t = H.t;
   h->cur = H.cur;

@@ -15,7 +15,7 @@ namespace lbx {
 
 enum { SIDE_AXIS = 0, SIDE_WALL = 1, SIDE_PERIODIC = 2, SIDE_FREESLIP = 3 };
 enum { SOUTH = 0, NORTH = 1, WEST = 2, EAST = 3 };
-enum { F_SWIRL = 1, F_THERMAL = 2, F_MRT = 4 };
+enum { F_SWIRL = 1, F_THERMAL = 2, F_MRT = 4, F_ORIG = 8 };
 enum { MODE_PRE = 1, MODE_SPEED = 2 };
 
 struct SideP {
@@ -295,6 +295,58 @@ __device__ inline void collide_f_mrt(const PR<R>& p, const Row<R>& w, const Mac<
   f[8] += (b2 - pc) - (X - Y);
 }
 
+// ---- the original scheme (Sec. II, Eqs. 5-10) ---------------------------------
+// Premnath and Abraham's scheme, kept as the comparison the paper improves
+// on: constant rate omega0, source Eq. (7)
+//   G_a = w_a [3 (1 + P_a)(e_a - u).F - rho u_r / r],
+//   F_r = mu0 D_r / r - 2 mu0 u_r / r^2 - rho u_r^2 / r,
+//   F_z = mu0 D_z / r - rho u_z u_r / r + a(t),
+// macros Eqs. (9)-(10).  D_r = 2 d_r u_r and D_z = d_r u_z + d_z u_r are
+// central differences of the velocity of the previous level, read from the
+// lagged velocity field (lag_grad below).
+
+// Eqs. (9)-(10) with D known: s0 = sum f = rho (1 + u_r / 2r),
+// u_r = (sum e_r f + mu0 D_r / 2r) / (s0 + mu0 / r^2),
+// u_z = (sum e_z f + mu0 D_z / 2r + a / 2) / s0; Fz, Fr hold Eq. (7)'s bracket.
+template <typename R>
+__device__ inline Mac<R> macros_orig(const PR<R>& p, const Row<R>& w, const R* f, R Dr, R Dz) {
+  Mac<R> m;
+  const R ir = w.ir;
+  const R s0d = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+  const R sz = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  const R sr = (f[2] - f[4]) + (f[5] - f[8]) + (f[6] - f[7]);
+  const R s0 = p.rho0 + s0d;
+  const R ur = (sr + (R)0.5 * p.mu0 * Dr * ir) * rcp(s0 + p.mu0 * w.ir2);
+  const R x = (R)0.5 * ur * ir;
+  m.drho = (s0d - p.rho0 * x) * rcp((R)1 + x);
+  m.rho = p.rho0 + m.drho;
+  m.uz = (sz + (R)0.5 * (p.mu0 * Dz * ir + p.a_t)) * rcp(s0);
+  m.ur = ur;
+  m.uth = (R)0;
+  m.dT = (R)0;
+  m.Fr = p.mu0 * ir * Dr - (R)2 * p.mu0 * ur * w.ir2 - m.rho * ur * ur * ir;
+  m.Fz = p.mu0 * ir * Dz - m.rho * m.uz * ur * ir + p.a_t;
+  return m;
+}
+
+// Eq. (8): f~ += -omega0 (f~ - f_eq) + (1 - omega0 / 2) G with G of Eq. (7),
+// in deviation form (f_eq = w (drho + rho P)).
+template <typename R>
+__device__ inline void collide_f_orig(const PR<R>& p, const Row<R>& w, const Mac<R>& m, R* f) {
+  const R uz = m.uz, ur = m.ur;
+  const R k15 = (R)1.5 * (uz * uz + ur * ur);
+  const R uF = uz * m.Fz + ur * m.Fr;
+  const R mass = m.rho * ur * w.ir;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    const R ez = (R)ez9(a), er = (R)er9(a), wa = (R)w9(a);
+    const R eu = ez * uz + er * ur;
+    const R Pa = (R)3 * eu + (R)4.5 * eu * eu - k15;
+    const R G = wa * ((R)3 * ((R)1 + Pa) * (ez * m.Fz + er * m.Fr - uF) - mass);
+    f[a] = f[a] - p.om0 * (f[a] - wa * (m.drho + m.rho * Pa)) + w.c0 * G;
+  }
+}
+
 // Eq. (13) with the source of Eq. (12) for f (or the MRT collision above);
 // Eq. (53)-(54) for g; the temperature analogue for h.  Updates the
 // populations in place.
@@ -407,6 +459,72 @@ __device__ inline void zseg_g(const InstP& P, const SideP* W, int j, int& kind, 
   omega = second ? cload(&W->omega2) : cload(&W->omega);
   thermal = second ? cload(&W->thermal2) : cload(&W->thermal);
   T = second ? cload(&W->T2) : cload(&W->T);
+}
+
+// Lagged velocity at (iu, ju), at most one of them outside the lattice:
+// mirrored across the axis (u_r odd) and a free-slip end (u_z odd), wrapped
+// at periodic ends, 2 u_w - u beyond a halfway wall.
+template <typename S, typename R>
+__device__ inline void lag_end(const InstP& P, const SideP& E, const S* uz, const S* ur,
+                               int iin, int iwrap, int ju, R& vz, R& vr) {
+  if (E.kind == SIDE_PERIODIC) {
+    vz = (R)uz[ju * P.nz + iwrap];
+    vr = (R)ur[ju * P.nz + iwrap];
+    return;
+  }
+  int kind, th;
+  double om, T;
+  zseg(P, E, ju, kind, om, th, T);
+  const R z0 = (R)uz[ju * P.nz + iin], r0 = (R)ur[ju * P.nz + iin];
+  if (kind == SIDE_FREESLIP) {
+    vz = -z0;
+    vr = r0;
+  } else {
+    vz = (R)2 * (R)E.uz - z0;
+    vr = (R)2 * (R)E.ur - r0;
+  }
+}
+
+template <typename S, typename R>
+__device__ inline void lag_at(const InstP& P, const S* uz, const S* ur, int iu, int ju, R& vz,
+                              R& vr) {
+  if (iu < 0) {
+    lag_end<S, R>(P, P.side[WEST], uz, ur, 0, P.nz - 1, ju, vz, vr);
+  } else if (iu >= P.nz) {
+    lag_end<S, R>(P, P.side[EAST], uz, ur, P.nz - 1, 0, ju, vz, vr);
+  } else if (ju < 0) {
+    if (P.side[SOUTH].kind == SIDE_AXIS) {
+      vz = (R)uz[P.nz + iu];
+      vr = -(R)ur[P.nz + iu];
+    } else {
+      vz = (R)2 * (R)P.side[SOUTH].uz - (R)uz[iu];
+      vr = (R)2 * (R)P.side[SOUTH].ur - (R)ur[iu];
+    }
+  } else if (ju >= P.nr) {
+    const int o = (P.nr - 1) * P.nz + iu;
+    vz = (R)2 * (R)P.side[NORTH].uz - (R)uz[o];
+    vr = (R)2 * (R)P.side[NORTH].ur - (R)ur[o];
+  } else {
+    vz = (R)uz[ju * P.nz + iu];
+    vr = (R)ur[ju * P.nz + iu];
+  }
+}
+
+// Gradient terms at (i, j) from the lagged field (uz, ur) of the lattice
+// (packed [nr][nz]); zero where 1/r is taken as zero.
+template <typename S, typename R>
+__device__ inline void lag_grad(const InstP& P, const Row<R>& w, const S* uz, const S* ur, int i,
+                                int j, R& Dr, R& Dz) {
+  Dr = (R)0;
+  Dz = (R)0;
+  if (w.ir == (R)0) return;
+  R zn, rn, zs, rs, ze, re, zw, rw;
+  lag_at<S, R>(P, uz, ur, i, j + 1, zn, rn);
+  lag_at<S, R>(P, uz, ur, i, j - 1, zs, rs);
+  lag_at<S, R>(P, uz, ur, i + 1, j, ze, re);
+  lag_at<S, R>(P, uz, ur, i - 1, j, zw, rw);
+  Dr = rn - rs;
+  Dz = (R)0.5 * (zn - zs) + (R)0.5 * (re - rw);
 }
 
 // Ghost slot (element offset in a plane) of the upstream position (iu, ju)

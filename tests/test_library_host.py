@@ -106,6 +106,14 @@ def test_validation(L):
     assert _status(L, [dict(mrt, tau=0.5)]) == -2
     assert _status(L, [mrt, ok]) == -1
     assert _status(L, [mrt, dict(mrt, wet=True), dict(mrt, cartesian=True, r0=0.0)]) == 0
+    # original scheme: f only, halfway walls; its own kernels per batch
+    orig = dict(ok, original=True)
+    assert _status(L, [orig]) == 0
+    assert _status(L, [dict(orig, swirl=True)]) == -1
+    assert _status(L, [dict(orig, wet=True)]) == -1
+    assert _status(L, [dict(orig, mrt=True)]) == -1
+    assert _status(L, [orig, ok]) == -1
+    assert L.workspace_bytes([orig], 0) > L.workspace_bytes([ok], 0)
 
 
 def test_workspace_grows_with_batch(L):
