@@ -16,6 +16,8 @@ Workloads (synthetic, seeded):
              step (default)
   batch256_mrt   the same 256 cavities with the MRT collision of f
   pipe_fp32 / pipe_fp64   16384 x 2048 body-force pipe, f only
+  pipe_fp64_original / pipe_fp32_original   the same pipe under the original
+             scheme of Sec. II (lagged-gradient source, Eqs. 7-10)
   womersley  64 x 128 Womersley pipe, FP32
   cavity     256 x 384 rotating-lid cavity at Re 990, FP32 f + g
   melt512    512 crystal/crucible melts 128 x 256, FP32 f + g + h
@@ -57,6 +59,12 @@ def workload(name: str):
         return [W.roofline_pipe()], 1, "16384x2048 body-force pipe, FP32 f"
     if name == "pipe_fp64":
         return [W.roofline_pipe()], 0, "16384x2048 body-force pipe, FP64 f"
+    if name == "pipe_fp64_original":
+        return ([dict(W.roofline_pipe(), original=True)], 0,
+                "16384x2048 body-force pipe, FP64 f, original scheme (Sec. II)")
+    if name == "pipe_fp32_original":
+        return ([dict(W.roofline_pipe(), original=True)], 1,
+                "16384x2048 body-force pipe, FP32 f, original scheme (Sec. II)")
     if name == "womersley":
         return [W.womersley()], 1, "Womersley pipe 64x128, FP32 f"
     if name == "cavity":
@@ -69,6 +77,8 @@ def workload(name: str):
 def bytes_per_update(case, prec):
     es = 8 if prec == 0 else 4
     q = 9 + (4 if case.get("swirl") else 0) + (4 if case.get("thermal") else 0)
+    if case.get("original"):
+        q += 2  # the lagged velocity (u_z, u_r): read once, written once
     return 2 * q * es  # every population read once and written once
 
 
