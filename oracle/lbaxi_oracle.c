@@ -110,6 +110,7 @@ typedef struct {
   double s_e, s_eps, s_q;   /* MRT rates of e, epsilon and q (s_v = 1/(tau+1/2)) */
   double s_rho, s_j;        /* rates of the conserved moments (they drop out) */
   int original;             /* 1: the original scheme of Eqs. (5)-(10), f only */
+  int zou_he;               /* 1 (with wet): radial walls rebuild f by Zou-He */
 } orc_params;
 
 typedef struct {
@@ -867,6 +868,56 @@ static int wet_wall_rule(const orc_params* p, int i, int j, wet_rule_t* w) {
   return 1;
 }
 
+/* Zou-He no-slip wall (the paper's Ref. 47, used for its pipe flows) for the
+ * f^ variables at a node b on a radial wall (north: row nr - 1, south: row
+ * 0 of an annulus) whose wall velocity u_w = (u_z,w, 0) has no normal part.
+ * The populations that streamed in from the fluid side are kept; the three
+ * that would have come from beyond the wall (e_r pointing away from the
+ * wall, into the fluid) are fixed by Eqs. (16)-(17) at b with u = u_w,
+ *   sum e_r f^ = -G_r / 2,   sum e_z f^ = u_z,w sum f^ - G_z / 2,
+ * (G the velocity-independent force of the macros) and by bounce-back of
+ * the non-equilibrium part along the wall normal, f^_n - E_n = f^_m - E_m
+ * (m the direction opposite to n, E = f_eq - S/2 at the wall state).  The
+ * two diagonal unknowns share the remaining mass equally, as in Zou and He.
+ * mb holds the wall values (u_z,w, u_r,w = 0, u_th,w, T_w) of b.          */
+static void zou_he_f(orc_state* s, int i, int j, const double* mb) {
+  const orc_params* p = &s->p;
+  int north = (j == p->nr - 1);
+  int sgn = north ? -1 : 1;        /* e_r of the unknown directions */
+  double f[9];
+  for (int a = 0; a < 9; ++a) f[a] = s->f[IDX(p, a, j, i)];
+  double Gz = orc_force_a(p, s->t);
+  if (p->thermal) Gz += p->rho0 * p->gbeta * (mb[4] - p->T_ref);
+  double Gr = p->swirl ? p->rho0 * mb[3] * mb[3] * inv_r(p, j) : 0.0;
+  /* known sums: e_r = 0 and e_r = -sgn (arriving from the fluid side) */
+  double A0 = 0.0, Ak = 0.0, Zk = 0.0;
+  for (int a = 0; a < 9; ++a) {
+    if (ER9[a] == 0) {
+      A0 += f[a];
+      Zk += EZ9[a] * f[a];
+    } else if (ER9[a] == -sgn) {
+      Ak += f[a];
+      Zk += EZ9[a] * f[a];
+    }
+  }
+  /* radial momentum: sgn * U - sgn * Ak = -Gr/2, U the unknowns' sum */
+  double U = Ak - sgn * 0.5 * Gr;
+  double s0 = A0 + Ak + U;
+  /* axial momentum: Zk + sum over unknowns of e_z f = u_z,w s0 - Gz/2 */
+  double Dz = mb[1] * s0 - 0.5 * Gz - Zk;
+  int n = find9(0, sgn), m = find9(0, -sgn);
+  int dp = find9(1, sgn), dm = find9(-1, sgn);  /* e_z = +1 / -1 unknowns */
+  /* the wall state takes the density these conditions give, rho = s0
+   * (Eq. 17 with u_r = 0) */
+  double mz[5] = {s0, mb[1], mb[2], mb[3], mb[4]}, ez[9], Sz[9];
+  orc_feq9(mz[0], mz[1], mz[2], ez);
+  orc_node_source(p, j, s->t, mz, ez, Sz);
+  double fn = f[m] + (ez[n] - 0.5 * Sz[n]) - (ez[m] - 0.5 * Sz[m]);
+  s->f[IDX(p, n, j, i)] = fn;
+  s->f[IDX(p, dp, j, i)] = 0.5 * (U - fn + Dz);
+  s->f[IDX(p, dm, j, i)] = 0.5 * (U - fn - Dz);
+}
+
 static void wet_substitute(orc_state* s) {
   const orc_params* p = &s->p;
   if (!p->wet) return;
@@ -894,8 +945,13 @@ static void wet_substitute(orc_state* s) {
       orc_node_source(p, j, s->t, mb, e1, S1);
       orc_feq9(m[0], m[1], m[2], e2);
       orc_node_source(p, w.jn, s->t, m, e2, S2);
-      for (int a = 0; a < 9; ++a)
-        s->f[IDX(p, a, j, i)] = f[a] + (e1[a] - 0.5 * S1[a]) - (e2[a] - 0.5 * S2[a]);
+      int radial = w.jn != j && w.in == i; /* on a radial wall, not a z-end */
+      if (p->zou_he && radial) {
+        zou_he_f(s, i, j, mb);
+      } else {
+        for (int a = 0; a < 9; ++a)
+          s->f[IDX(p, a, j, i)] = f[a] + (e1[a] - 0.5 * S1[a]) - (e2[a] - 0.5 * S2[a]);
+      }
       if (p->swirl) {
         double q1[4], q2[4];
         orc_geq4(p->rho0, uthw, uzw, urw, q1);

@@ -65,6 +65,7 @@ class _Params(C.Structure):
         ("s_rho", C.c_double),
         ("s_j", C.c_double),
         ("original", C.c_int),
+        ("zou_he", C.c_int),
     ]
 
 
@@ -178,6 +179,11 @@ def params(case: dict) -> _Params:
     p.original = int(bool(case.get("original", False)))
     if p.original and (p.swirl or p.thermal or p.wet or p.mrt):
         raise ValueError("the original scheme models f only, with halfway walls and BGK")
+    # Zou-He no-slip on the radial walls of a wet-node lattice
+    p.zou_he = int(bool(case.get("zou_he", False)))
+    if p.zou_he and (not p.wet or any(case[s].get("kind") == "wall" and case[s].get("ur", 0.0)
+                                      for s in ("south", "north"))):
+        raise ValueError("Zou-He walls need wet-node walls and no normal wall velocity")
     return p
 
 
