@@ -87,14 +87,24 @@ enum { LBAXI_FP64 = 0, LBAXI_FP32 = 1, LBAXI_FP32_FAST = 2 };
  * Eq. (7) and the macros of Eqs. (9)-(10), whose velocity-gradient terms are
  * central differences of the previous level's velocity (the handle keeps
  * that field: 2 values per node more in the workspace, read and written
- * each step).  f only: not with SWIRL, THERMAL, WET_WALLS or MRT. */
+ * each step).  f only: not with SWIRL, THERMAL, WET_WALLS or MRT.
+ * LBAXI_ZOU_HE (with LBAXI_WET_WALLS) rebuilds f on the radial wall nodes by
+ * Zou and He's no-slip rule, the paper's wall treatment of its pipe flows
+ * (Sec. IV A, its Ref. 47): the populations from beyond the wall follow from
+ * Eqs. (16)-(17) at the wall velocity and non-equilibrium bounce-back along
+ * the normal; g and h keep the extrapolation.  Only with periodic z-ends
+ * (the paper's pipes: where a Zou-He wall met an extrapolated z-end wall
+ * the corner went unstable at small tau) and radial walls without normal
+ * velocity (u_r = 0); EINVAL otherwise.  Zou-He walls are not robust at
+ * small tau: started from noisy states they diverged at tau <= 0.55. */
 enum {
   LBAXI_SWIRL = 1u,
   LBAXI_THERMAL = 2u,
   LBAXI_CARTESIAN = 4u,
   LBAXI_WET_WALLS = 8u,
   LBAXI_MRT = 16u,
-  LBAXI_ORIGINAL = 32u
+  LBAXI_ORIGINAL = 32u,
+  LBAXI_ZOU_HE = 64u
 };
 enum {
   LBAXI_SIDE_AXIS = 0,     /* south side only, r0 = 0: specular axis */
@@ -127,7 +137,8 @@ typedef struct {
   int32_t nz, nr;   /* nodes along z and r, each >= 2 */
   double r0;        /* radius of node row 0; 0 with an axis south side */
   int32_t prec;     /* LBAXI_FP64 / _FP32 / _FP32_FAST (same for a whole batch) */
-  uint32_t fields;  /* LBAXI_SWIRL | _THERMAL | _CARTESIAN | _WET_WALLS | _MRT | _ORIGINAL */
+  uint32_t fields;  /* LBAXI_SWIRL | _THERMAL | _CARTESIAN | _WET_WALLS | _MRT | _ORIGINAL
+                       | _ZOU_HE */
   double tau;       /* tau_s of f */
   double tau_g;     /* tau_s of g, 0 -> paper default */
   double tau_h;     /* tau_s of h, 0 -> tau */

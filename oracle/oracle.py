@@ -182,8 +182,10 @@ def params(case: dict) -> _Params:
     # Zou-He no-slip on the radial walls of a wet-node lattice
     p.zou_he = int(bool(case.get("zou_he", False)))
     if p.zou_he and (not p.wet or any(case[s].get("kind") == "wall" and case[s].get("ur", 0.0)
-                                      for s in ("south", "north"))):
-        raise ValueError("Zou-He walls need wet-node walls and no normal wall velocity")
+                                      for s in ("south", "north"))
+                     or case["west"].get("kind") != "periodic"):
+        raise ValueError("Zou-He walls need wet-node walls, periodic z-ends (the paper's "
+                         "pipes) and no normal wall velocity")
     return p
 
 

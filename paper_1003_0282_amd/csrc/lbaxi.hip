@@ -192,6 +192,34 @@ __device__ inline R eq_hat(int a, R drho, R rho, R uz, R ur, R Fz, R Fr, R ir) {
   return w * (drho + rho * Pa) - (R)0.5 * src_a<R, F>(a, rho, uz, ur, Fz, Fr, ir, Pa);
 }
 
+// Zou-He no-slip at a node on a radial wall (the paper's Ref. 47), f only:
+// the populations that streamed in from the fluid side (in f) are kept; the
+// three with e_r = SGN (coming from beyond the wall) follow from Eqs.
+// (16)-(17) at the wall velocity (u_z,w, 0): sum e_r f = -G_r / 2 and
+// sum e_z f = u_z,w sum f - G_z / 2, from non-equilibrium bounce-back along
+// the normal, f_n - E_n = f_m - E_m, and from an equal share of the rest
+// between the two diagonals.  In deviation form the w rho0 parts cancel
+// except in the mass, rho = sum f.
+template <typename R, int F, int SGN>
+__device__ inline void zou_he(const PR<R>& p, const Row<R>& rb, R uzw, R Gz, R Gr, R* f) {
+  const R* fo = f;  // the known populations; only the unknown slots are written
+  constexpr int N = SGN > 0 ? 2 : 4, M = SGN > 0 ? 4 : 2;  // normal pair
+  constexpr int DP = SGN > 0 ? 5 : 8, DM = SGN > 0 ? 6 : 7;  // e_z = +1 / -1 unknowns
+  constexpr int KP = SGN > 0 ? 8 : 5, KM = SGN > 0 ? 7 : 6;  // e_z = +1 / -1 knowns
+  const R D0 = fo[0] + (fo[1] + fo[3]);
+  const R Dk = fo[M] + (fo[KP] + fo[KM]);
+  const R Ud = Dk - (R)SGN * (R)0.5 * Gr;
+  const R drho = D0 + Dk + Ud;
+  const R rho = p.rho0 + drho;
+  const R Zk = (fo[1] - fo[3]) + (fo[KP] - fo[KM]);
+  const R Dz = uzw * rho - (R)0.5 * Gz - Zk;
+  const R dn = fo[M] + eq_hat<R, F>(N, drho, rho, uzw, (R)0, Gz, Gr, rb.ir) -
+               eq_hat<R, F>(M, drho, rho, uzw, (R)0, Gz, Gr, rb.ir);
+  f[N] = dn;
+  f[DP] = (R)0.5 * (Ud - dn + Dz);
+  f[DM] = (R)0.5 * (Ud - dn - Dz);
+}
+
 template <typename S, typename R, int F>
 __device__ inline void wall_state(const InstP& P, const PR<R>& p, const S* s, int i, int j,
                                   const WetRule& w, R* f, R* g, R* h) {
@@ -220,10 +248,23 @@ __device__ inline void wall_state(const InstP& P, const PR<R>& p, const S* s, in
   if (F & F_THERMAL) Fzb += p.rho0 * p.gbeta * dTw;
   R Frb = -(R)2 * p.mu0 * urw * rb.ir2;
   if (F & F_SWIRL) Frb += p.rho0 * uthw * uthw * rb.ir;
+  const bool zou = P.zou && w.in == i && w.jn != j;  // Zou-He on a radial wall
+  if (zou) {
+    // corners and z-ends keep the extrapolation, g and h too; the node's own
+    // streamed-in populations are loaded into f and completed in place
+    R gd[4], hd[4];
+    load_node<S, R, F>(P, s, i, j, false, f, gd, hd);
+    const R Gr = (F & F_SWIRL) ? p.rho0 * uthw * uthw * rb.ir : (R)0;
+    if (w.jn < j)
+      zou_he<R, F, -1>(p, rb, uzw, Fzb, Gr, f);
+    else
+      zou_he<R, F, 1>(p, rb, uzw, Fzb, Gr, f);
+  } else {
 #pragma unroll
-  for (int a = 0; a < 9; ++a)
-    f[a] = fn[a] + eq_hat<R, F>(a, drhob, rhob, uzw, urw, Fzb, Frb, rb.ir) -
-           eq_hat<R, F>(a, m.drho, m.rho, m.uz, m.ur, m.Fz, m.Fr, rn.ir);
+    for (int a = 0; a < 9; ++a)
+      f[a] = fn[a] + eq_hat<R, F>(a, drhob, rhob, uzw, urw, Fzb, Frb, rb.ir) -
+             eq_hat<R, F>(a, m.drho, m.rho, m.uz, m.ur, m.Fz, m.Fr, rn.ir);
+  }
   if (F & F_SWIRL) {
     const R qb = (R)0.25 * p.rho0 * uthw, qn = (R)0.25 * p.rho0 * m.uth;
 #pragma unroll
@@ -482,25 +523,32 @@ __device__ inline Mac<R> node_macros(const InstP& P, const InstP* Pg, const Inst
   return macros<R, F>(p, make_row<R, F>(p, j), axis_row, f, g, h);
 }
 
+// 256 threads per workgroup walk the tile's nodes (a tile may hold up to
+// 1024): wet-node wall rebuilds inline here, and 256-thread workgroups leave
+// them the registers that 1024-thread ones would not.
 template <typename S, typename R, int F>
-__global__ void __launch_bounds__(1024) k_macros(const InstP* ip, const InstDyn* dyn,
-                                                 const Tile* tiles, const int* ntiles,
-                                                 const S* bufA, const S* bufB, S* rho, S* uz,
-                                                 S* ur, S* uth, S* T, int tzlog, Lag lag) {
+__global__ void __launch_bounds__(256) k_macros(const InstP* ip, const InstDyn* dyn,
+                                                const Tile* tiles, const int* ntiles,
+                                                const S* bufA, const S* bufB, S* rho, S* uz,
+                                                S* ur, S* uth, S* T, int tzlog, int tile_nodes,
+                                                Lag lag) {
   const int ti = blockIdx.x;
   if (ti >= *ntiles) return;
   const Tile Tl = cload(tiles + ti);
   const InstP P = cload(ip + Tl.inst);
   const int tz = 1 << tzlog;
-  const int i = Tl.z0 + (threadIdx.x & (tz - 1)), j = Tl.r0 + (threadIdx.x >> tzlog);
-  if (i >= P.nz || j >= P.nr) return;
-  const Mac<R> m = node_macros<S, R, F>(P, ip + Tl.inst, dyn[Tl.inst], bufA, bufB, lag, i, j);
-  const long long o = P.off_fld + (long long)j * P.nz + i;
-  if (rho) rho[o] = (S)m.rho;
-  if (uz) uz[o] = (S)m.uz;
-  if (ur) ur[o] = (S)m.ur;
-  if (uth) uth[o] = (S)m.uth;
-  if (T) T[o] = (S)((R)P.T_ref + m.dT);
+#pragma unroll 1
+  for (int q = threadIdx.x; q < tile_nodes; q += blockDim.x) {
+    const int i = Tl.z0 + (q & (tz - 1)), j = Tl.r0 + (q >> tzlog);
+    if (i >= P.nz || j >= P.nr) continue;
+    const Mac<R> m = node_macros<S, R, F>(P, ip + Tl.inst, dyn[Tl.inst], bufA, bufB, lag, i, j);
+    const long long o = P.off_fld + (long long)j * P.nz + i;
+    if (rho) rho[o] = (S)m.rho;
+    if (uz) uz[o] = (S)m.uz;
+    if (ur) ur[o] = (S)m.ur;
+    if (uth) uth[o] = (S)m.uth;
+    if (T) T[o] = (S)((R)P.T_ref + m.dT);
+  }
 }
 
 // Bit pattern of a non-negative double: monotone in the value, and every NaN
@@ -509,27 +557,31 @@ __device__ inline unsigned long long key(double v) {
   return (unsigned long long)__double_as_longlong(fabs(v));
 }
 
-// Eq. (57) per lattice: max | |u|(t) - |u|(t-1) | with |u|(t-1) in spd.
+// Eq. (57) per lattice: max | |u|(t) - |u|(t-1) | with |u|(t-1) in spd
+// (256 threads per workgroup walking the tile, as k_macros).
 template <typename S, typename R, int F>
-__global__ void __launch_bounds__(1024) k_residual(const InstP* ip, const InstDyn* dyn,
-                                                   const Tile* tiles, const int* ntiles,
-                                                   const S* bufA, const S* bufB,
-                                                   const double* spd, unsigned long long* res,
-                                                   int tzlog, Lag lag) {
-  __shared__ unsigned long long red[16];
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) k_residual(const InstP* ip, const InstDyn* dyn,
+                                                  const Tile* tiles, const int* ntiles,
+                                                  const S* bufA, const S* bufB,
+                                                  const double* spd, unsigned long long* res,
+                                                  int tzlog, int tile_nodes, Lag lag) {
+  __shared__ unsigned long long red[4];
   const int ti = blockIdx.x;
   if (ti >= *ntiles) return;  // uniform per workgroup
   const Tile Tl = cload(tiles + ti);
   const InstP P = cload(ip + Tl.inst);
   const int tz = 1 << tzlog;
-  const int i = Tl.z0 + (threadIdx.x & (tz - 1)), j = Tl.r0 + (threadIdx.x >> tzlog);
   unsigned long long v = 0;
-  if (i < P.nz && j < P.nr) {
+#pragma unroll 1
+  for (int q = threadIdx.x; q < tile_nodes; q += blockDim.x) {
+    const int i = Tl.z0 + (q & (tz - 1)), j = Tl.r0 + (q >> tzlog);
+    if (i >= P.nz || j >= P.nr) continue;
     const Mac<R> m = node_macros<S, R, F>(P, ip + Tl.inst, dyn[Tl.inst], bufA, bufB, lag, i, j);
     const double sp = (double)sqrt(m.uz * m.uz + m.ur * m.ur);
-    v = key(sp - spd[P.off_fld + (long long)j * P.nz + i]);
+    const unsigned long long k = key(sp - spd[P.off_fld + (long long)j * P.nz + i]);
+    v = k > v ? k : v;
   }
-  // wave-level max, then across the waves of the workgroup
+  // wave-level max, then across the four waves of the workgroup
   for (int off = 32; off > 0; off >>= 1) {
     unsigned long long o = __shfl_xor(v, off, 64);
     v = o > v ? o : v;
@@ -693,7 +745,12 @@ lbaxi_status validate(const lbaxi_desc& d, int k) {
     return bad(LBAXI_EINVAL, "lattice too large for 32-bit in-lattice offsets");
   if (d.prec != LBAXI_FP64 && d.prec != LBAXI_FP32 && d.prec != LBAXI_FP32_FAST)
     return bad(LBAXI_EINVAL, "bad prec");
-  if (d.fields & ~63u) return bad(LBAXI_EINVAL, "unknown field bits");
+  if (d.fields & ~127u) return bad(LBAXI_EINVAL, "unknown field bits");
+  if ((d.fields & LBAXI_ZOU_HE) &&
+      (!(d.fields & LBAXI_WET_WALLS) || d.west.kind != LBAXI_SIDE_PERIODIC ||
+       (d.south.kind == LBAXI_SIDE_WALL && d.south.u_r != 0.0) || d.north.u_r != 0.0))
+    return bad(LBAXI_EINVAL,
+               "Zou-He walls need wet-node walls, periodic z-ends and no normal wall velocity");
   if ((d.fields & LBAXI_ORIGINAL) &&
       (d.fields & (LBAXI_SWIRL | LBAXI_THERMAL | LBAXI_WET_WALLS | LBAXI_MRT)))
     return bad(LBAXI_EINVAL, "the original scheme models f only, with halfway walls");
@@ -761,6 +818,7 @@ InstP make_inst(const lbaxi_desc& d, long long off, long long off_fld) {
   P.se = P.sw + strip_len(d);
   P.cart = (d.fields & LBAXI_CARTESIAN) ? 1 : 0;
   P.wet = (d.fields & LBAXI_WET_WALLS) ? 1 : 0;
+  P.zou = (d.fields & LBAXI_ZOU_HE) ? 1 : 0;
   P.r0 = d.r0;
   taus(d, P.tau, P.tau_g, P.tau_h);
   P.rho0 = d.rho0;
@@ -1151,9 +1209,10 @@ lbaxi_status residuals(lbaxi_t* h, std::vector<double>& out) {
   const int* nt = h->d_counts + LIST_ALL;
   int tzlog = ilog2(h->tz);
   Lag lag = {h->lagA, h->lagB, h->L.lag_stride};
-  void* args[] = {&ip, &dy, &tl, &nt, &A, &B, &S, &r, &tzlog, &lag};
-  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])), dim3(h->tz * h->tr), args,
-                         0, h->stream));
+  int tile_nodes = h->tz * h->tr;
+  void* args[] = {&ip, &dy, &tl, &nt, &A, &B, &S, &r, &tzlog, &tile_nodes, &lag};
+  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])), dim3(256), args, 0,
+                         h->stream));
   std::vector<unsigned long long> bits(h->n);
   HIPCHK(hipMemcpyAsync(bits.data(), h->d_res, sizeof(unsigned long long) * h->n,
                         hipMemcpyDeviceToHost, h->stream));
@@ -1366,9 +1425,11 @@ lbaxi_status lbaxi_macros(lbaxi_t* h, void* d_rho, void* d_uz, void* d_ur, void*
   const void* B = h->bufB;
   int tzlog = ilog2(h->tz);
   Lag lag = {h->lagA, h->lagB, h->L.lag_stride};
-  void* args[] = {&ip, &dy, &tl, &nt, &A, &B, &d_rho, &d_uz, &d_ur, &d_uth, &d_T, &tzlog, &lag};
-  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])), dim3(h->tz * h->tr), args,
-                         0, h->stream));
+  int tile_nodes = h->tz * h->tr;
+  void* args[] = {&ip,    &dy,   &tl,   &nt,    &A,     &B,          &d_rho,
+                  &d_uz,  &d_ur, &d_uth, &d_T, &tzlog, &tile_nodes, &lag};
+  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])), dim3(256), args, 0,
+                         h->stream));
   return LBAXI_OK;
 }
 

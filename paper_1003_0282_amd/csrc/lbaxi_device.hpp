@@ -27,6 +27,7 @@ struct SideP {
 struct InstP {
   int nz, nr, cart;
   int wet;    // wall sides are wet-node walls (wall through the outer node row)
+  int zou;    // with wet: radial wall nodes rebuild f by Zou-He
   int pitch;  // row length of a padded plane (a multiple of 128 bytes)
   int c0;     // column of node i = 0 (128 bytes into the row)
   int plane;  // elements per padded plane: (nr + 2) rows of pitch, then the two strips

@@ -114,6 +114,13 @@ def test_validation(L):
     assert _status(L, [dict(orig, mrt=True)]) == -1
     assert _status(L, [orig, ok]) == -1
     assert L.workspace_bytes([orig], 0) > L.workspace_bytes([ok], 0)
+    # Zou-He: on wet-node walls only, radial walls without normal velocity
+    zh = dict(ok, wet=True, zou_he=True)
+    assert _status(L, [zh]) == 0
+    assert _status(L, [dict(ok, zou_he=True)]) == -1
+    assert _status(L, [dict(zh, north=W.wall(ur=1e-3))]) == -1
+    assert _status(L, [zh, dict(ok, wet=True)]) == 0   # a per-lattice wall model
+    assert _status(L, [dict(zh, west=W.wall(), east=W.wall())]) == -1
 
 
 def test_workspace_grows_with_batch(L):

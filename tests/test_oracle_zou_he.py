@@ -29,16 +29,19 @@ def _run(orc, case, steps, **seed):
     return o, o.macros()
 
 
-def test_needs_wet_walls_and_no_normal_wall_velocity(orc):
+def test_needs_wet_walls_periodic_ends_and_no_normal_wall_velocity(orc):
     with pytest.raises(ValueError):
         orc.params(dict(W.hagen_poiseuille(), zou_he=True))
     with pytest.raises(ValueError):
         orc.params(_zh(W.base_case(4, 8, 0.8, r0=3.0, south=W.wall(ur=1e-3))))
+    with pytest.raises(ValueError):
+        orc.params(_zh(W.base_case(4, 8, 0.8, west=W.wall(), east=W.wall())))
 
 
 def test_wall_nodes_take_the_wall_velocity(orc):
     case = _zh(W.base_case(12, 10, 0.7, swirl=True, a0=1e-5, r0=3.0,
                            south=W.wall(uz=2e-3, omega=1e-3), north=W.wall(uz=-1e-3, omega=2e-3)))
+    assert case["west"]["kind"] == "periodic"
     fld = W.random_fields(case, 3)
     fld.pop("T")
     o = orc.Oracle(case)
