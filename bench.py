@@ -16,6 +16,7 @@ Workloads (synthetic, seeded):
              step (default)
   batch256_mrt   the same 256 cavities with the MRT collision of f
   pipe_fp32 / pipe_fp64   16384 x 2048 body-force pipe, f only
+  pipe_fp64_zou_he   the same pipe with wet-node Zou-He walls (k_wall added)
   pipe_fp64_original / pipe_fp32_original   the same pipe under the original
              scheme of Sec. II (lagged-gradient source, Eqs. 7-10)
   womersley  64 x 128 Womersley pipe, FP32
@@ -59,6 +60,9 @@ def workload(name: str):
         return [W.roofline_pipe()], 1, "16384x2048 body-force pipe, FP32 f"
     if name == "pipe_fp64":
         return [W.roofline_pipe()], 0, "16384x2048 body-force pipe, FP64 f"
+    if name == "pipe_fp64_zou_he":
+        return ([dict(W.roofline_pipe(), wet=True, zou_he=True)], 0,
+                "16384x2048 body-force pipe, FP64 f, wet-node Zou-He walls")
     if name == "pipe_fp64_original":
         return ([dict(W.roofline_pipe(), original=True)], 0,
                 "16384x2048 body-force pipe, FP64 f, original scheme (Sec. II)")
