@@ -1,10 +1,11 @@
 """Parity at the benchmark's full sizes, in the launch shapes bench.py times.
 
-The whole workload runs on the GPU in one handle (256 cavities, 56.3 M nodes;
-512 melts of 128 x 256; the 16384 x 2048 pipe) from seeded random states; the
-oracle recomputes a sample of the lattices (the largest, the smallest and a
-few seeded picks) in full for the same number of steps, and every node of
-those lattices is compared.  Graph replay is part of the run (graph length 8,
+The whole workload runs on the GPU in one handle (256 cavities, 56.3 M nodes,
+with BGK and with MRT collision; 512 melts of 128 x 256; the 16384 x 2048
+pipe with halfway walls, with Zou-He walls and under the original scheme)
+from seeded random states; the oracle recomputes a sample of the lattices
+(the largest, the smallest and a few seeded picks) in full for the same
+number of steps, and every node of those lattices is compared.  Graph replay is part of the run (graph length 8,
 20 steps: two replays and four direct steps).  The other lattices must stay
 finite.  Tolerance: FP32 storage 1e-5 of u_max, FP64 1e-10, as elsewhere.
 """
@@ -106,3 +107,22 @@ def test_melt512_full_size():
 def test_roofline_pipe_full_size_fp64():
     """16384 x 2048 body-force pipe in FP64, every node compared."""
     _run_and_compare([W.roofline_pipe()], 0, (256, 1, 0, 0, 1), [0], seed=13)
+
+
+def test_batch256_mrt_full_size():
+    """The 256 cavities with the MRT collision (bench workload batch256_mrt)."""
+    cases = [dict(c, mrt=True) for c in W.batch_cavities(256, seed=0)]
+    _run_and_compare(cases, 1, (128, 1, 0, 0, 1), _sample(cases, 2, 7), seed=14)
+
+
+def test_pipe_original_full_size_fp64():
+    """The pipe under the original scheme (bench workload pipe_fp64_original),
+    in the autotuner's shape for it, every node compared."""
+    _run_and_compare([dict(W.roofline_pipe(), original=True)], 0, (512, 1, 0, 0, 0), [0],
+                     seed=15)
+
+
+def test_pipe_zou_he_full_size_fp64():
+    """The pipe with wet-node Zou-He walls (bench workload pipe_fp64_zou_he)."""
+    _run_and_compare([dict(W.roofline_pipe(), wet=True, zou_he=True)], 0, (256, 2, 0, 0, 1), [0],
+                     seed=16)
