@@ -449,19 +449,6 @@ __device__ inline void zseg(const InstP& P, const SideP& S, int j, int& kind, do
   }
 }
 
-// The same for a side chosen at run time, read field by field from the
-// lattice's parameter block: a whole-struct copy with a run-time choice
-// between its fields would be kept in scratch memory.
-__device__ inline void zseg_g(const InstP& P, const SideP* W, int j, int& kind, double& omega,
-                              int& thermal, double& T) {
-  const double rs = cload(&W->r_split);
-  const bool second = rs >= 0.0 && P.r0 + (double)j > rs;
-  kind = second ? cload(&W->kind2) : cload(&W->kind);
-  omega = second ? cload(&W->omega2) : cload(&W->omega);
-  thermal = second ? cload(&W->thermal2) : cload(&W->thermal);
-  T = second ? cload(&W->T2) : cload(&W->T);
-}
-
 // Lagged velocity at (iu, ju), at most one of them outside the lattice:
 // mirrored across the axis (u_r odd) and a free-slip end (u_z odd), wrapped
 // at periodic ends, 2 u_w - u beyond a halfway wall.
@@ -528,6 +515,54 @@ __device__ inline void lag_grad(const InstP& P, const Row<R>& w, const S* uz, co
   Dz = (R)0.5 * (zn - zs) + (R)0.5 * (re - rw);
 }
 
+// The same for a side chosen at run time, read field by field from the
+// lattice's parameter block: a whole-struct copy with a run-time choice
+// between its fields would be kept in scratch memory.
+__device__ inline void zseg_g(const InstP& P, const SideP* W, int j, int& kind, double& omega,
+                              int& thermal, double& T) {
+  const double rs = cload(&W->r_split);
+  const bool second = rs >= 0.0 && P.r0 + (double)j > rs;
+  kind = second ? cload(&W->kind2) : cload(&W->kind);
+  omega = second ? cload(&W->omega2) : cload(&W->omega);
+  thermal = second ? cload(&W->thermal2) : cload(&W->thermal);
+  T = second ? cload(&W->T2) : cload(&W->T);
+}
+
+// Parameters of the z-end segment that row j of the west (or east) end
+// belongs to.  Both ends' fields are read from the lattice's parameter
+// block at uniform addresses (scalar loads, issued together) and the lane's
+// end is then chosen value by value: no load waits on the choice.
+struct ZSeg {
+  int kind, thermal;
+  double omega, T, uz, ur;
+};
+
+__device__ inline ZSeg zend(const InstP& P, const InstP* Pg, bool west, int j) {
+  const SideP* Wp = &Pg->side[WEST];
+  const SideP* Ep = &Pg->side[EAST];
+  const double rsW = cload(&Wp->r_split), rsE = cload(&Ep->r_split);
+  const int kW = cload(&Wp->kind), kE = cload(&Ep->kind);
+  const int k2W = cload(&Wp->kind2), k2E = cload(&Ep->kind2);
+  const int tW = cload(&Wp->thermal), tE = cload(&Ep->thermal);
+  const int t2W = cload(&Wp->thermal2), t2E = cload(&Ep->thermal2);
+  const double oW = cload(&Wp->omega), oE = cload(&Ep->omega);
+  const double o2W = cload(&Wp->omega2), o2E = cload(&Ep->omega2);
+  const double TW = cload(&Wp->T), TE = cload(&Ep->T);
+  const double T2W = cload(&Wp->T2), T2E = cload(&Ep->T2);
+  const double uzW = cload(&Wp->uz), uzE = cload(&Ep->uz);
+  const double urW = cload(&Wp->ur), urE = cload(&Ep->ur);
+  const double rs = west ? rsW : rsE;
+  const bool second = rs >= 0.0 && P.r0 + (double)j > rs;
+  ZSeg z;
+  z.kind = second ? (west ? k2W : k2E) : (west ? kW : kE);
+  z.thermal = second ? (west ? t2W : t2E) : (west ? tW : tE);
+  z.omega = second ? (west ? o2W : o2E) : (west ? oW : oE);
+  z.T = second ? (west ? T2W : T2E) : (west ? TW : TE);
+  z.uz = west ? uzW : uzE;
+  z.ur = west ? urW : urE;
+  return z;
+}
+
 // Ghost slot (element offset in a plane) of the upstream position (iu, ju)
 // outside the lattice: beyond a z-end, the west / east strip, which holds
 // the ghost column of rows -1..nr contiguously (so that filling it is a
@@ -549,20 +584,18 @@ __device__ inline double rule_f(const InstP& P, const InstP* Pg, const S* s, int
   int iu = i - ez;
   const int ju = j - er;
   if (iu < 0 || iu >= nz) {
-    const SideP* W = &Pg->side[iu < 0 ? WEST : EAST];  // run-time side: from memory
-    if (cload(&W->kind) == SIDE_PERIODIC) {
+    if (P.side[WEST].kind == SIDE_PERIODIC) {  // both ends or neither
       iu += (iu < 0) ? nz : -nz;
     } else {
-      int kind, th; double om, T;
-      zseg_g(P, W, j, kind, om, th, T);
-      if (kind == SIDE_FREESLIP) {
+      const ZSeg z = zend(P, Pg, iu < 0, j);
+      if (z.kind == SIDE_FREESLIP) {
         constexpr int b = mz9(A);
         if (ju >= 0 && ju < nr) return (double)s[b * pl + nidx(P, ju, i)];
         if (ju < 0 && P.side[SOUTH].kind == SIDE_AXIS) return (double)s[mr9(b) * pl + nidx(P, 1, i)];
         return (double)s[opp9(A) * pl + nidx(P, j, i)];
       }
       return (double)s[opp9(A) * pl + nidx(P, j, i)] +
-             6.0 * w9(A) * P.rho0 * (ez * cload(&W->uz) + er * cload(&W->ur));
+             6.0 * w9(A) * P.rho0 * (ez * z.uz + er * z.ur);
     }
   }
   if (ju < 0) {
@@ -586,14 +619,12 @@ __device__ inline double rule_g(const InstP& P, const InstP* Pg, const S* s, int
   int iu = i - ez;
   const int ju = j - er;
   if (iu < 0 || iu >= nz) {
-    const SideP* W = &Pg->side[iu < 0 ? WEST : EAST];  // run-time side: from memory
-    if (cload(&W->kind) == SIDE_PERIODIC) {
+    if (P.side[WEST].kind == SIDE_PERIODIC) {
       iu += (iu < 0) ? nz : -nz;
     } else {
-      int kind, th; double om, T;
-      zseg_g(P, W, j, kind, om, th, T);
-      if (kind == SIDE_FREESLIP) return (double)s[opp4(A) * pl + nidx(P, j, i)];
-      return -(double)s[opp4(A) * pl + nidx(P, j, i)] + 0.5 * P.rho0 * om * (P.r0 + (double)j);
+      const ZSeg z = zend(P, Pg, iu < 0, j);
+      if (z.kind == SIDE_FREESLIP) return (double)s[opp4(A) * pl + nidx(P, j, i)];
+      return -(double)s[opp4(A) * pl + nidx(P, j, i)] + 0.5 * P.rho0 * z.omega * (P.r0 + (double)j);
     }
   }
   if (ju < 0) {
@@ -618,14 +649,12 @@ __device__ inline double rule_h(const InstP& P, const InstP* Pg, const S* s, int
   int iu = i - ez;
   const int ju = j - er;
   if (iu < 0 || iu >= nz) {
-    const SideP* W = &Pg->side[iu < 0 ? WEST : EAST];  // run-time side: from memory
-    if (cload(&W->kind) == SIDE_PERIODIC) {
+    if (P.side[WEST].kind == SIDE_PERIODIC) {
       iu += (iu < 0) ? nz : -nz;
     } else {
-      int kind, th; double om, T;
-      zseg_g(P, W, j, kind, om, th, T);
-      if (kind == SIDE_WALL && th)
-        return -(double)s[opp4(A) * pl + nidx(P, j, i)] + 0.5 * (T - P.T_ref);
+      const ZSeg z = zend(P, Pg, iu < 0, j);
+      if (z.kind == SIDE_WALL && z.thermal)
+        return -(double)s[opp4(A) * pl + nidx(P, j, i)] + 0.5 * (z.T - P.T_ref);
       return (double)s[opp4(A) * pl + nidx(P, j, i)];
     }
   }
