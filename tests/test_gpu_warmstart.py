@@ -27,7 +27,9 @@ def test_warm_start_reaches_the_steady_field_sooner():
     print({k: r[k] for k in ("generate", "train")})
     for d in e["by_distance"] + e["by_tol"]:
         print({k: v for k, v in d.items() if not k.startswith("steps_") or "median" in k})
-    assert r["train"]["loss_last"] < 0.2 * r["train"]["loss_first"]
+    # training does not repeat bit for bit (its reductions use atomics), so
+    # the loss drop is asked with margin: about 0.2 x is typical, 0.3 x required
+    assert r["train"]["loss_last"] < 0.3 * r["train"]["loss_first"]
     d10 = {d["err"]: d for d in e["by_distance"]}[0.1]
     assert d10["reached_both"] >= 6
     assert d10["steps_ratio_median"] > 2.0
