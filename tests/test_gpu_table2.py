@@ -14,7 +14,16 @@ from paper_1003_0282_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TABLE2 = {990.0: (0.0987, 0.213), 1290.0: (0.0716, 0.147)}
+def _table2():
+    import json
+    import os
+    p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table2_cylinder.json")
+    with open(p) as f:
+        g = json.load(f)
+    return {c["Re"]: (c["uz_max"], c["h_max_over_H"]) for c in g["cases"]}
+
+
+TABLE2 = _table2()
 
 
 @pytest.fixture(scope="module", autouse=True)

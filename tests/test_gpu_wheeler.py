@@ -20,9 +20,18 @@ from _parity import assert_parity, gpu_run, oracle_run, to_np
 
 pytestmark = pytest.mark.gpu
 
-# (Re_x, Re_c): psi_min values, psi_max values of the three references
-TABLE1 = {(100.0, -25.0): ((-0.0494, -0.0514, -0.0443), (0.1180, 0.1140, 0.1177)),
-          (1000.0, -250.0): ((-1.444, -1.478, -1.478), (1.128, 1.114, 1.148))}
+def _table1():
+    """(Re_x, Re_c) -> (psi_min values, psi_max values) of the three references."""
+    import json
+    import os
+    p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table1_wheeler.json")
+    with open(p) as f:
+        g = json.load(f)
+    return {(c["Re_x"], c["Re_c"]): (tuple(c["psi_min"].values()), tuple(c["psi_max"].values()))
+            for c in g["cases"]}
+
+
+TABLE1 = _table1()
 
 
 @pytest.fixture(scope="module", autouse=True)
