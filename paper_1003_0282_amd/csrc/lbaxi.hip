@@ -3,11 +3,14 @@
 // One fused kernel advances every lattice of a handle by one time step:
 // each thread owns one node, pulls its 9 (+4 +4) populations from the
 // post-collision buffer of the previous step applying the boundary rules,
-// computes the macros of Eqs. (16)-(17), collides with Eqs. (12)-(13) and
-// (53)-(54), and writes its populations to the other buffer at its own
-// address.  Work is described by a tile table {instance, z0, r0, interior}
-// so that hundreds of uneven lattices share one (optionally persistent)
-// launch; runs are replayed from HIP graphs of K steps.
+// computes the macros of Eqs. (16)-(17), collides f with Eqs. (12)-(13) (or
+// the MRT model of Sec. III B, or, for comparison, the original scheme of
+// Sec. II) and g, h with Eqs. (53)-(54), and writes its populations to the
+// other buffer at its own address.  Wet-node walls are rebuilt by a second
+// kernel and ghost slots filled by a third.  Work is described by a tile
+// table {instance, z0, r0} so that hundreds of uneven lattices share one
+// (optionally persistent) launch; runs are replayed from HIP graphs of K
+// steps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

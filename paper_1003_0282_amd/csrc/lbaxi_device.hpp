@@ -1,6 +1,8 @@
 // lbaxi_device.hpp -- per-node arithmetic of the improved axisymmetric LB
 // scheme for gfx950 (Li, He, Tang, Tao, arXiv:1003.0282), shared by the step,
-// seed, macro and residual kernels of lbaxi.hip.
+// seed, macro and residual kernels of lbaxi.hip: macros, the BGK collision
+// of Eqs. (12)-(13), the MRT collision of Sec. III B, the original scheme of
+// Sec. II, the D2Q4 rules of Eqs. (53)-(54) and the boundary rules.
 //
 // Storage is deviation form: a stored f_a is f^_a - w_a rho0 and a stored h_a
 // is h_a - T_ref/4 (g is stored as is).  Rounding of FP32 populations near
