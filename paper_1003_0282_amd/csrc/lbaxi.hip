@@ -526,9 +526,9 @@ __device__ inline Mac<R> node_macros(const InstP& P, const InstP* Pg, const Inst
   return macros<R, F>(p, make_row<R, F>(p, j), axis_row, f, g, h);
 }
 
-// 256 threads per workgroup walk the tile's nodes (a tile may hold up to
-// 1024): wet-node wall rebuilds inline here, and 256-thread workgroups leave
-// them the registers that 1024-thread ones would not.
+// Up to 256 threads per workgroup walk the tile's nodes (a tile holds 64 to
+// 1024): wet-node wall rebuilds inline here, and workgroups of at most 256
+// threads leave them the registers that 1024-thread ones would not.
 template <typename S, typename R, int F>
 __global__ void __launch_bounds__(256) k_macros(const InstP* ip, const InstDyn* dyn,
                                                 const Tile* tiles, const int* ntiles,
@@ -561,7 +561,7 @@ __device__ inline unsigned long long key(double v) {
 }
 
 // Eq. (57) per lattice: max | |u|(t) - |u|(t-1) | with |u|(t-1) in spd
-// (256 threads per workgroup walking the tile, as k_macros).
+// (up to 256 threads per workgroup walking the tile, as k_macros).
 template <typename S, typename R, int F>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) k_residual(const InstP* ip, const InstDyn* dyn,
                                                   const Tile* tiles, const int* ntiles,
@@ -1214,8 +1214,8 @@ lbaxi_status residuals(lbaxi_t* h, std::vector<double>& out) {
   Lag lag = {h->lagA, h->lagB, h->L.lag_stride};
   int tile_nodes = h->tz * h->tr;
   void* args[] = {&ip, &dy, &tl, &nt, &A, &B, &S, &r, &tzlog, &tile_nodes, &lag};
-  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])), dim3(256), args, 0,
-                         h->stream));
+  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])),
+                         dim3(std::min(256, tile_nodes)), args, 0, h->stream));
   std::vector<unsigned long long> bits(h->n);
   HIPCHK(hipMemcpyAsync(bits.data(), h->d_res, sizeof(unsigned long long) * h->n,
                         hipMemcpyDeviceToHost, h->stream));
@@ -1431,8 +1431,8 @@ lbaxi_status lbaxi_macros(lbaxi_t* h, void* d_rho, void* d_uz, void* d_ur, void*
   int tile_nodes = h->tz * h->tr;
   void* args[] = {&ip,    &dy,   &tl,   &nt,    &A,     &B,          &d_rho,
                   &d_uz,  &d_ur, &d_uth, &d_T, &tzlog, &tile_nodes, &lag};
-  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])), dim3(256), args, 0,
-                         h->stream));
+  HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])),
+                         dim3(std::min(256, tile_nodes)), args, 0, h->stream));
   return LBAXI_OK;
 }
 
