@@ -128,3 +128,14 @@ def test_workspace_grows_with_batch(L):
     b = L.workspace_bytes([W.cavity(16, 24, 100.0)] * 3, 1)
     assert b > 2 * a
     assert L.workspace_bytes([W.cavity(16, 24, 100.0)], 0) > a
+
+
+def test_largest_lattice_accepted(L):
+    """In-lattice offsets are 32-bit: a lattice whose population planes reach
+    2^31 elements is refused, one just below is accepted (FP32, f only)."""
+    ok = W.base_case(14000, 16384, 0.8, a0=1e-7)
+    too_big = W.base_case(15000, 16384, 0.8, a0=1e-7)
+    assert _status(L, [ok], prec=1) == 0
+    assert _status(L, [too_big], prec=1) == -1
+    # the bound counts elements, not bytes: refused in FP64 as well
+    assert _status(L, [too_big], prec=0) == -1
