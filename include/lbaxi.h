@@ -244,7 +244,8 @@ lbaxi_status lbaxi_set_graph_steps(lbaxi_t* h, int32_t k);
  * cfg5_out (may be NULL) receives it.  Synchronises the stream. */
 lbaxi_status lbaxi_autotune(lbaxi_t* h, int32_t steps_per_trial, int32_t* cfg5_out);
 
-/* Checkpoint: raw populations of the current level plus time and status.
+/* Checkpoint: raw populations of the current level plus time and status (and,
+ * with LBAXI_ORIGINAL, the lagged velocity field the next step needs).
  * lbaxi_state_bytes gives the size; lbaxi_save copies to host memory
  * (synchronising), lbaxi_load restores a state saved by a handle created
  * from identical descriptors (EINVAL otherwise). */
