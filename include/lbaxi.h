@@ -182,8 +182,9 @@ void lbaxi_destroy(lbaxi_t* h);
 
 /* Equilibrium seeding of every lattice (Eq. 6 and Eq. 54; the paper starts
  * from rest): f^ = f_eq(rho, u) - S(rho, u)/2 with S of Eq. (12) (with
- * LBAXI_MRT the velocity-space MRT source M^-1 S~), g = g_eq,
- * h = h_eq, so Eqs. (16)-(17) return the given fields.  Each d_ pointer is a
+ * LBAXI_MRT the velocity-space MRT source M^-1 S~; with LBAXI_ORIGINAL the
+ * G of Eq. (7), its gradient terms taken from the given velocity field),
+ * g = g_eq, h = h_eq, so the macros return the given fields.  Each d_ pointer is a
  * packed field set of the handle's precision (double for FP64, float for
  * FP32), or NULL for rho0 / zero velocity / T_ref.  u_r and u_theta are
  * forced to 0 on an axis row.  Resets the time to 0 and every status to
@@ -194,11 +195,13 @@ lbaxi_status lbaxi_seed(lbaxi_t* h, const void* d_rho, const void* d_uz, const v
 
 /* Advance every RUNNING lattice by n >= 0 time steps (asynchronous).  One
  * step = pull streaming with the boundary rules + macros (Eqs. 16-17) +
- * collision (Eqs. 12-13, 53-54).  Long runs replay a captured HIP graph. */
+ * collision (Eqs. 12-13, or the MRT or original model the handle selects,
+ * and 53-54).  Long runs replay a captured HIP graph. */
 lbaxi_status lbaxi_step(lbaxi_t* h, int64_t n);
 
-/* Macroscopic fields at the current time level (Eqs. 16-17, u_theta =
- * sum g / rho0, T = sum h), packed over all lattices; any pointer may be
+/* Macroscopic fields at the current time level (Eqs. 16-17, or Eqs. 9-10 with
+ * LBAXI_ORIGINAL; u_theta = sum g / rho0, T = sum h), packed over all
+ * lattices; any pointer may be
  * NULL.  Element type = the handle's precision.  Asynchronous. */
 lbaxi_status lbaxi_macros(lbaxi_t* h, void* d_rho, void* d_uz, void* d_ur, void* d_uth,
                           void* d_T);
