@@ -95,16 +95,19 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_entry(name: str, per_launch_algo: float):
-    """HBM bytes per launch from committed rocprofv3 counter summaries of this
-    exact kernel source, or None."""
+def traffic_entry(name: str, launch: str):
+    """HBM bytes per launch of the step kernel from committed rocprofv3 counter
+    summaries taken on this exact kernel source and launch shape, or None."""
     p = os.path.join(ROOT, "profiles", "traffic_%s.json" % name)
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("kernel_hash") != kernel_hash():
         return None
-    return float(d["hbm_bytes_per_launch"])
+    for e in d.get("by_launch", [d]):
+        if e.get("launch") == launch:
+            return float(e["hbm_bytes_per_launch"])
+    return None
 
 
 def cpu_baseline(cases, seconds: float):
@@ -485,7 +488,7 @@ def main():
     lat.set_profiling(False)
     k_avg_ms = k_ms / max(k_n, 1)
     achieved = algo / (k_avg_ms / 1e3) / 1e9
-    tr = traffic_entry(args.workload, algo)
+    tr = traffic_entry(args.workload, ",".join(str(int(x)) for x in launch))
     res = lat.residual()
     n_finite = int(sum(1 for r in res if r == r and r < 1e30))
     out = {
