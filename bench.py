@@ -273,7 +273,7 @@ def wheeler_probe():
                            / r.wall_s / 1e6, 1), "cases": per}
 
 
-def fig7_probe(budget_s: float = 240.0):
+def fig7_probe(budget_s: float = 240.0, max_steps: int = 40_000_000):
     """Fig. 7: the rotating-lid cylinder of Table 2 at Re = 1290 with nu =
     0.005 / 3 (tau_s = 0.505).  The BGK handle runs until its residual turns
     NaN; the MRT handle runs to the Eq. (57) residual 1e-10 (the paper's
@@ -292,10 +292,12 @@ def fig7_probe(budget_s: float = 240.0):
         return dict(c, tau=0.505, east=W.wall(omega=1290.0 * nu / (R * R)), mrt=mrt,
                     name="fig7_%s" % ("mrt" if mrt else "bgk"))
 
-    bgk = ST.solve([case(False)], tol=1e-10, max_steps=200_000, check_every=500, prec=L.FP64)
+    bgk = ST.solve([case(False)], tol=1e-10, max_steps=min(200_000, max_steps), check_every=500,
+                   prec=L.FP64)
     c = case(True)
     torch.cuda.synchronize()
-    r = ST.solve([c], tol=1e-10, max_steps=40_000_000, check_every=20_000, prec=L.FP64,
+    r = ST.solve([c], tol=1e-10, max_steps=max_steps, check_every=min(20_000, max_steps),
+                 prec=L.FP64,
                  budget_s=budget_s, log=lambda m: print(m, file=sys.stderr, flush=True),
                  tag="fig7 mrt", log_every_s=20.0)
     nr, nz = c["nr"], c["nz"]
@@ -420,6 +422,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--kernel-steps", type=int, default=100,
                     help="steps timed kernel by kernel for the roofline figure")
+    ap.add_argument("--max-steps", type=int, default=0,
+                    help="fig7: cap on the steps of each run (0 = run to the criterion)")
     ap.add_argument("--prec", default="", choices=["", "fp64", "fp32", "fp32fast"],
                     help="override the workload's precision")
     args = ap.parse_args()
@@ -444,7 +448,7 @@ def main():
         print(json.dumps(wheeler_probe()))
         return
     if args.workload == "fig7":
-        print(json.dumps(fig7_probe()))
+        print(json.dumps(fig7_probe(max_steps=args.max_steps or 40_000_000)))
         return
     if args.workload == "batch256_sequential":
         print(json.dumps(sequential_probe(args.steps)))
