@@ -214,8 +214,8 @@ def warmstart_probe():
     from paper_1003_0282_amd import warmstart as WS
     t0 = time.perf_counter()
     r = WS.experiment(n_train=256, n_eval=16, nr=128, nz=256, re_max=1000.0, tol=1e-8,
-                      gen_steps=1_000_000, eval_steps=2_000_000, train_steps=5000, batch=8,
-                      lr=1e-3, gen_budget_s=200, train_budget_s=60, eval_budget_s=100,
+                      gen_steps=1_000_000, eval_steps=2_000_000, train_steps=10000, batch=8,
+                      lr=1e-3, gen_budget_s=200, train_budget_s=150, eval_budget_s=100,
                       ref_budget_s=100, wet=True,
                       log=lambda m: print(m, file=sys.stderr, flush=True))
     e, n = r["eval"], r["eval"]["nn_smooth"]
