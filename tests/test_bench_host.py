@@ -1,0 +1,38 @@
+"""Host-side logic of bench.py: the roofline's traffic figure is taken only
+from counters recorded on the same kernel sources and launch shape (else it
+is null), and the byte counts per node update follow the field set and
+scheme."""
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_1003_0282_amd import workloads as W  # noqa: E402
+
+
+def test_traffic_only_for_matching_sources_and_shape(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_hash", lambda: "abc")
+    d = {"kernel_hash": "abc", "by_launch": [{"launch": "128,1,0,0,1", "hbm_bytes_per_launch": 7.0},
+                                             {"launch": "256,1,0,0,1", "hbm_bytes_per_launch": 5.0}]}
+    (prof / "traffic_w.json").write_text(json.dumps(d))
+    assert bench.traffic_entry("w", "128,1,0,0,1") == 7.0
+    assert bench.traffic_entry("w", "256,1,0,0,1") == 5.0
+    assert bench.traffic_entry("w", "64,4,0,0,1") is None
+    assert bench.traffic_entry("missing", "128,1,0,0,1") is None
+    d["kernel_hash"] = "old"
+    (prof / "traffic_w.json").write_text(json.dumps(d))
+    assert bench.traffic_entry("w", "128,1,0,0,1") is None
+
+
+def test_bytes_per_update():
+    pipe = W.roofline_pipe()
+    assert bench.bytes_per_update(pipe, 0) == 144 and bench.bytes_per_update(pipe, 1) == 72
+    assert bench.bytes_per_update(dict(pipe, original=True), 0) == 176
+    assert bench.bytes_per_update(W.cavity(16, 24, 100.0), 1) == 104
+    assert bench.bytes_per_update(W.melt(10.0, 10.0, 1e3), 1) == 136
