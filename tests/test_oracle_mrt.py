@@ -312,3 +312,23 @@ def test_bgk_diverges_and_mrt_holds_at_tau_0005(orc):
     res, m = out[True]
     assert np.isfinite(res) and res < 1e-3
     assert np.abs(m["uz"]).max() < Om * R and np.abs(m["uth"]).max() <= 1.01 * Om * R
+
+
+def test_bulk_rate_must_match_shear_rate(orc):
+    """The paper's closing remark on the MRT scheme: axisymmetric flow has a
+    nonzero pseudo-divergence (d_r u_r + d_z u_z = -u_r / r), so the bulk
+    rate s_e must equal s_v.  In radial source flow, where that divergence
+    is everywhere nonzero, p + rho u^2 / 2 stays constant with s_e = s_v and
+    is off by several times more when s_e departs from it."""
+    Q, r0, nr, tau = 0.1, 4.0, 16, 0.8
+    sv = 1.0 / tau
+    dev = {}
+    for se in (sv, 1.0, 0.6):
+        case = _mrt(W.base_case(2, nr, tau, r0=r0, south=W.wall(ur=Q / (r0 - 0.5)),
+                                north=W.wall(ur=Q / (r0 + nr - 0.5))), s_e=se)
+        _, m = _seeded(case, 20000)
+        r = r0 + np.arange(nr)
+        B = m["rho"][:, 0] / 3 + 0.5 * m["ur"][:, 0] ** 2
+        dev[se] = (B.max() - B.min()) / (0.5 * (Q / r[0]) ** 2)
+    assert dev[sv] < 0.4
+    assert dev[1.0] > 3 * dev[sv] and dev[0.6] > 3 * dev[1.0], dev
