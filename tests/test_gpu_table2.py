@@ -33,10 +33,12 @@ def _cuda():
         pytest.skip("no GPU")
 
 
-def test_rotating_lid_table2():
+@pytest.mark.parametrize("mrt", [False, True])
+def test_rotating_lid_table2(mrt):
+    """BGK (the paper's Table 2 runs) and the MRT collision at the same tau."""
     from paper_1003_0282_amd import lbaxi as L
     from paper_1003_0282_amd import steady as ST
-    cases = [W.cavity_paper(Re, wet=True) for Re in TABLE2]
+    cases = [dict(W.cavity_paper(Re, wet=True), mrt=mrt) for Re in TABLE2]
     r = ST.solve(cases, tol=1e-9, max_steps=1_500_000, check_every=1000, prec=L.FP64)
     assert (r.status == L.CONVERGED).all(), r.status
     for k, c in enumerate(cases):
@@ -47,7 +49,8 @@ def test_rotating_lid_table2():
         mag, h = abs(axis[i]) / Ut, i / (nz - 1.0)
         reversed_ = int((axis * np.sign(axis[i]) < -1e-6 * Ut).sum())
         want_mag, want_h = TABLE2[c["Re"]]
-        print(c["name"], "u_z,max / U_t %.4f (paper %.4f), h / H %.3f (paper %.3f), reversed %d"
+        print(c["name"], "mrt" if mrt else "bgk",
+              "u_z,max / U_t %.4f (paper %.4f), h / H %.3f (paper %.3f), reversed %d"
               % (mag, want_mag, h, want_h, reversed_))
         assert abs(mag - want_mag) < 0.05 * want_mag
         assert abs(h - want_h) < 0.02
