@@ -124,3 +124,30 @@ def test_wet_melt_reaches_paper_tolerance(orc):
         if res < 1e-8:
             break
     assert 0 <= res < 1e-8, res
+
+
+def test_wheeler_top_boundary_values(orc):
+    """Wheeler's geometry (Sec. IV B) with wet-node walls: on the top row the
+    crystal nodes (r <= 0.4 R_c) take u_z = 0, u_r = 0 and u_theta =
+    Omega_x r, the free-surface nodes beyond it u_z = 0; the crucible's side
+    wall and bottom rotate at Omega_c; all exactly (to rounding, U_t = 0.1),
+    through Eqs. (16)-(17)."""
+    from paper_1003_0282_amd import workloads as W
+    c = W.wheeler(1000.0, -250.0, n=24)
+    o = orc.Oracle(c)
+    o.seed()
+    o.step(300)
+    m = o.macros()
+    nr, nz = c["nr"], c["nz"]
+    r = np.arange(nr, dtype=float)
+    top = nz - 1
+    crystal = r <= 0.4 * c["R_c"]
+    om_x, om_c = c["east"]["omega"], c["north"]["omega"]
+    assert np.abs(m["uz"][:, top]).max() < 1e-15
+    assert np.abs(m["ur"][crystal, top]).max() < 1e-15
+    assert np.abs(m["uth"][crystal, top] - om_x * r[crystal]).max() < 1e-15
+    assert np.abs(m["uth"][1:-1, 0] - om_c * r[1:-1]).max() < 1e-15   # bottom
+    assert np.abs(m["uth"][-1, 1:-1] - om_c * r[-1]).max() < 1e-15    # side wall
+    assert np.abs(m["uz"][-1, 1:-1]).max() < 1e-15 and np.abs(m["ur"][-1, 1:-1]).max() < 1e-15
+    # the free surface moves: its u_r and u_theta are not pinned
+    assert np.abs(m["ur"][~crystal, top]).max() > 1e-6
