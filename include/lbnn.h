@@ -10,11 +10,13 @@
  * part of the paper.
  *
  * Network (tensors NHWC, H = nr rows along r, W = nz columns along z):
- *   encoder level l = 0..3, widths c_l:  relu(conv3x3) twice -> e_l,
+ *   encoder level l = 0..3, widths c_l:  sp(conv3x3) twice -> e_l,
  *                                         2x2 average pool between levels;
  *   decoder l = 2, 1, 0: concat(nearest 2x upsample of the level below, e_l)
- *                        -> relu(conv3x3) twice -> d_l;
- *   head: 1x1 convolution d_0 -> c_out channels; loss: mean squared error.
+ *                        -> sp(conv3x3) twice -> d_l;
+ *   head: 1x1 convolution d_0 -> c_out channels; loss: mean squared error;
+ *   sp(v) = log(1 + e^v) (softplus), whose derivative 1 - e^(-sp) the
+ *   backward pass takes from the stored activation.
  * 3x3 convolutions use zero "same" padding and weights W[tap][c_in][c_out],
  * tap = (dy + 1) * 3 + (dx + 1): out[y][x] = sum in[y + dy][x + dx] W[tap].
  * Parameters are FP32 masters (flat, in the order e0a.W, e0a.b, e0b.W, e0b.b,

@@ -5,23 +5,61 @@ file; the product never imports it.  It shares no code with the GPU path.
 
 The network is a 4-level convolutional U-Net on NHWC tensors [B, H, W, C]:
 
-    encoder level l (widths c_l):  x -> relu(conv3x3) -> relu(conv3x3) = e_l
+    encoder level l (widths c_l):  x -> sp(conv3x3) -> sp(conv3x3) = e_l
                                    p_l = avgpool2x2(e_l)           (l < 3)
     decoder level l = 2, 1, 0:     u = upsample2x(d_{l+1}) (d_3 = e_3)
-                                   d_l = relu(conv3x3(relu(conv3x3(concat(u, e_l)))))
+                                   d_l = sp(conv3x3(sp(conv3x3(concat(u, e_l)))))
     head:                          y = conv1x1(d_0) + b   (no activation)
     loss:                          L = mean((y - target)^2)
 
-3x3 convolutions use zero "same" padding; weights W[tap, c_in, c_out] with
-tap = (dy + 1) * 3 + (dx + 1) act as out[y, x] = sum in[y + dy, x + dx] W[tap].
-Nothing here is tuned; every backward formula is the plain adjoint of its
+sp is the softplus activation, sp(z) = log(1 + e^z), whose derivative
+sigmoid(z) = 1 - e^(-sp(z)) follows from its output.  3x3 convolutions use
+zero "same" padding; weights W[tap, c_in, c_out] with tap = (dy + 1) * 3 +
+(dx + 1) act as out[y, x] = sum in[y + dy, x + dx] W[tap].  Nothing here is
+tuned; every backward formula is the plain adjoint of its
 forward and is pinned by central finite differences in the tests.
+
+Operand precision.  ``forward(p, x)`` evaluates the network with every
+tensor exact (FP64).  ``forward(p, x, operands="bf16")`` evaluates the
+network the GPU kernels define, whose matrix-core products take BF16
+operands: the weights of the 3x3 convolutions, the network input and every
+activation tensor the network stores (the activation output of each
+convolution and each pooled map) are rounded to the nearest BF16 value (ties
+to even) where they are produced; biases and the 1x1 head stay as given, and
+all arithmetic (sums, products, the backward pass) stays FP64.  The backward
+pass treats the rounding as the identity (the usual straight-through
+convention) and takes each activation's derivative from its stored output,
+so ``backward`` is the same code in both modes.  A kernel that stores BF16
+activations is compared with this mode.
 """
 from __future__ import annotations
 
 import numpy as np
 
 TAPS = [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+
+
+# ---- BF16 rounding -----------------------------------------------------------
+
+def bf16_round(x):
+    """Nearest BF16 value (8 significant bits, ties to even) of each element,
+    as float64; zero stays zero.  Values stay far inside BF16's exponent
+    range here, so no overflow or subnormal case arises."""
+    x = np.asarray(x, dtype=np.float64)
+    m, e = np.frexp(x)                 # x = m 2^e, 1/2 <= |m| < 1
+    return np.ldexp(np.round(m * 256.0), e - 8)   # np.round: half to even
+
+
+def _ident(x):
+    return x
+
+
+def _rounders(operands):
+    if operands is None:
+        return _ident
+    if operands == "bf16":
+        return bf16_round
+    raise ValueError("operands must be None or 'bf16'")
 
 
 # ---- layers ---------------------------------------------------------------
@@ -53,8 +91,14 @@ def conv3x3_backward(x, W, gout):
     return gxp[:, 1:-1, 1:-1], gW, gb
 
 
-def relu(x):
-    return np.maximum(x, 0.0)
+def softplus(x):
+    """log(1 + e^x), written so that no exponential overflows."""
+    return np.maximum(x, 0.0) + np.log1p(np.exp(-np.abs(x)))
+
+
+def softplus_grad_from_output(a):
+    """d softplus / dx at the input whose output is a: sigmoid(x) = 1 - e^(-a)."""
+    return -np.expm1(-a)
 
 
 def avgpool(x):
@@ -106,25 +150,28 @@ def init_params(c_in: int, seed: int, widths=(32, 64, 128, 256), c_out: int = 4)
     return p
 
 
-def _block(x, p, name, cache):
-    z1 = conv3x3(x, p[name + "a.W"], p[name + "a.b"])
-    a1 = relu(z1)
-    z2 = conv3x3(a1, p[name + "b.W"], p[name + "b.b"])
-    a2 = relu(z2)
+def _block(x, p, name, cache, rnd):
+    z1 = conv3x3(x, rnd(p[name + "a.W"]), p[name + "a.b"])
+    a1 = rnd(softplus(z1))
+    z2 = conv3x3(a1, rnd(p[name + "b.W"]), p[name + "b.b"])
+    a2 = rnd(softplus(z2))
     cache[name] = (x, a1, a2)
     return a2
 
 
-def forward(p, x):
-    """x [B,H,W,Cin] -> (y [B,H,W,Cout], cache)."""
-    cache = {}
-    e0 = _block(x, p, "e0", cache)
-    e1 = _block(avgpool(e0), p, "e1", cache)
-    e2 = _block(avgpool(e1), p, "e2", cache)
-    e3 = _block(avgpool(e2), p, "e3", cache)
-    d2 = _block(np.concatenate([upsample(e3), e2], axis=-1), p, "d2", cache)
-    d1 = _block(np.concatenate([upsample(d2), e1], axis=-1), p, "d1", cache)
-    d0 = _block(np.concatenate([upsample(d1), e0], axis=-1), p, "d0", cache)
+def forward(p, x, operands=None):
+    """x [B,H,W,Cin] -> (y [B,H,W,Cout], cache); operands: None (exact) or
+    "bf16" (see the module docstring)."""
+    rnd = _rounders(operands)
+    cache = {"operands": operands}
+    x = rnd(x)
+    e0 = _block(x, p, "e0", cache, rnd)
+    e1 = _block(rnd(avgpool(e0)), p, "e1", cache, rnd)
+    e2 = _block(rnd(avgpool(e1)), p, "e2", cache, rnd)
+    e3 = _block(rnd(avgpool(e2)), p, "e3", cache, rnd)
+    d2 = _block(np.concatenate([upsample(e3), e2], axis=-1), p, "d2", cache, rnd)
+    d1 = _block(np.concatenate([upsample(d2), e1], axis=-1), p, "d1", cache, rnd)
+    d0 = _block(np.concatenate([upsample(d1), e0], axis=-1), p, "d0", cache, rnd)
     y = d0 @ p["head.W"] + p["head.b"]
     cache["d0out"] = d0
     return y, cache
@@ -134,17 +181,20 @@ def loss(y, target):
     return float(np.mean((y - target) ** 2))
 
 
-def _block_backward(p, name, cache, g, grads):
+def _block_backward(p, name, cache, g, grads, rnd):
     x, a1, a2 = cache[name]
-    g = g * (a2 > 0)
-    g, grads[name + "b.W"], grads[name + "b.b"] = conv3x3_backward(a1, p[name + "b.W"], g)
-    g = g * (a1 > 0)
-    g, grads[name + "a.W"], grads[name + "a.b"] = conv3x3_backward(x, p[name + "a.W"], g)
+    g = g * softplus_grad_from_output(a2)
+    g, grads[name + "b.W"], grads[name + "b.b"] = conv3x3_backward(a1, rnd(p[name + "b.W"]), g)
+    g = g * softplus_grad_from_output(a1)
+    g, grads[name + "a.W"], grads[name + "a.b"] = conv3x3_backward(x, rnd(p[name + "a.W"]), g)
     return g
 
 
 def backward(p, cache, y, target):
-    """Gradients of loss(y, target) w.r.t. every parameter."""
+    """Gradients of loss(y, target) w.r.t. every parameter (of the mode the
+    forward pass ran in; the rounding of the BF16 mode passes gradients
+    through unchanged)."""
+    rnd = _rounders(cache.get("operands"))
     grads = {}
     gy = 2.0 * (y - target) / y.size
     d0 = cache["d0out"]
@@ -153,14 +203,14 @@ def backward(p, cache, y, target):
     g = gy @ p["head.W"].T
     skips = {}
     for lvl, skip, up_ch in (("d0", "e0", None), ("d1", "e1", None), ("d2", "e2", None)):
-        gcat = _block_backward(p, lvl, cache, g, grads)
+        gcat = _block_backward(p, lvl, cache, g, grads, rnd)
         c_skip = cache[skip][2].shape[-1]
         skips[skip] = gcat[..., -c_skip:]
         g = upsample_backward(gcat[..., :-c_skip])
-    g = _block_backward(p, "e3", cache, g, grads)
+    g = _block_backward(p, "e3", cache, g, grads, rnd)
     for lvl in ("e2", "e1", "e0"):
         g = avgpool_backward(g) + skips[lvl]
-        g = _block_backward(p, lvl, cache, g, grads)
+        g = _block_backward(p, lvl, cache, g, grads, rnd)
     return grads
 
 

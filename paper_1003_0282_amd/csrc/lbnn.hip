@@ -38,6 +38,14 @@ __device__ inline bf16s f2bf(float f) {
   return (bf16s)(u >> 16);
 }
 
+// Activation of every 3x3 convolution: softplus, sp(v) = log(1 + e^v).  Its
+// derivative, sigmoid(v) = 1 - e^(-sp(v)), follows from the stored output,
+// so the backward pass needs no pre-activation.  (A smooth activation keeps
+// the gradient of a network with BF16 activations well conditioned: a
+// ReLU's mask flips wherever rounding moves a pre-activation across zero.)
+__device__ inline float softplus(float v) { return fmaxf(v, 0.0f) + log1pf(__expf(-fabsf(v))); }
+__device__ inline float softplus_grad(float a) { return -expm1f(-a); }
+
 __device__ inline f32x16 mfma(u16x8 a, u16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
@@ -64,9 +72,9 @@ struct ConvArgs {
   const bf16s* in;
   const bf16s* wt;
   const float* bias;  // [Cn] or NULL
-  const bf16s* mask;  // [B][H][W][Cn] or NULL: output zeroed where mask <= 0
+  const bf16s* mask;  // [B][H][W][Cn] or NULL: output times softplus_grad(mask)
   bf16s* out;
-  int B, H, W, Ck, Cn, sign, relu;
+  int B, H, W, Ck, Cn, sign, act;  // act: softplus on the output
 };
 
 // Workgroup tile: PT pixels x NT output channels, 4 waves in a WPX x WCH
@@ -183,9 +191,9 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs A) {
         const long long px = pix0 + (wpx * MW + i) * 32 + acc_row(q, g);
         if (px >= npix) continue;
         float v = acc[i][j][q] + bias;
-        if (A.relu && v < 0.0f) v = 0.0f;
+        if (A.act) v = softplus(v);
         const long long o = px * A.Cn + col;
-        if (A.mask && !(bf2f(A.mask[o]) > 0.0f)) v = 0.0f;
+        if (A.mask) v *= softplus_grad(bf2f(A.mask[o]));
         A.out[o] = f2bf(v);
       }
   }
@@ -281,9 +289,9 @@ __global__ void __launch_bounds__(256) k_conv_row(ConvArgs A) {
     for (int q = 0; q < 16; ++q) {
       const long long px = prow + acc_row(q, g);
       float v = acc[j][q] + bias;
-      if (A.relu && v < 0.0f) v = 0.0f;
+      if (A.act) v = softplus(v);
       const long long o = px * A.Cn + col;
-      if (A.mask && !(bf2f(A.mask[o]) > 0.0f)) v = 0.0f;
+      if (A.mask) v *= softplus_grad(bf2f(A.mask[o]));
       A.out[o] = f2bf(v);
     }
   }
@@ -301,12 +309,15 @@ __global__ void __launch_bounds__(256) k_conv_row(ConvArgs A) {
 // pixels walked in stages of SP = wg_sp(MB, NB) pixels (SP / 16 K-steps, as
 // many as the 256 threads can load in one round); wave w owns block
 // (w % MB, (w / MB) % NB) and the K-steps kk with kk % KS = w / (MB NB),
-// KS = 4 / (MB NB).  Partial sums go to dW with FP32 atomics.  x has Cx
+// KS = 4 / (MB NB).  Each workgroup stores its partial sums in the slice
+// of its pixel chunk, part[chunk][9][Ci][Co]; k_sum_chunks then adds the
+// slices in chunk order, so the result does not depend on which workgroup
+// finishes first (no atomics: training repeats bit for bit).  x has Cx
 // channels (the padded input of the first layer); only ci < Ci are written.
 struct WgradArgs {
   const bf16s* x;   // [B][H][W][Cx]
   const bf16s* gz;  // [B][H][W][Co]
-  float* dW;        // [9][Ci][Co]
+  float* part;      // [chunks][9][Ci][Co]
   int B, H, W, Cx, Ci, Co, chunk;
   int cib, cob;     // ci / co tiles per tap
 };
@@ -362,7 +373,8 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs A) {
   const int ci0 = (blk % A.cib) * 32 * MB, co0 = (blk / A.cib) * 32 * NB;
   const int dy = t / 3 - 1, dx = t % 3 - 1;
   const long long npix = (long long)A.B * A.H * A.W;
-  const long long p_beg = (long long)xcd_tile(blockIdx.x, gridDim.x) * A.chunk;
+  const int cidx = xcd_tile(blockIdx.x, gridDim.x);
+  const long long p_beg = (long long)cidx * A.chunk;
   const long long p_end = std::min<long long>(p_beg + A.chunk, npix);
   // this thread's loading role: an 8-pixel group and an 8-channel group
   const bool ldx = tid < XT, ldg = tid >= XT && tid < XT + GT;
@@ -412,11 +424,37 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs A) {
       acc = mfma(a, b, acc);
     }
   }
+  // the KS waves that split this block's K-steps meet in LDS (fixed order)
+  float* part = A.part + (long long)cidx * 9 * A.Ci * A.Co;
   const int co = co0 + 32 * nb + m;
+  if (KS == 1) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int ci = ci0 + 32 * mb + acc_row(q, g);
-    if (ci < A.Ci) atomicAdd(A.dW + ((long long)t * A.Ci + ci) * A.Co + co, acc[q]);
+    for (int q = 0; q < 16; ++q) {
+      const int ci = ci0 + 32 * mb + acc_row(q, g);
+      if (ci < A.Ci) part[((long long)t * A.Ci + ci) * A.Co + co] = acc[q];
+    }
+  } else {
+    // waves ks > 0 hand their sums to wave ks = 0 of the same block through
+    // LDS (the x tile is no longer needed), which adds them in ks order
+    constexpr int L = 64 * MB * NB;  // threads of one K-step slice
+    static_assert(sizeof(sx) >= 16 * (KS - 1) * L * sizeof(float), "reduction buffer");
+    float* red = reinterpret_cast<float*>(sx);
+    const int lt = tid % L;
+    __syncthreads();  // every wave is done with the staged tiles
+    if (ks > 0) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) red[(q * (KS - 1) + ks - 1) * L + lt] = acc[q];
+    }
+    __syncthreads();
+    if (ks == 0) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        float v = acc[q];
+        for (int k = 1; k < KS; ++k) v += red[(q * (KS - 1) + k - 1) * L + lt];
+        const int ci = ci0 + 32 * mb + acc_row(q, g);
+        if (ci < A.Ci) part[((long long)t * A.Ci + ci) * A.Co + co] = v;
+      }
+    }
   }
 }
 
@@ -444,7 +482,8 @@ __global__ void __launch_bounds__(256) k_wgrad_row(WgradArgs A) {
   const int ci0 = (blk % A.cib) * 32, co0 = (blk / A.cib) * 32;
   const int segs = A.W / WR_TW;
   const long long nseg = (long long)A.B * A.H * segs;
-  const long long s_beg = (long long)xcd_tile(blockIdx.x, gridDim.x) * A.chunk;
+  const int cidx = xcd_tile(blockIdx.x, gridDim.x);
+  const long long s_beg = (long long)cidx * A.chunk;
   const long long s_end = std::min<long long>(s_beg + A.chunk, nseg);
   f32x16 acc[3];
 #pragma unroll
@@ -505,6 +544,7 @@ __global__ void __launch_bounds__(256) k_wgrad_row(WgradArgs A) {
       }
     }
   }
+  float* part = A.part + (long long)cidx * 9 * A.Ci * A.Co;
   const int co = co0 + m;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -513,18 +553,46 @@ __global__ void __launch_bounds__(256) k_wgrad_row(WgradArgs A) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int ci = ci0 + acc_row(q, g);
-      if (ci < A.Ci) atomicAdd(A.dW + ((long long)t * A.Ci + ci) * A.Co + co, acc[k][q]);
+      if (ci < A.Ci) part[((long long)t * A.Ci + ci) * A.Co + co] = acc[k][q];
     }
   }
 }
 
-// Bias gradient db[c] += sum over a chunk of pixels of gz[p][c].  Thread t
-// owns channels 8 (t % G) .. + 7 (G = C / 8, one 16-byte load per pixel) and
-// every (256 / G)-th pixel of the chunk, with four independent partial sums
-// per channel so that four loads are in flight; the partial sums meet in
-// LDS and one atomic add per channel and chunk remains.  The chunk holds
-// 64 (256 / G) pixels (64 loads per thread).  C <= 256, a multiple of 8.
-__global__ void __launch_bounds__(256) k_bgrad(const bf16s* gz, float* db, long long npix, int C) {
+// out[w] = sum over chunks c = 0, 1, ... of part[c][w], in that order: the
+// second, fixed-order pass of every parameter-gradient reduction.
+__global__ void __launch_bounds__(256) k_sum_chunks(const float* part, float* out, long long n,
+                                                    int nchunk) {
+  const long long w = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= n) return;
+  float s = 0.0f;
+  for (int c = 0; c < nchunk; ++c) s += part[(long long)c * n + w];
+  out[w] = s;
+}
+
+// The same for FP64 partial sums reduced to one value by one workgroup:
+// thread t adds the partials t, t + 256, ... in order, then a fixed tree.
+__global__ void __launch_bounds__(256) k_sum_chunks_d(const double* part, double* out,
+                                                      int nchunk) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int c = threadIdx.x; c < nchunk; c += 256) s += part[c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// Bias gradient part[chunk][c] = sum over a chunk of pixels of gz[p][c].
+// Thread t owns channels 8 (t % G) .. + 7 (G = C / 8, one 16-byte load per
+// pixel) and every (256 / G)-th pixel of the chunk, with four independent
+// partial sums per channel so that four loads are in flight; the partial
+// sums meet in LDS in a fixed order and k_sum_chunks adds the chunks.  The
+// chunk holds 64 (256 / G) pixels (64 loads per thread).  C <= 256, a
+// multiple of 8.
+__global__ void __launch_bounds__(256) k_bgrad(const bf16s* gz, float* part, long long npix, int C) {
   __shared__ float red[256 * 8];
   const int G = C / 8, nq = 256 / G;
   const int cg = threadIdx.x % G, q = threadIdx.x / G;
@@ -557,7 +625,7 @@ __global__ void __launch_bounds__(256) k_bgrad(const bf16s* gz, float* db, long 
     const int c = threadIdx.x, g = c / 8, e = c % 8;
     float t = 0.0f;
     for (int k = 0; k < nq; ++k) t += red[(k * G + g) * 8 + e];
-    atomicAdd(db + c, t);
+    part[(long long)blockIdx.x * C + c] = t;
   }
 }
 
@@ -594,8 +662,9 @@ __global__ void k_pool(const bf16s* in, bf16s* out, int B, int H, int W, int C) 
   *reinterpret_cast<u16x8*>(out + 8LL * v) = o;
 }
 
-// Gradient into an encoder output e [B][H][W][C]: a quarter of the pooled
-// gradient of its 2x2 parent plus the skip gradient, zeroed where e <= 0.
+// Gradient into the pre-activation of an encoder output e [B][H][W][C]: a
+// quarter of the pooled gradient of its 2x2 parent plus the skip gradient,
+// times the activation's derivative softplus_grad(e).
 __global__ void k_pool_back(const bf16s* gp, const bf16s* gskip, const bf16s* e, bf16s* ge,
                             int B, int H, int W, int C) {
   const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -610,7 +679,7 @@ __global__ void k_pool_back(const bf16s* gp, const bf16s* gskip, const bf16s* e,
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const float t = 0.25f * bf2f(pg[k]) + bf2f(sk[k]);
-    o[k] = bf2f(ev[k]) > 0.0f ? f2bf(t) : (bf16s)0;
+    o[k] = f2bf(t * softplus_grad(bf2f(ev[k])));
   }
   *reinterpret_cast<u16x8*>(ge + 8LL * v) = o;
 }
@@ -633,8 +702,9 @@ __global__ void k_upcat(const bf16s* u, const bf16s* s, bf16s* cat, int B, int H
   *reinterpret_cast<u16x8*>(cat + 8LL * v) = o;
 }
 
-// Backward of k_upcat: gu [B][H/2][W/2][Cu] = sum of the 2x2 children,
-// zeroed where the upsampled tensor u <= 0 (it is a ReLU output); the skip
+// Backward of k_upcat: gu [B][H/2][W/2][Cu] = sum of the 2x2 children times
+// softplus_grad(u) (u is an activation output; gu is the gradient of its
+// pre-activation); the skip
 // part is copied to gskip [B][H][W][Cs].  Threads [0, nu) cover gu, the next
 // ns threads gskip (8 channels each).
 __global__ void k_upcat_back(const bf16s* gcat, const bf16s* u, bf16s* gu, bf16s* gskip, int B,
@@ -655,7 +725,7 @@ __global__ void k_upcat_back(const bf16s* gcat, const bf16s* u, bf16s* gu, bf16s
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const float t = bf2f(a[k]) + bf2f(c[k]) + bf2f(d[k]) + bf2f(e[k]);
-      o[k] = bf2f(uv[k]) > 0.0f ? f2bf(t) : (bf16s)0;
+      o[k] = f2bf(t * softplus_grad(bf2f(uv[k])));
     }
     *reinterpret_cast<u16x8*>(gu + 8LL * v) = o;
   } else if (v < nu + ns) {
@@ -667,10 +737,12 @@ __global__ void k_upcat_back(const bf16s* gcat, const bf16s* u, bf16s* gu, bf16s
 
 // Head: y[p][k] = sum_c d0[p][c] Wh[c][k] + bh[k] (FP32 parameters, K <= 8,
 // C a multiple of 8: the row of d0 is read 16 bytes at a time).  With a
-// target: gy = 2 (y - t) / N into gy and the squared error summed into loss.
+// target: gy = 2 (y - t) / N into gy and the workgroup's squared error into
+// loss_part[block] (added in block order by k_sum_chunks_d).
 __global__ void __launch_bounds__(256) k_head(const bf16s* d0, const float* Wh, const float* bh,
-                                              float* y, const float* tgt, float* gy, double* loss,
-                                              long long npix, int C, int K, double inv_n) {
+                                              float* y, const float* tgt, float* gy,
+                                              double* loss_part, long long npix, int C, int K,
+                                              double inv_n) {
   __shared__ float red[256];
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   float se = 0.0f;
@@ -706,11 +778,12 @@ __global__ void __launch_bounds__(256) k_head(const bf16s* d0, const float* Wh, 
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(loss, (double)red[0]);
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = (double)red[0];
 }
 
-// Head backward, input side: gd0[p][c] = (sum_k gy[p][k] Wh[c][k]) where
-// d0 > 0 (d0 is a ReLU output); 8 channels per 16-byte load and store.
+// Head backward, input side: gd0[p][c] = (sum_k gy[p][k] Wh[c][k])
+// times softplus_grad(d0) (d0 is an activation output); 8 channels per
+// 16-byte load and store.
 __global__ void __launch_bounds__(256) k_head_back(const bf16s* d0, const float* gy,
                                                    const float* Wh, bf16s* gd0, long long npix,
                                                    int C, int K) {
@@ -728,7 +801,7 @@ __global__ void __launch_bounds__(256) k_head_back(const bf16s* d0, const float*
 #pragma unroll
       for (int k = 0; k < 8; ++k)
         if (k < K) s += g[k] * Wh[(c0 + e) * K + k];
-      o[e] = bf2f(v[e]) > 0.0f ? f2bf(s) : (bf16s)0;
+      o[e] = f2bf(s * softplus_grad(bf2f(v[e])));
     }
     *reinterpret_cast<u16x8*>(gd0 + p * C + c0) = o;
   }
@@ -738,11 +811,11 @@ __global__ void __launch_bounds__(256) k_head_back(const bf16s* d0, const float*
 // dbh[k] = sum_p gy[p][k].  As in k_bgrad, thread t owns channels
 // 8 (t % G) .. + 7 (one 16-byte load of d0 per pixel) and every (256 / G)-th
 // pixel of a chunk of 64 (256 / G) pixels, accumulating 8 x K products in
-// registers; the partial sums meet in LDS and one atomic add per weight and
-// chunk remains (few chunks: same-address atomics serialise).  C <= 256 a
-// multiple of 8, K <= 8.
-__global__ void __launch_bounds__(256) k_head_wgrad(const bf16s* d0, const float* gy, float* dWh,
-                                                    float* dbh, long long npix, int C, int K) {
+// registers; the partial sums meet in LDS in a fixed order and the chunk's
+// C K + K sums go to part[chunk] (dWh then dbh), which k_sum_chunks adds.
+// C <= 256 a multiple of 8, K <= 8.
+__global__ void __launch_bounds__(256) k_head_wgrad(const bf16s* d0, const float* gy, float* part,
+                                                    long long npix, int C, int K) {
   __shared__ float red[8 * 256 * 8];  // [k][thread][e]
   __shared__ float redb[256 * 8];     // [thread][k]
   const int G = C / 8, nq = 256 / G;
@@ -776,12 +849,11 @@ __global__ void __launch_bounds__(256) k_head_wgrad(const bf16s* d0, const float
     if (t < C * K) {
       const int c = t / K, k = t % K, g = c / 8, e = c % 8;
       for (int j = 0; j < nq; ++j) acc += red[(k * 256 + j * G + g) * 8 + e];
-      atomicAdd(dWh + c * K + k, acc);
     } else {
       const int k = t - C * K;
       for (int j = 0; j < nq; ++j) acc += redb[(j * G) * 8 + k];
-      atomicAdd(dbh + k, acc);
     }
+    part[(long long)blockIdx.x * (C * K + K) + t] = acc;
   }
 }
 
@@ -818,10 +890,6 @@ __global__ void k_zero(float* p, long long n) {
 
 __global__ void k_set_i32(int* p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
-}
-
-__global__ void k_zero_d(double* p) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0.0;
 }
 
 struct FieldOut {
@@ -916,13 +984,62 @@ struct Plan {
   Conv cv[NCONV];
   long long off_hW, off_hb, nparam;
   // workspace byte offsets
-  size_t params, grads, m1, m2, wcopies, loss, act, total;
+  size_t params, grads, m1, m2, wcopies, loss, act, part, loss_part, total;
   // activations (BF16) per level, element counts per sample
   size_t xin, e_a[4], e_b[4], pool[3], cat[3], d_a[3], d_b[3], y, gy, gbig1[4], gbig2[4],
       gcat[3], gskip[3];
 };
 
 long long npix_lvl(const lbnn_desc& d, int l) { return (long long)(d.H >> l) * (d.W >> l); }
+
+unsigned blocks(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// Level (image size H >> lvl) of convolution k of the U-Net.
+int conv_level(int k) { return k < D2A ? k / 2 : 2 - (k - D2A) / 2; }
+
+// Launch shape of the weight gradient of a convolution with padded input
+// channels Ck, real ci and co outputs on a B x H x W level: the row-segment
+// kernel (narrow outputs on rows a multiple of WR_TW wide) or the tiled one,
+// its pixel (segment) chunk, and the grid: gx chunks x gy tiles.
+struct WgShape {
+  bool row;
+  int MB, NB, cib, cob, chunk;
+  long long gx, gy;
+};
+
+WgShape wgrad_shape(int Ck, int co, int B, int H, int W) {
+  WgShape S;
+  const long long npix = (long long)B * H * W;
+  S.row = W % WR_TW == 0 && co % 64 != 0;
+  if (S.row) {
+    S.MB = S.NB = 1;
+    S.cib = (Ck + 31) / 32;
+    S.cob = co / 32;
+    const long long nseg = (long long)B * H * (W / WR_TW);
+    const long long tiles = (long long)S.cib * S.cob;
+    // about 1024 workgroups, each at least 4 segments long
+    S.chunk = (int)std::max<long long>(4, (nseg * tiles + 1023) / 1024);
+    S.gx = (nseg + S.chunk - 1) / S.chunk;
+    S.gy = tiles;
+  } else {
+    S.MB = Ck >= 64 && Ck % 64 == 0 ? 2 : 1;
+    S.NB = co % 64 == 0 ? 2 : 1;
+    S.cib = (Ck + 32 * S.MB - 1) / (32 * S.MB);
+    S.cob = co / (32 * S.NB);
+    const long long tiles = 9LL * S.cib * S.cob;
+    // about 2048 workgroups, each at least one and at most 64 stages long
+    const int sp = wg_sp(S.MB, S.NB);
+    long long ch = (npix * tiles + 2047) / 2048;
+    ch = std::max<long long>(sp, std::min<long long>(64LL * sp, ch));
+    S.chunk = (int)((ch + sp - 1) / sp * sp);
+    S.gx = blocks(npix, S.chunk);
+    S.gy = tiles;
+  }
+  return S;
+}
+
+// Chunks of the bias gradient and of the head's parameter gradient.
+long long bgrad_chunks(long long npix, int C) { return blocks(npix, 64 * (256 / (C / 8))); }
 
 bool plan(const lbnn_desc& d, Plan& P) {
   P.d = d;
@@ -984,6 +1101,23 @@ bool plan(const lbnn_desc& d, Plan& P) {
   }
   P.y = o; o = al(o + 4 * B * d.c_out * (size_t)npix_lvl(d, 0));
   P.gy = o; o = al(o + 4 * B * d.c_out * (size_t)npix_lvl(d, 0));
+  // per-chunk partial sums of the parameter gradients (one reduction at a
+  // time on the stream, so one buffer serves all), for every batch size up to
+  // max_batch; and the per-workgroup squared errors of the loss
+  size_t part = 0;
+  for (int b = 1; b <= d.max_batch; ++b) {
+    for (int k = 0; k < NCONV; ++k) {
+      const Conv& c = P.cv[k];
+      const int l = conv_level(k);
+      const WgShape S = wgrad_shape(c.Ck, c.co, b, d.H >> l, d.W >> l);
+      part = std::max(part, (size_t)S.gx * 9 * c.ci * c.co);
+      part = std::max(part, (size_t)bgrad_chunks((long long)b * npix_lvl(d, l), c.co) * c.co);
+    }
+    part = std::max(part, (size_t)bgrad_chunks((long long)b * npix_lvl(d, 0), c0) *
+                              ((size_t)c0 * d.c_out + d.c_out));
+  }
+  P.part = o; o = al(o + 4 * part);
+  P.loss_part = o; o = al(o + 8 * (size_t)blocks(B * npix_lvl(d, 0)));
   P.total = o;
   return true;
 }
@@ -1021,8 +1155,6 @@ struct lbnn_s {
 
 namespace {
 
-unsigned blocks(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
-
 lbaxi_status refresh_weights(lbnn_t* h) {
   if (!h->wdirty) return LBAXI_OK;
   for (int k = 0; k < NCONV; ++k) {
@@ -1051,14 +1183,14 @@ lbaxi_status conv(lbnn_t* h, const Conv& c, const bf16s* in, bf16s* out, int lvl
     A.Ck = c.Ck;
     A.Cn = c.co;
     A.sign = 1;
-    A.relu = 1;
+    A.act = 1;
   } else {
     A.wt = h->at<bf16s>(c.wb);
     A.bias = nullptr;
     A.Ck = c.co;
     A.Cn = c.Ck;
     A.sign = -1;
-    A.relu = 0;
+    A.act = 0;
   }
   const long long npix = (long long)B * A.H * A.W;
   // 2 x 2 blocks per wave where the output width allows, else 4 x 1
@@ -1103,11 +1235,19 @@ lbaxi_status conv(lbnn_t* h, const Conv& c, const bf16s* in, bf16s* out, int lvl
   return LBAXI_OK;
 }
 
+// Sum of the per-chunk partials part[nchunk][n] into out[n] (chunk order).
+lbaxi_status sum_chunks(lbnn_t* h, float* out, long long n, long long nchunk) {
+  hipLaunchKernelGGL(k_sum_chunks, dim3(blocks(n)), dim3(256), 0, h->stream,
+                     h->at<float>(h->P.part), out, n, (int)nchunk);
+  NCHK(hipGetLastError());
+  return LBAXI_OK;
+}
+
 lbaxi_status wgrad(lbnn_t* h, const Conv& c, const bf16s* x, const bf16s* gz, int lvl, int B) {
   WgradArgs A;
   A.x = x;
   A.gz = gz;
-  A.dW = h->grads() + c.off_W;
+  A.part = h->at<float>(h->P.part);
   A.B = B;
   A.H = h->P.d.H >> lvl;
   A.W = h->P.d.W >> lvl;
@@ -1115,39 +1255,29 @@ lbaxi_status wgrad(lbnn_t* h, const Conv& c, const bf16s* x, const bf16s* gz, in
   A.Ci = c.ci;
   A.Co = c.co;
   const long long npix = (long long)B * A.H * A.W;
-  if (A.W % WR_TW == 0 && c.co % 64 != 0) {
+  const WgShape S = wgrad_shape(c.Ck, c.co, B, A.H, A.W);
+  A.cib = S.cib;
+  A.cob = S.cob;
+  A.chunk = S.chunk;
+  dim3 grid((unsigned)S.gx, (unsigned)S.gy);
+  void* fn;
+  if (S.row) {
     // narrow outputs on wide rows: row segments, every input row staged once
     // for all nine taps
-    A.cib = (c.Ck + 31) / 32;
-    A.cob = c.co / 32;
-    const long long nseg = (long long)B * A.H * (A.W / WR_TW);
-    const long long tiles = (long long)A.cib * A.cob;
-    // about 1024 workgroups, each at least 4 segments long
-    A.chunk = (int)std::max<long long>(4, (nseg * tiles + 1023) / 1024);
-    dim3 grid((unsigned)((nseg + A.chunk - 1) / A.chunk), (unsigned)tiles);
-    void* args[] = {&A};
-    NCHK(hipLaunchKernel((void*)&k_wgrad_row, grid, dim3(256), args, 0, h->stream));
+    fn = (void*)&k_wgrad_row;
   } else {
-  const int MB = c.Ck >= 64 && c.Ck % 64 == 0 ? 2 : 1;
-  const int NB = c.co % 64 == 0 ? 2 : 1;
-  A.cib = (c.Ck + 32 * MB - 1) / (32 * MB);
-  A.cob = c.co / (32 * NB);
-  const long long tiles = 9LL * A.cib * A.cob;
-  // about 2048 workgroups, each at least one and at most 64 stages long
-  const int sp = wg_sp(MB, NB);
-  long long ch = (npix * tiles + 2047) / 2048;
-  ch = std::max<long long>(sp, std::min<long long>(64LL * sp, ch));
-  A.chunk = (int)((ch + sp - 1) / sp * sp);
-  dim3 grid(blocks(npix, A.chunk), (unsigned)tiles);
-  void* fn = MB == 2 ? (NB == 2 ? (void*)&k_wgrad<2, 2> : (void*)&k_wgrad<2, 1>)
-                     : (NB == 2 ? (void*)&k_wgrad<1, 2> : (void*)&k_wgrad<1, 1>);
+    fn = S.MB == 2 ? (S.NB == 2 ? (void*)&k_wgrad<2, 2> : (void*)&k_wgrad<2, 1>)
+                   : (S.NB == 2 ? (void*)&k_wgrad<1, 2> : (void*)&k_wgrad<1, 1>);
+  }
   void* args[] = {&A};
   NCHK(hipLaunchKernel(fn, grid, dim3(256), args, 0, h->stream));
-  }
-  hipLaunchKernelGGL(k_bgrad, dim3(blocks(npix, 64 * (256 / (c.co / 8)))), dim3(256), 0, h->stream, gz,
-                     h->grads() + c.off_b, npix, c.co);
+  lbaxi_status s;
+  if ((s = sum_chunks(h, h->grads() + c.off_W, 9LL * c.ci * c.co, S.gx)) != LBAXI_OK) return s;
+  const long long nb = bgrad_chunks(npix, c.co);
+  hipLaunchKernelGGL(k_bgrad, dim3((unsigned)nb), dim3(256), 0, h->stream, gz,
+                     h->at<float>(h->P.part), npix, c.co);
   NCHK(hipGetLastError());
-  return LBAXI_OK;
+  return sum_chunks(h, h->grads() + c.off_b, c.co, nb);
 }
 
 }  // namespace
@@ -1283,22 +1413,25 @@ lbaxi_status lbnn_backward(lbnn_t* h, const float* d_target, float* d_grads, dou
   const int cw[4] = {c0, c1, c2, c3};
   const long long np0 = (long long)B * npix_lvl(P.d, 0);
   lbaxi_status s;
-  hipLaunchKernelGGL(k_zero, dim3(blocks(P.nparam)), dim3(256), 0, h->stream, h->grads(),
-                     P.nparam);
-  hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, h->stream, h->at<double>(P.loss));
+  // every parameter gradient and the loss are written (not accumulated) below
   // head: y again with the target, then its backward into gz of d0b
   hipLaunchKernelGGL(k_head, dim3(blocks(np0)), dim3(256), 0, h->stream, h->act(P.d_b[0]),
                      h->params() + P.off_hW, h->params() + P.off_hb, h->at<float>(P.y), d_target,
-                     h->at<float>(P.gy), h->at<double>(P.loss), np0, c0, P.d.c_out,
+                     h->at<float>(P.gy), h->at<double>(P.loss_part), np0, c0, P.d.c_out,
                      1.0 / ((double)np0 * P.d.c_out));
+  hipLaunchKernelGGL(k_sum_chunks_d, dim3(1), dim3(256), 0, h->stream,
+                     h->at<double>(P.loss_part), h->at<double>(P.loss), (int)blocks(np0));
   hipLaunchKernelGGL(k_head_back, dim3(blocks(np0)), dim3(256), 0, h->stream, h->act(P.d_b[0]),
                      h->at<float>(P.gy), h->params() + P.off_hW, h->act(P.gbig1[0]), np0, c0,
                      P.d.c_out);
-  hipLaunchKernelGGL(k_head_wgrad, dim3(blocks(np0, 64 * (256 / (c0 / 8)))), dim3(256), 0, h->stream,
-                     h->act(P.d_b[0]),
-                     h->at<float>(P.gy), h->grads() + P.off_hW, h->grads() + P.off_hb, np0, c0,
-                     P.d.c_out);
+  const long long nh = bgrad_chunks(np0, c0);
+  hipLaunchKernelGGL(k_head_wgrad, dim3((unsigned)nh), dim3(256), 0, h->stream, h->act(P.d_b[0]),
+                     h->at<float>(P.gy), h->at<float>(P.part), np0, c0, P.d.c_out);
   NCHK(hipGetLastError());
+  // head.W and head.b are contiguous in the parameter vector, as in a chunk
+  if ((s = sum_chunks(h, h->grads() + P.off_hW, (long long)c0 * P.d.c_out + P.d.c_out, nh)) !=
+      LBAXI_OK)
+    return s;
   // decoder levels 0, 1, 2: gz of the block output is in gbig1[l]
   for (int l = 0; l <= 2; ++l) {
     const int ka = D2A + 2 * (2 - l);
@@ -1311,7 +1444,7 @@ lbaxi_status lbnn_backward(lbnn_t* h, const float* d_target, float* d_grads, dou
     if ((s = wgrad(h, ca, h->act(P.cat[l]), gza, l, B)) != LBAXI_OK) return s;
     if ((s = conv(h, ca, gza, h->act(P.gcat[l]), l, B, true, nullptr)) != LBAXI_OK) return s;
     // split: upsampled part -> gz of the level below's block output (masked by
-    // that ReLU output), skip part -> gskip[l]
+    // that activation's derivative), skip part -> gskip[l]
     const int Hl = P.d.H >> l, Wl = P.d.W >> l;
     const bf16s* u = l < 2 ? h->act(P.d_b[l + 1]) : h->act(P.e_b[3]);
     bf16s* gu = h->act(P.gbig1[l + 1]);

@@ -1,9 +1,15 @@
 """GPU tests of the warm-start network kernels against the FP64 NumPy oracle.
 
-The kernels run BF16 MFMA products with FP32 accumulation and keep
-activations and their gradients in BF16 (8-bit mantissa), so agreement with
-the FP64 oracle is judged by relative norms and cosines: ~14 layers of BF16
-rounding give a few per cent at most on the output and on every gradient.
+The kernels multiply BF16 operands on the matrix cores with FP32
+accumulation: the convolution weights and every stored activation are BF16
+values.  The oracle's BF16-operand mode evaluates exactly that network (the
+same operands, rounded to the nearest BF16 value where the network produces
+them) with FP64 arithmetic everywhere else, so the forward output agrees to
+accumulation-order rounding and every parameter gradient (whose chain runs
+through BF16 gradient tensors in the kernels) to the contracted bar: cosine
+>= 0.999 and relative norm <= 1e-2.  The exact-operand oracle is reported
+beside it for information: the BF16 network is a slightly different
+function from the FP64 one.
 """
 import numpy as np
 import pytest
@@ -40,6 +46,9 @@ def _setup(H=16, W=32, B=2, c_in=8, c_out=4, seed=0):
     t = 0.5 * rng.standard_normal((B, H, W, c_out))
     net = lbnn.Net(H, W, c_in, c_out, WIDTHS, max_batch=B)
     assert net.nparam == N.n_params(p)
+    # the GPU holds FP32 parameters and inputs: the oracle gets the same values
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    x = x.astype(np.float32).astype(np.float64)
     net.set_params(lbnn.flatten_params(p, names).astype(np.float32))
     xd = torch.tensor(x, dtype=torch.float32, device="cuda")
     td = torch.tensor(t, dtype=torch.float32, device="cuda")
@@ -50,34 +59,46 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-def test_forward_matches_oracle():
-    net, p, names, x, t, xd, td = _setup()
-    y = net.forward(xd).double().cpu().numpy()
-    y_ref, _ = N.forward(p, x)
-    err = _rel(y, y_ref)
-    print("forward rel err", err)
-    assert err < 3e-2
+FWD_TOL = 1e-2       # relative norm of the output
+COS_MIN, REL_MAX = 0.999, 1e-2
 
 
-def test_gradients_match_oracle():
+def _check_gradients(net, p, names, x, t, td, c_in, c_out):
     from paper_1003_0282_amd import lbnn
-    net, p, names, x, t, xd, td = _setup(seed=1)
-    net.forward(xd)
     loss, g = net.backward(td)
-    y_ref, cache = N.forward(p, x)
+    y_ref, cache = N.forward(p, x, operands="bf16")
     g_ref = N.backward(p, cache, y_ref, t)
-    assert abs(loss - N.loss(y_ref, t)) / N.loss(y_ref, t) < 3e-2
-    gd = lbnn.unflatten(g.double().cpu().numpy(), N.layer_shapes(8, WIDTHS, 4))
-    worst = []
+    assert abs(loss - N.loss(y_ref, t)) / N.loss(y_ref, t) < 1e-3
+    gd = lbnn.unflatten(g.double().cpu().numpy(), N.layer_shapes(c_in, WIDTHS, c_out))
+    y_x, cache_x = N.forward(p, x)
+    g_x = N.backward(p, cache_x, y_x, t)
+    worst, worst_x = [], []
     for name in names:
         a, b = gd[name].reshape(-1), g_ref[name].reshape(-1)
         cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
         rel = _rel(a, b)
         worst.append((rel, cos, name))
-        # the deepest weight gradients sum over few pixels (64 at level 2 of
-        # this 16 x 32 input), so BF16 rounding is least averaged out there
-        assert cos > 0.99 and rel < 0.15, (name, cos, rel)
-    print("worst gradient", max(worst))
+        bx = g_x[name].reshape(-1)
+        worst_x.append((_rel(a, bx), name))
+        assert cos >= COS_MIN and rel <= REL_MAX, (name, cos, rel)
+    print("worst gradient vs BF16-operand oracle", max(worst))
+    print("worst gradient vs exact-operand oracle (information)", max(worst_x))
+
+
+def test_forward_matches_oracle():
+    net, p, names, x, t, xd, td = _setup()
+    y = net.forward(xd).double().cpu().numpy()
+    y_ref, _ = N.forward(p, x, operands="bf16")
+    err = _rel(y, y_ref)
+    y_x, _ = N.forward(p, x)
+    print("forward rel err %.2e (exact-operand oracle: %.2e)" % (err, _rel(y, y_x)))
+    assert err <= FWD_TOL
+
+
+def test_gradients_match_oracle():
+    net, p, names, x, t, xd, td = _setup(seed=1)
+    net.forward(xd)
+    _check_gradients(net, p, names, x, t, td, 8, 4)
 
 
 @pytest.mark.parametrize("H,W,B,c_in,c_out", [(40, 72, 3, 5, 5), (128, 256, 2, 8, 5)])
@@ -85,23 +106,26 @@ def test_forward_and_gradients_other_shapes(H, W, B, c_in, c_out):
     """Odd level sizes (5 x 9 at the deepest level, so pixel groups straddle
     rows), padded input channels, several pixel chunks per weight-gradient
     workgroup, and the 128 x 256 shape of the warm start."""
-    from paper_1003_0282_amd import lbnn
     net, p, names, x, t, xd, td = _setup(H, W, B, c_in, c_out, seed=4)
     y = net.forward(xd).double().cpu().numpy()
-    y_ref, cache = N.forward(p, x)
-    assert _rel(y, y_ref) < 3e-2, _rel(y, y_ref)
-    loss, g = net.backward(td)
-    g_ref = N.backward(p, cache, y_ref, t)
-    assert abs(loss - N.loss(y_ref, t)) / N.loss(y_ref, t) < 3e-2
-    gd = lbnn.unflatten(g.double().cpu().numpy(), N.layer_shapes(c_in, WIDTHS, c_out))
-    worst = []
-    for name in names:
-        a, b = gd[name].reshape(-1), g_ref[name].reshape(-1)
-        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
-        rel = _rel(a, b)
-        worst.append((rel, cos, name))
-        assert cos > 0.99 and rel < 0.15, (name, cos, rel)
-    print("worst gradient", max(worst))
+    y_ref, _ = N.forward(p, x, operands="bf16")
+    assert _rel(y, y_ref) <= FWD_TOL, _rel(y, y_ref)
+    _check_gradients(net, p, names, x, t, td, c_in, c_out)
+
+
+def test_training_is_bitwise_reproducible():
+    """Every reduction runs in a fixed order (per-chunk partial sums, then a
+    second pass in chunk order): two trainings from one state give the same
+    parameters bit for bit."""
+    import torch
+    runs = []
+    for _ in range(2):
+        net, p, names, x, t, xd, td = _setup(40, 72, 3, 5, 5, seed=8)
+        losses = [net.train_step(xd, td, 1e-3) for _ in range(12)]
+        runs.append((losses, net.get_params().cpu().numpy()))
+        torch.cuda.synchronize()
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1])
 
 
 def test_training_reduces_loss():

@@ -80,3 +80,53 @@ def test_adam_matches_definition():
     N.adam_step(p, g, m, v, 1, 0.1)
     # first step of Adam moves every weight by -lr * sign(g)
     assert np.allclose(p["w"], [0.9, -1.9], atol=1e-7)
+
+
+def test_bf16_rounding_matches_torch():
+    """The oracle's BF16 rounding against torch's float32 -> bfloat16 cast
+    (round to nearest, ties to even) on random values and exact ties."""
+    import torch
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-6, 6, 20000),
+                        [0.0, 1.0, -1.0]]).astype(np.float32).astype(np.float64)
+    want = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(N.bf16_round(x), want)
+    # ties: 1 + 2^-8 lies halfway between 1 and 1 + 2^-7 (-> 1, even);
+    # 1 + 3 2^-8 between 1 + 2^-7 and 1 + 2^-6 (-> 1 + 2^-6, even)
+    ties = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -(1 + 2.0 ** -8), 3 * 2.0 ** -9 * 2 ** 5])
+    assert np.array_equal(N.bf16_round(ties), [1.0, 1 + 2.0 ** -6, -1.0, 3 * 2.0 ** -9 * 2 ** 5])
+
+
+def test_bf16_operand_mode_is_the_exact_network_on_rounded_operands():
+    """With every weight already a BF16 value and the input too, the BF16
+    mode differs from the exact mode only by the rounding of the stored
+    activations: same output to BF16 rounding level, same backward code."""
+    rng = np.random.default_rng(6)
+    p = N.init_params(SMALL["c_in"], 3, SMALL["widths"], SMALL["c_out"])
+    p = {k: N.bf16_round(v) if k.endswith(".W") and v.ndim == 3 else v for k, v in p.items()}
+    x = N.bf16_round(rng.standard_normal((2, 8, 16, SMALL["c_in"])))
+    t = rng.standard_normal((2, 8, 16, SMALL["c_out"]))
+    ye, ce = N.forward(p, x)
+    yb, cb = N.forward(p, x, operands="bf16")
+    rel = np.linalg.norm(yb - ye) / np.linalg.norm(ye)
+    assert 0 < rel < 2e-2
+    # stored activations of the BF16 mode are BF16 values
+    for name in ("e0", "e2", "d1"):
+        for a in cb[name][1:]:
+            assert np.array_equal(N.bf16_round(a), a)
+    # the backward pass is the exact one evaluated at the BF16 mode's state:
+    # replaying the exact backward on its cache gives the same gradients
+    gb = N.backward(p, cb, yb, t)
+    cb_exact = dict(cb)
+    cb_exact["operands"] = None
+    ge = N.backward(p, cb_exact, yb, t)
+    for k in gb:
+        assert np.array_equal(gb[k], ge[k])
+
+
+def test_softplus_against_logaddexp_and_its_derivative():
+    x = np.linspace(-40.0, 40.0, 4001)
+    assert np.allclose(N.softplus(x), np.logaddexp(0.0, x), rtol=1e-15, atol=1e-300)
+    # sigmoid(x) recovered from the output, against 1 / (1 + e^-x)
+    assert np.allclose(N.softplus_grad_from_output(N.softplus(x)), 1.0 / (1.0 + np.exp(-x)),
+                       rtol=1e-12, atol=0)
