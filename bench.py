@@ -418,6 +418,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="batch256")
     ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--tune-steps", type=int, default=16,
+                    help="time steps per autotuner trial (real steps: the state advances)")
     ap.add_argument("--launch", default="", help="tile_z,tile_r,grid,xcd,nt (skips autotune)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--kernel-steps", type=int, default=100,
@@ -465,8 +467,14 @@ def main():
         cfg = [int(x) for x in args.launch.split(",")]
         lat.set_launch(*cfg)
     elif args.autotune:
-        tuned = lat.autotune(steps_per_trial=max(4, min(50, args.warmup // 8)))
+        tuned = lat.autotune(steps_per_trial=args.tune_steps)
     launch = lat.get_launch()
+    # timed runs replay the step graph: its length fits inside the run, and
+    # its two instances (one per buffer parity) are built here, untimed
+    kg = max(2, min(64, (args.steps - 1) // 2 * 2))
+    lat.set_graph_steps(kg)
+    for _ in range(2):
+        lat.step(kg + 1)
     lat.step(args.warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)

@@ -134,7 +134,7 @@ static double inv_r(const orc_params* p, int j) {
 }
 /* Thread the row loops only when the lattice is big enough to pay for it. */
 static int par_ok(const orc_params* p) {
-  return (long)p->nz * (long)p->nr >= 16384;
+  return (long)p->nz * (long)p->nr >= 2048;
 }
 static int is_axis_row(const orc_params* p, int j) {
   return j == 0 && p->side[0].kind == ORC_AXIS;

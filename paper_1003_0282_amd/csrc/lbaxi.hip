@@ -1587,14 +1587,18 @@ lbaxi_status lbaxi_autotune(lbaxi_t* h, int32_t steps_per_trial, int32_t* cfg5_o
   };
   float best = 1e30f;
   int b[5] = {h->tz, h->tr, h->grid, h->xcd, h->nt};
-  for (const auto& sh : shapes) {
-    float ms;
-    if ((st = trial(sh[0], sh[1], 0, 0, 1, ms)) != LBAXI_OK) break;
-    if (ms < best) {
-      best = ms;
-      b[0] = sh[0]; b[1] = sh[1]; b[2] = 0; b[3] = 0; b[4] = 1;
+  // one workgroup per tile, dealt round-robin over the XCDs (xcd = 0) or in
+  // eight contiguous bands, one per XCD (xcd = 1: z-adjacent tiles, which
+  // share the cache lines at their common edge, then meet in one L2)
+  for (const auto& sh : shapes)
+    for (int xcd = 0; xcd < 2 && st == LBAXI_OK; ++xcd) {
+      float ms;
+      if ((st = trial(sh[0], sh[1], 0, xcd, 1, ms)) != LBAXI_OK) break;
+      if (ms < best) {
+        best = ms;
+        b[0] = sh[0]; b[1] = sh[1]; b[2] = 0; b[3] = xcd; b[4] = 1;
+      }
     }
-  }
   if (st == LBAXI_OK) {
     const int wg = b[0] * b[1];
     const int per_cu = std::max(1, 2048 / wg);

@@ -37,9 +37,10 @@ def test_warm_start_reaches_the_steady_field_sooner():
     print("reference status", r["reference"]["status"],
           "residual", ["%.2e" % x for x in r["reference"]["residual"]])
     # the paper's criterion, residual 1e-8: every melt that has a steady state
-    # (its FP64 reference run converges to 1e-10) gets there both ways; a
-    # melt whose flow never settles is excluded and counted (at most one here)
-    steady = [k for k in range(n) if r["reference"]["status"][k] == 1]
+    # (its FP64 reference run, aimed at 1e-10, gets below 1e-8) gets there both
+    # ways; a melt whose flow never settles is excluded and counted (at most
+    # one here)
+    steady = [k for k in range(n) if r["reference"]["residual"][k] <= 1e-8]
     assert len(steady) >= n - 1
     for tag in ("zero", "nn_smooth"):
         st = r["eval"][tag]["status"]
