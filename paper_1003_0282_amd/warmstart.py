@@ -152,7 +152,12 @@ def predict(net, X, sc: Scales, smooth=True) -> dict:
 
 
 def save_model(path, net, sc: Scales, meta: dict):
+    """Trained parameters (FP32 masters, flat), target scales and offsets,
+    and a JSON description of how the model was made (no pickled objects)."""
     p = net.get_params().cpu().numpy()
+    d = os.path.dirname(path)
+    if d:
+        os.makedirs(d, exist_ok=True)
     np.savez(path, params=p, scales=sc.s, offsets=sc.off, meta=json.dumps(meta))
 
 
@@ -206,19 +211,46 @@ def experiment(n_train=256, n_eval=16, nr=128, nz=256, re_max=1000.0, tol=1e-8,
                gen_budget_s=None, train_budget_s=None, eval_budget_s=None, check_every=1000,
                seed_train=2, seed_eval=1, tols=(1e-6, 3e-7, 1e-7, 3e-8, 1e-8),
                errs=(0.1, 0.03, 0.01, 0.003), out_dir=None, smooth_variants=(True,), wet=False,
-               ref_tol=1e-10, ref_steps=2_000_000, ref_budget_s=None, log=print):
+               ref_tol=1e-10, ref_steps=2_000_000, ref_budget_s=None, log=print,
+               load_model_path=None, save_model_path=None):
     """Generate steady training fields with the batched solver, train the
     network on them, then solve held-out cases from rest and from the
     prediction and compare the time to each residual tolerance and to each
     distance from reference steady fields (an FP64 run to ref_tol), and the
-    distance of each run's final field from that reference."""
+    distance of each run's final field from that reference.  With
+    load_model_path the generation and training are skipped (a model saved
+    by save_model_path is used); with n_eval = 0 the evaluation is."""
     import torch
     res = {"config": dict(n_train=n_train, n_eval=n_eval, nr=nr, nz=nz, re_max=re_max, tol=tol,
                           gen_steps=gen_steps, eval_steps=eval_steps, train_steps=train_steps,
                           batch=batch, lr=lr, check_every=check_every, seed_train=seed_train,
-                          seed_eval=seed_eval, wet=wet)}
+                          seed_eval=seed_eval, wet=wet, model=load_model_path)}
+    ev = W.melt_set(n_eval, seed_eval, nr=nr, nz=nz, re_max=re_max, wet=wet) if n_eval else []
+    if load_model_path:
+        net, sc, meta = load_model(load_model_path, max_batch=batch)
+        assert (meta["nr"], meta["nz"]) == (nr, nz), "model trained on another lattice size"
+        res["train"] = dict(meta.get("train", {}), loaded_from=load_model_path)
+        res["generate"] = meta.get("generate", {})
+    else:
+        net, sc = _generate_and_train(res, n_train, nr, nz, re_max, tol, gen_steps, train_steps,
+                                      batch, lr, gen_budget_s, train_budget_s, check_every,
+                                      seed_train, wet, log)
+        if save_model_path:
+            save_model(save_model_path, net, sc,
+                       dict(nr=nr, nz=nz, re_max=re_max, wet=wet, seed_train=seed_train,
+                            n_train=n_train, tol=tol, train=res["train"],
+                            generate=res["generate"]))
+    if not n_eval:
+        return res
+    return _evaluate(res, net, sc, ev, nr, nz, tol, eval_steps, check_every, eval_budget_s,
+                     tols, errs, smooth_variants, ref_tol, ref_steps, ref_budget_s, out_dir, log,
+                     re_max)
+
+
+def _generate_and_train(res, n_train, nr, nz, re_max, tol, gen_steps, train_steps, batch, lr,
+                        gen_budget_s, train_budget_s, check_every, seed_train, wet, log):
+    import torch
     tr = W.melt_set(n_train, seed_train, nr=nr, nz=nz, re_max=re_max, wet=wet)
-    ev = W.melt_set(n_eval, seed_eval, nr=nr, nz=nz, re_max=re_max, wet=wet)
     rho0, T_ref = tr[0]["rho0"], tr[0]["T_ref"]
 
     g = solve(tr, tol=tol, max_steps=gen_steps, check_every=check_every, budget_s=gen_budget_s,
@@ -247,6 +279,13 @@ def experiment(n_train=256, n_eval=16, nr=128, nz=256, re_max=1000.0, tol=1e-8,
                         loss_first=losses[0], loss_last=float(np.mean(losses[-20:])),
                         params=net.nparam, scales=sc.s.tolist())
     del X, Y
+    return net, sc
+
+
+def _evaluate(res, net, sc, ev, nr, nz, tol, eval_steps, check_every, eval_budget_s, tols, errs,
+              smooth_variants, ref_tol, ref_steps, ref_budget_s, out_dir, log, re_max):
+    import torch
+    n_eval = len(ev)
 
     # reference steady fields: FP64 from rest to a residual far below tol
     ref_run = solve(ev, tol=ref_tol, max_steps=ref_steps, check_every=check_every,
@@ -316,16 +355,24 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--variants", default="smooth", help="comma list of smooth,raw")
     ap.add_argument("--wet", action="store_true", help="wet-node walls (the paper's treatment)")
+    ap.add_argument("--save-model", default=None, help="write the trained model (.npz) here")
+    ap.add_argument("--load-model", default=None,
+                    help="skip generation and training: evaluate this saved model")
     a = ap.parse_args(argv)
     variants = tuple(v == "smooth" for v in a.variants.split(","))
     r = experiment(a.n_train, a.n_eval, a.nr, a.nz, a.re_max, a.tol, a.gen_steps, a.eval_steps,
                    a.train_steps, a.batch, a.lr, a.gen_budget, a.train_budget, a.eval_budget,
                    check_every=a.check_every, out_dir=a.out, smooth_variants=variants, wet=a.wet,
                    ref_tol=a.ref_tol, ref_steps=a.ref_steps, ref_budget_s=a.ref_budget,
-                   log=lambda s: print(s, flush=True))
+                   log=lambda s: print(s, flush=True), load_model_path=a.load_model,
+                   save_model_path=a.save_model)
     print(json.dumps({k: r[k] for k in ("generate", "train")}))
+    if a.out and "eval" not in r:
+        os.makedirs(a.out, exist_ok=True)
+        with open(os.path.join(a.out, "train_%dx%d.json" % (a.nz, a.nr)), "w") as f:
+            json.dump(r, f, indent=1)
     for tag in ("nn_smooth", "nn_raw"):
-        if tag not in r["eval"]:
+        if tag not in r.get("eval", {}):
             continue
         e = r["eval"][tag]
         print(tag, "prediction error median %.3f" % float(np.median(e["prediction_error"])),
