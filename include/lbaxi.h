@@ -212,6 +212,15 @@ lbaxi_status lbaxi_macros(lbaxi_t* h, void* d_rho, void* d_uz, void* d_ur, void*
  * LBAXI_ESTATE when no step has been taken since seeding or loading. */
 lbaxi_status lbaxi_residual(lbaxi_t* h, double* host_res);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid it): lbaxi_residual with its
+ * per-lattice reduction words in a fixed array of the library's device memory
+ * (64 KiB per GPU, held until the process ends) instead of the handle's
+ * workspace.  Same results and statuses as lbaxi_residual; EINVAL for a handle
+ * of more than 8192 lattices.  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (other host threads, other streams) race. */
+lbaxi_status lbaxi_residual_static(lbaxi_t* h, double* host_res);
+
 /* Current time level of lattice k. */
 lbaxi_status lbaxi_time(const lbaxi_t* h, int32_t k, int64_t* t);
 

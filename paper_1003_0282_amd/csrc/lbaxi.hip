@@ -22,6 +22,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -665,6 +666,13 @@ __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src,
   if (k < n) __builtin_nontemporal_store(src[k], dst + k);
 }
 
+// Residual words of lbaxi_residual_static: a fixed array in device memory
+// (one copy per GPU the library runs on, held until the process ends), for
+// callers that cannot allocate.  Host code reaches it only through the device
+// address hipGetSymbolAddress returns for the current device.
+constexpr int STATIC_RESIDUAL_MAX = 8192;  // lattices per handle
+static __device__ __align__(256) unsigned long long scratch[STATIC_RESIDUAL_MAX];
+
 // ============================================================================
 // host runtime
 // ============================================================================
@@ -1269,18 +1277,21 @@ lbaxi_status run_steps(lbaxi_t* h, long long n) {
   return LBAXI_OK;
 }
 
-// Residual words of every lattice (Eq. 57), as doubles on the host.
-lbaxi_status residuals(lbaxi_t* h, std::vector<double>& out) {
+// Residual words of every lattice (Eq. 57) reduced into `words` (device
+// memory, one 64-bit word per lattice) and copied to out[n] on the host.
+// A word holds the bit pattern of a non-negative double (see key), so the
+// copy is the residual itself.
+lbaxi_status residuals_into(lbaxi_t* h, unsigned long long* words, double* out) {
   lbaxi_status st;
   if ((st = upload_dyn(h)) != LBAXI_OK) return st;
-  hipLaunchKernelGGL(k_fill_u64, dim3((h->n + 255) / 256), dim3(256), 0, h->stream, h->d_res,
-                     h->n, 0ULL);
+  hipLaunchKernelGGL(k_fill_u64, dim3((h->n + 255) / 256), dim3(256), 0, h->stream, words, h->n,
+                     0ULL);
   HIPCHK(hipGetLastError());
   void* fn = PICK(resid_fn, h->prec, h->fields);
   const void* A = h->bufA;
   const void* B = h->bufB;
   const void* S = h->spd;
-  unsigned long long* r = h->d_res;
+  unsigned long long* r = words;
   const InstP* ip = h->d_ip;
   const InstDyn* dy = h->d_dyn;
   const Tile* tl = h->d_tiles[LIST_ALL];
@@ -1291,16 +1302,39 @@ lbaxi_status residuals(lbaxi_t* h, std::vector<double>& out) {
   void* args[] = {&ip, &dy, &tl, &nt, &A, &B, &S, &r, &tzlog, &tile_nodes, &lag};
   HIPCHK(hipLaunchKernel(fn, dim3(std::max(1, h->count[LIST_ALL])),
                          dim3(std::min(256, tile_nodes)), args, 0, h->stream));
-  std::vector<unsigned long long> bits(h->n);
-  HIPCHK(hipMemcpyAsync(bits.data(), h->d_res, sizeof(unsigned long long) * h->n,
-                        hipMemcpyDeviceToHost, h->stream));
+  static_assert(sizeof(double) == sizeof(unsigned long long), "residual words are doubles");
+  HIPCHK(hipMemcpyAsync(out, words, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
+  return LBAXI_OK;
+}
+
+lbaxi_status residuals(lbaxi_t* h, std::vector<double>& out) {
   out.resize(h->n);
-  for (int k = 0; k < h->n; ++k) {
-    double v;
-    memcpy(&v, &bits[k], sizeof v);
-    out[k] = v;
+  return residuals_into(h, h->d_res, out.data());
+}
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned long long*> g_scratch_ptr;
+
+// Device address of `scratch` on device dev (looked up once per device, with
+// that device current).
+lbaxi_status scratch_words(int dev, unsigned long long** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return LBAXI_OK;
   }
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != dev) HIPCHK(hipSetDevice(dev));
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (cur != dev) HIPCHK(hipSetDevice(cur));
+  if (e != hipSuccess || !ptr)
+    return fail(LBAXI_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[dev] = static_cast<unsigned long long*>(ptr);
+  *out = static_cast<unsigned long long*>(ptr);
   return LBAXI_OK;
 }
 
@@ -1532,6 +1566,23 @@ lbaxi_status lbaxi_residual(lbaxi_t* h, double* host_res) {
     host_res[k] = r[k];
     if (!std::isfinite(r[k])) bad = true;
   }
+  return bad ? fail(LBAXI_EDIVERGED, "NaN or Inf in some lattice") : LBAXI_OK;
+}
+
+lbaxi_status lbaxi_residual_static(lbaxi_t* h, double* host_res) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  if (!host_res) return fail(LBAXI_EINVAL, "NULL host_res");
+  if (h->n > STATIC_RESIDUAL_MAX)
+    return fail(LBAXI_EINVAL, "lbaxi_residual_static serves handles of at most 8192 lattices");
+  for (int k = 0; k < h->n; ++k)
+    if (!h->inst_spd[k]) return fail(LBAXI_ESTATE, "no step since seeding or loading");
+  unsigned long long* words = nullptr;
+  if ((st = scratch_words(h->device, &words)) != LBAXI_OK) return st;
+  if ((st = residuals_into(h, words, host_res)) != LBAXI_OK) return st;
+  bool bad = false;
+  for (int k = 0; k < h->n; ++k)
+    if (!std::isfinite(host_res[k])) bad = true;
   return bad ? fail(LBAXI_EDIVERGED, "NaN or Inf in some lattice") : LBAXI_OK;
 }
 

@@ -62,6 +62,7 @@ _sigs = {
     "lbaxi_step": (_st, [_P, C.c_int64]),
     "lbaxi_macros": (_st, [_P, _P, _P, _P, _P, _P]),
     "lbaxi_residual": (_st, [_P, C.POINTER(C.c_double)]),
+    "lbaxi_residual_static": (_st, [_P, C.POINTER(C.c_double)]),
     "lbaxi_time": (_st, [_P, C.c_int32, C.POINTER(C.c_int64)]),
     "lbaxi_batch_run": (_st, [_P, C.c_double, C.c_int64, C.c_int64, C.POINTER(C.c_int32),
                               C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
@@ -251,6 +252,16 @@ class Lattices:
         if st == -5 and not raise_on_nan:
             return np.array(out[:])
         _check(st, "lbaxi_residual")
+        return np.array(out[:])
+
+    def residual_static(self, raise_on_nan: bool = False) -> np.ndarray:
+        """lbaxi_residual_static: the residual with the library's fixed
+        reduction words (no workspace use)."""
+        out = (C.c_double * self.n)()
+        st = _L.lbaxi_residual_static(self.h, out)
+        if st == -5 and not raise_on_nan:
+            return np.array(out[:])
+        _check(st, "lbaxi_residual_static")
         return np.array(out[:])
 
     def time(self, k: int = 0) -> int:
