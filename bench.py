@@ -114,10 +114,8 @@ def traffic_entry(name: str, launch: str):
     return None
 
 
-def cpu_baseline(cases, seconds: float):
-    """The oracle, as it stands, on a bounded sample of the same workload."""
+def _oracle_sample(cases, seconds: float):
     from oracle import oracle as O
-    O.build()
     done = 0
     used = []
     t0 = time.perf_counter()
@@ -127,7 +125,6 @@ def cpu_baseline(cases, seconds: float):
         o = O.Oracle(c)
         o.seed()
         steps = 0
-        t1 = time.perf_counter()
         while steps < 200 and time.perf_counter() - t0 < seconds:
             o.step(5)
             steps += 5
@@ -136,10 +133,27 @@ def cpu_baseline(cases, seconds: float):
         del o
         k += 1
     el = time.perf_counter() - t0
-    return {"value": done / el / 1e6, "unit": "MLUPS", "cores": O.get_threads(),
+    return done, el, k, used
+
+
+def cpu_baseline(cases, seconds: float):
+    """The oracle, as it stands, on a bounded sample of the same workload: on
+    every host core it is given, and on one core for a third of the time."""
+    from oracle import oracle as O
+    O.build()
+    cores = O.get_threads()
+    done, el, k, used = _oracle_sample(cases, seconds)
+    O.set_threads(1)
+    try:
+        done1, el1, k1, _ = _oracle_sample(cases, seconds / 3.0)
+    finally:
+        O.set_threads(cores)
+    return {"value": done / el / 1e6, "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": "%d of %d lattices, %d node updates in %.1f s (%s)" % (
-                k, len(cases), done, el, "; ".join(used[:4]) + (" ..." if len(used) > 4 else ""))}
+                k, len(cases), done, el, "; ".join(used[:4]) + (" ..." if len(used) > 4 else "")),
+            "single_core": {"value": done1 / el1 / 1e6, "unit": "MLUPS", "cores": 1,
+                            "sample": "%d lattices, %d node updates in %.1f s" % (k1, done1, el1)}}
 
 
 def copy_probe(steps: int, warmup: int, nbytes: int = 4 << 30):
@@ -241,6 +255,46 @@ def warmstart_probe():
         "both_reached_1e-8": d8["reached_both"],
         "pipeline_wall_s": round(time.perf_counter() - t0, 1),
     }
+
+
+MODEL = os.path.join(ROOT, "paper_1003_0282_amd", "models", "melt_unet_128x256.npz")
+
+
+def time_to_steady_leg(n_melts: int, tol: float = 1e-8):
+    """The second half of the metric: wall time until every one of n_melts
+    held-out crystal / crucible melts (128 x 256, wet-node walls, FP32
+    storage, seed 1) reaches the Eq. (57) residual tol, from rest and from the
+    learned warm start (the committed network, trained by the library's own
+    kernels on 4096 steady fields the batched solver generated; inference and
+    seeding are inside the warm start's time), in one batched handle each."""
+    import numpy as np
+    import torch
+    from paper_1003_0282_amd import lbaxi as L
+    from paper_1003_0282_amd import warmstart as WS
+    from paper_1003_0282_amd import workloads as W
+    from paper_1003_0282_amd.steady import solve
+    cases = W.melt_set(n_melts, 1, nr=128, nz=256, wet=True)
+    net, sc, meta = WS.load_model(MODEL, max_batch=8)
+    z = solve(cases, tol=tol, max_steps=3_000_000, check_every=1000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X = torch.tensor(WS.features(cases), device="cuda")
+    init = WS.predict(net, X, sc, smooth=True)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    w = solve(cases, init=init, tol=tol, max_steps=3_000_000, check_every=1000)
+    net.close()
+    shape = (n_melts, 128, 256)
+    diff = WS.rel_field_error(w.fields, z.fields, shape)
+    ok = lambda r: int((r.status == L.CONVERGED).sum())
+    return {"workload": "melt_128x256_wet_x%d" % n_melts, "tol": tol,
+            "from_rest_s": round(z.wall_s, 3), "warm_start_s": round(w.wall_s + t_inf, 3),
+            "inference_s": round(t_inf, 4), "speedup": round(z.wall_s / (w.wall_s + t_inf), 3),
+            "steps_median_from_rest": float(np.median(z.steps)),
+            "steps_median_warm": float(np.median(w.steps)),
+            "converged_from_rest": ok(z), "converged_warm": ok(w), "lattices": n_melts,
+            "end_state_difference_median": float(np.median(diff)),
+            "model": "trained on %d solver-generated fields (seed 2)" % meta.get("n_train", 0)}
 
 
 def wheeler_probe():
@@ -426,6 +480,8 @@ def main():
                     help="time steps per autotuner trial (real steps: the state advances)")
     ap.add_argument("--launch", default="", help="tile_z,tile_r,grid,xcd,nt (skips autotune)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--tts-melts", type=int, default=16,
+                    help="melts of the time-to-steady leg of the default line (0: skip)")
     ap.add_argument("--kernel-steps", type=int, default=100,
                     help="steps timed kernel by kernel for the roofline figure")
     ap.add_argument("--max-steps", type=int, default=0,
@@ -494,14 +550,8 @@ def main():
     nodes = lat.nodes
     mlups = nodes * args.steps / (ms / 1e3) / 1e6
     bpu = bytes_per_update(cases[0], prec)
-    # the step kernel updates rows 1 .. nr - 2 (without the end columns when
-    # those are wet-node walls); rows 0 and nr - 1 go to k_edge
-    def _interior(c):
-        wet_ends = c.get("wet") and c["west"]["kind"] != "periodic"
-        return (c["nz"] - (2 if wet_ends else 0)) * max(0, c["nr"] - 2)
-    interior = sum(_interior(c) for c in cases)
-    algo = bpu * interior  # bytes per launch of the step kernel
-    algo_step = bpu * nodes  # bytes per time step (both kernels)
+    algo = bpu * nodes  # bytes per launch of the step kernel (one per time step)
+    algo_step = algo
     step_gbs = algo_step / (ms_step / 1e3) / 1e9
     # the step kernel's own duration: HIP events around each of its launches
     # on the handle's stream, over a second stretch of real steps
@@ -538,12 +588,15 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": tr,
-                     "kernel": "k_step (fused pull-stream + collide, interior nodes)",
+                     "kernel": "k_step (fused pull-stream + collide)",
                      "kernel_avg_ms": round(k_avg_ms, 5), "kernel_launches_timed": k_n,
-                     "algorithmic_bytes_per_launch": algo, "interior_nodes": interior,
+                     "algorithmic_bytes_per_launch": algo,
                      "whole_step_gbs": round(step_gbs, 1)},
         "lattices_finite": n_finite,
     }
+    if args.workload == "batch256" and args.tts_melts > 0:
+        lat.close()
+        out["time_to_steady"] = time_to_steady_leg(args.tts_melts)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(cases, args.cpu_seconds)
     print(json.dumps(out))

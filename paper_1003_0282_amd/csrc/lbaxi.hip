@@ -6,13 +6,9 @@
 // computes the macros of Eqs. (16)-(17), collides f with Eqs. (12)-(13) (or
 // the MRT model of Sec. III B, or, for comparison, the original scheme of
 // Sec. II) and g, h with Eqs. (53)-(54), and writes its populations to the
-// other buffer at its own address.  Interior nodes (every upstream node
-// inside the lattice) are done by a lean kernel with a plain pull; the
-// perimeter nodes by a second one that applies the link rules of the sides
-// while pulling and rebuilds wet-node wall nodes.  Both read only the
-// previous step's buffer and write disjoint nodes, so the two launches of a
-// step are independent of each other.  Work is described by tile tables
-// {instance, z0, r0} so that hundreds of uneven lattices share one
+// other buffer at its own address.  Wet-node walls are rebuilt by a second
+// kernel and ghost slots filled by a third.  Work is described by a tile
+// table {instance, z0, r0} so that hundreds of uneven lattices share one
 // (optionally persistent) launch; runs are replayed from HIP graphs of K
 // steps.
 #include <hip/hip_runtime.h>
@@ -84,7 +80,6 @@ struct StepArgs {
   const S* lag_src;
   S* lag_dst;
   long long lag_stride;
-  const ZEnd* zt;  // z-end rules: [lattice][end][segment]
 };
 
 // The two lagged velocity buffers of the original scheme, for the macro and
@@ -108,20 +103,20 @@ __device__ inline void st(S* p, S v, int nt) {
 // (Sec. IV B), computed before the node's own pull so that the two
 // population sets are never live together.
 template <typename S, typename R, int F>
-__device__ inline void pull_plain(const InstP& P, const InstP* Pg, const PR<R>& p, const S* s,
-                                  int i, int j, bool pre, R* f, R* g, R* h, bool axis_g = true) {
+__device__ inline void pull_plain(const InstP& P, const PR<R>& p, const S* s, int i, int j,
+                                  bool pre, R* f, R* g, R* h, bool axis_g = true) {
   const bool axis_row = axis_g && (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
   R gn[4];
   if ((F & F_SWIRL) && axis_row) {
     R f1[9], g1[4], h1[4];
-    load_node<S, R, F>(P, Pg, s, i, 1, pre, f1, g1, h1);
+    load_node<S, R, F>(P, s, i, 1, pre, f1, g1, h1);
     const Mac<R> m1 = macros<R, F>(p, make_row<R, F>(p, 1), false, f1, g1, h1);
     const R q = (R)0.25 * p.rho0 * m1.uth;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
       gn[a] = g1[a] - q * ((R)1 + (R)2 * ((R)ez4(a) * m1.uz + (R)er4(a) * m1.ur));
   }
-  load_node<S, R, F>(P, Pg, s, i, j, pre, f, g, h);
+  load_node<S, R, F>(P, s, i, j, pre, f, g, h);
   if ((F & F_SWIRL) && axis_row) {
 #pragma unroll
     for (int a = 0; a < 4; ++a) g[a] = gn[a];
@@ -229,102 +224,69 @@ __device__ inline void zou_he(const PR<R>& p, const Row<R>& rb, R uzw, R Gz, R G
   f[DM] = (R)0.5 * (Ud - dn - Dz);
 }
 
-// Wall values of wet wall node b (row constants rb) given the macros m of
-// its inner neighbour and the mass s0d b streamed in (deviation from rho0).
-template <typename R>
-struct WallVals {
-  R uzw, urw, uthw, dTw, drhob, rhob, Fzb, Frb;
-};
-
-template <typename R, int F>
-__device__ inline WallVals<R> wall_values(const InstP& P, const PR<R>& p, const Row<R>& rb, int j,
-                                          const WetRule& w, R s0d, const Mac<R>& m,
-                                          bool axis_b) {
-  WallVals<R> v;
-  v.uzw = w.free_ ? (R)0 : (R)w.uz;
-  v.urw = w.free_ ? m.ur : (R)w.ur;
-  v.uthw = w.free_ ? m.uth : (R)(w.omega * (P.r0 + (double)j));
-  if (axis_b) v.uthw = (R)0;
-  v.dTw = (w.thermal && !w.free_) ? (R)(w.T - P.T_ref) : m.dT;
-  const R x = (R)0.5 * v.urw * rb.ir;
-  v.drhob = (s0d - p.rho0 * x) * rcp((R)1 + x);
-  v.rhob = p.rho0 + v.drhob;
-  v.Fzb = p.a_t;
-  if (F & F_THERMAL) v.Fzb += p.rho0 * p.gbeta * v.dTw;
-  v.Frb = -(R)2 * p.mu0 * v.urw * rb.ir2;
-  if (F & F_SWIRL) v.Frb += p.rho0 * v.uthw * v.uthw * rb.ir;
-  return v;
-}
-
-// Extrapolation of f: on entry f holds the neighbour's pulled populations
-// (row constants rn, macros m), on exit b's: f + E(b) - E(n).
-template <typename R, int F>
-__device__ inline void extrapolate_f(const Row<R>& rb, const Row<R>& rn, const WallVals<R>& v,
-                                     const Mac<R>& m, R* f) {
-#pragma unroll
-  for (int a = 0; a < 9; ++a)
-    f[a] = f[a] + eq_hat<R, F>(a, v.drhob, v.rhob, v.uzw, v.urw, v.Fzb, v.Frb, rb.ir) -
-           eq_hat<R, F>(a, m.drho, m.rho, m.uz, m.ur, m.Fz, m.Fr, rn.ir);
-}
-
-// The same for g and h (in place): g + g_eq(b) - g_eq(n), h likewise.
-template <typename R, int F>
-__device__ inline void extrapolate_gh(const PR<R>& p, const WallVals<R>& v, const Mac<R>& m, R* g,
-                                      R* h) {
-  if (F & F_SWIRL) {
-    const R qb = (R)0.25 * p.rho0 * v.uthw, qn = (R)0.25 * p.rho0 * m.uth;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const R ez = (R)ez4(a), er = (R)er4(a);
-      g[a] = g[a] + qb * ((R)1 + (R)2 * (ez * v.uzw + er * v.urw)) -
-             qn * ((R)1 + (R)2 * (ez * m.uz + er * m.ur));
-    }
-  }
-  if (F & F_THERMAL) {
-    const R Tb = p.T_ref + v.dTw, Tn = p.T_ref + m.dT;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const R ez = (R)ez4(a), er = (R)er4(a);
-      h[a] = h[a] + (R)0.25 * (Tb * ((R)1 + (R)2 * (ez * v.uzw + er * v.urw)) -
-                               Tn * ((R)1 + (R)2 * (ez * m.uz + er * m.ur)));
-    }
-  }
-}
-
 template <typename S, typename R, int F>
-__device__ inline void wall_state(const InstP& P, const InstP* Pg, const PR<R>& p, const S* s,
-                                  int i, int j, const WetRule& w, R* f, R* g, R* h) {
+__device__ inline void wall_state(const InstP& P, const PR<R>& p, const S* s, int i, int j,
+                                  const WetRule& w, R* f, R* g, R* h) {
   R s0d;
   {
     R fo[9], go[4], ho[4];
-    load_node<S, R, F>(P, Pg, s, i, j, false, fo, go, ho);
+    load_node<S, R, F>(P, s, i, j, false, fo, go, ho);
     s0d = ((fo[0] + fo[1]) + (fo[2] + fo[3])) + ((fo[4] + fo[5]) + (fo[6] + fo[7])) + fo[8];
   }
-  R fn[9];
-  pull_plain<S, R, F>(P, Pg, p, s, w.in, w.jn, false, fn, g, h);
+  R fn[9], gn[4], hn[4];
+  pull_plain<S, R, F>(P, p, s, w.in, w.jn, false, fn, gn, hn);
   const bool axis_n = (w.jn == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
   const bool axis_b = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
   const Row<R> rn = make_row<R, F>(p, w.jn);
   const Row<R> rb = make_row<R, F>(p, j);
-  const Mac<R> m = macros<R, F>(p, rn, axis_n, fn, g, h);
-  const WallVals<R> v = wall_values<R, F>(P, p, rb, j, w, s0d, m, axis_b);
+  const Mac<R> m = macros<R, F>(p, rn, axis_n, fn, gn, hn);
+  const R uzw = w.free_ ? (R)0 : (R)w.uz;
+  const R urw = w.free_ ? m.ur : (R)w.ur;
+  R uthw = w.free_ ? m.uth : (R)(w.omega * (P.r0 + (double)j));
+  if (axis_b) uthw = (R)0;
+  const R dTw = (w.thermal && !w.free_) ? (R)(w.T - P.T_ref) : m.dT;
+  const R x = (R)0.5 * urw * rb.ir;
+  const R drhob = (s0d - p.rho0 * x) * rcp((R)1 + x);
+  const R rhob = p.rho0 + drhob;
+  R Fzb = p.a_t;
+  if (F & F_THERMAL) Fzb += p.rho0 * p.gbeta * dTw;
+  R Frb = -(R)2 * p.mu0 * urw * rb.ir2;
+  if (F & F_SWIRL) Frb += p.rho0 * uthw * uthw * rb.ir;
   const bool zou = P.zou && w.in == i && w.jn != j;  // Zou-He on a radial wall
   if (zou) {
     // corners and z-ends keep the extrapolation, g and h too; the node's own
     // streamed-in populations are loaded into f and completed in place
     R gd[4], hd[4];
-    load_node<S, R, F>(P, Pg, s, i, j, false, f, gd, hd);
-    const R Gr = (F & F_SWIRL) ? p.rho0 * v.uthw * v.uthw * rb.ir : (R)0;
+    load_node<S, R, F>(P, s, i, j, false, f, gd, hd);
+    const R Gr = (F & F_SWIRL) ? p.rho0 * uthw * uthw * rb.ir : (R)0;
     if (w.jn < j)
-      zou_he<R, F, -1>(p, rb, v.uzw, v.Fzb, Gr, f);
+      zou_he<R, F, -1>(p, rb, uzw, Fzb, Gr, f);
     else
-      zou_he<R, F, 1>(p, rb, v.uzw, v.Fzb, Gr, f);
+      zou_he<R, F, 1>(p, rb, uzw, Fzb, Gr, f);
   } else {
 #pragma unroll
-    for (int a = 0; a < 9; ++a) f[a] = fn[a];
-    extrapolate_f<R, F>(rb, rn, v, m, f);
+    for (int a = 0; a < 9; ++a)
+      f[a] = fn[a] + eq_hat<R, F>(a, drhob, rhob, uzw, urw, Fzb, Frb, rb.ir) -
+             eq_hat<R, F>(a, m.drho, m.rho, m.uz, m.ur, m.Fz, m.Fr, rn.ir);
   }
-  extrapolate_gh<R, F>(p, v, m, g, h);
+  if (F & F_SWIRL) {
+    const R qb = (R)0.25 * p.rho0 * uthw, qn = (R)0.25 * p.rho0 * m.uth;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const R ez = (R)ez4(a), er = (R)er4(a);
+      g[a] = gn[a] + qb * ((R)1 + (R)2 * (ez * uzw + er * urw)) -
+             qn * ((R)1 + (R)2 * (ez * m.uz + er * m.ur));
+    }
+  }
+  if (F & F_THERMAL) {
+    const R Tb = p.T_ref + dTw, Tn = p.T_ref + m.dT;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const R ez = (R)ez4(a), er = (R)er4(a);
+      h[a] = hn[a] + (R)0.25 * (Tb * ((R)1 + (R)2 * (ez * uzw + er * urw)) -
+                                Tn * ((R)1 + (R)2 * (ez * m.uz + er * m.ur)));
+    }
+  }
 }
 
 // Macros, collision and store of one pulled node.
@@ -365,20 +327,22 @@ __device__ inline void finish_node(const StepArgs<S>& A, const InstP& P, const P
     A.spd[P.off_fld + (long long)j * P.nz + i] = (double)sqrt(m.uz * m.uz + m.ur * m.ur);
 }
 
-// Whether the end columns of a lattice are wet-node wall nodes (rebuilt by
-// k_edge).  Otherwise the step kernel updates them with the rows they lie in,
-// so that every row of rows 1 .. nr - 2 is stored by one wave (a cache line
-// written in part by two kernels costs HBM far more than a whole one); an
-// end-column node takes what crosses its z-end from the lattice's z-end rule
-// table (zend_pull).
-__host__ __device__ inline bool wet_ends(int wet, int west_kind) {
-  return wet && west_kind != SIDE_PERIODIC;
+// Boundary node number p of a lattice: row 0, row nr-1, then columns 0 and
+// nz-1 without their corners.
+__device__ inline void perimeter_node(const InstP& P, int p, int& i, int& j) {
+  const int nz = P.nz, nr = P.nr;
+  if (p < nz) { i = p; j = 0; return; }
+  p -= nz;
+  if (p < nz) { i = p; j = nr - 1; return; }
+  p -= nz;
+  if (p < nr - 2) { i = 0; j = 1 + p; return; }
+  p -= nr - 2;
+  i = nz - 1; j = 1 + p;
 }
 
-// One time step of rows 1 .. nr - 2: plain pull through the padded planes
-// (an end-column node then replaces what crossed its z-end by the z-end
-// rules), macros, collision, store at the node's own slots of the other
-// buffer.  Rows 0 and nr - 1, and wet-node wall columns, are left to k_edge.
+// One time step: pull (padded planes, no boundary tests), macros, collision,
+// store at the node's own slots of the other buffer.  The halo kernel then
+// completes the boundary rules for the next pull.
 template <typename S, typename R, int F>
 __global__ void __launch_bounds__(1024) k_step(StepArgs<S> A) {
   const long long t = A.tdev ? (*A.tdev + A.k) : A.t0;
@@ -391,61 +355,56 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs<S> A) {
     const Tile T = cload(A.tiles + ti);
     const InstP P = cload(A.ip + T.inst);
     const int i = T.z0 + li, j = T.r0 + lj;
-    if (i >= P.nz || j >= P.nr - 1) continue;
-    const bool end = i == 0 || i == P.nz - 1;
-    if (end && wet_ends(P.wet, P.side[WEST].kind)) continue;
+    if (i >= P.nz || j >= P.nr) continue;
+    // wet wall nodes are rebuilt by k_wall, except on the first step after
+    // seeding, where they collide their seeded state like any node
+    const bool wall = P.wet && wet_rule(P, nullptr, i, j, nullptr);
+    if (wall && !pre) continue;
     const PR<R> p = make_pr<R>(P, t);
     R f[9], g[4], h[4];
-    plain_pull<S, R, F>(P, A.src + P.off, i, j, pre, f, g, h);
-    if (end && !pre) {
-      const bool west = i == 0;
-      const double rs = west ? P.side[WEST].r_split : P.side[EAST].r_split;
-      const int seg = (rs >= 0.0 && P.r0 + (double)j > rs) ? 1 : 0;
-      const ZEnd* Z = A.zt + (((long long)T.inst * 2 + (west ? 0 : 1)) * 2 + seg);
-      zend_pull<S, R, F>(A.src + P.off, Z, west, nidx(P, j, i), j, f, g, h);
-    }
+    pull_plain<S, R, F>(P, p, A.src + P.off, i, j, pre, f, g, h, !wall);
     finish_node<S, R, F>(A, P, p, i, j, f, g, h);
   }
 }
 
-// The same time step for rows 0 and nr - 1 and for wet-node wall columns
-// (one thread per node; tiles are {instance, first node, part}: part 0 is
-// row 0 and part 1 row nr - 1 from node z0 on, part 2 the end columns
-// without their corners from column node z0 on).  The pull takes the link
-// rules of the sides for what crosses them (from the post-collision values
-// of the source buffer), an axis row takes the extrapolated swirl
-// populations, and a wet-node wall node is rebuilt from its inner neighbour
-// (wall_state) -- except on the first step after seeding, where it collides
-// its seeded state like any node.
+// Wet wall nodes of every running lattice after a streaming step (one
+// thread per perimeter node, tiles of the halo list): rebuild from the inner
+// neighbour, then macros, collision and store like k_step.  Reads the same
+// source buffer as k_step and writes other nodes of the same destination.
 template <typename S, typename R, int F>
-__global__ void __launch_bounds__(256) k_edge(StepArgs<S> A) {
+__global__ void __launch_bounds__(256) k_wall(StepArgs<S> A) {
   const int ti = blockIdx.x;
   if (ti >= *A.ntiles) return;
   const Tile T = cload(A.tiles + ti);
   const InstP P = cload(A.ip + T.inst);
-  const InstP* Pg = A.ip + T.inst;
+  if (!P.wet) return;
   const int q = T.z0 + threadIdx.x;
+  if (q >= 2 * P.nz + 2 * (P.nr - 2)) return;
   int i, j;
-  if (T.r0 < 2) {
-    if (q >= P.nz) return;
-    i = q;
-    j = T.r0 ? P.nr - 1 : 0;
-  } else {
-    if (q >= 2 * (P.nr - 2)) return;
-    i = q < P.nr - 2 ? 0 : P.nz - 1;
-    j = 1 + (q < P.nr - 2 ? q : q - (P.nr - 2));
-  }
+  perimeter_node(P, q, i, j);
+  WetRule w;
+  if (!wet_rule(P, A.ip + T.inst, i, j, &w)) return;
   const long long t = A.tdev ? (*A.tdev + A.k) : A.t0;
-  const bool pre = A.mode & MODE_PRE;
   const PR<R> p = make_pr<R>(P, t);
   R f[9], g[4], h[4];
-  WetRule w;
-  const bool wall = P.wet && wet_rule(P, Pg, i, j, &w);
-  if (wall && !pre)
-    wall_state<S, R, F>(P, Pg, p, A.src + P.off, i, j, w, f, g, h);
-  else
-    pull_plain<S, R, F>(P, Pg, p, A.src + P.off, i, j, pre, f, g, h, !wall);
+  wall_state<S, R, F>(P, p, A.src + P.off, i, j, w, f, g, h);
   finish_node<S, R, F>(A, P, p, i, j, f, g, h);
+}
+
+// Ghost-slot fill after a step: tiles here are {instance, first perimeter
+// node, 0, 0}, one thread per perimeter node.
+template <typename S, int F>
+__global__ void __launch_bounds__(256) k_halo(const InstP* ip, const Tile* tiles,
+                                              const int* ntiles, S* buf) {
+  const int ti = blockIdx.x;
+  if (ti >= *ntiles) return;
+  const Tile T = cload(tiles + ti);
+  const InstP P = cload(ip + T.inst);
+  const int p = T.z0 + threadIdx.x;
+  if (p >= 2 * P.nz + 2 * (P.nr - 2)) return;
+  int i, j;
+  perimeter_node(P, p, i, j);
+  halo_fill<S, F>(P, ip + T.inst, buf + P.off, i, j);
 }
 
 // Equilibrium seeding: f^ = f_eq - S/2 (S of the collision model), g = g_eq,
@@ -551,7 +510,7 @@ __device__ inline Mac<R> node_macros(const InstP& P, const InstP* Pg, const Inst
   const S* s = (D.cur ? bufB : bufA) + P.off;
   R f[9], g[4], h[4];
   if (F & F_ORIG) {
-    load_node<S, R, F>(P, Pg, s, i, j, D.pre != 0, f, g, h);
+    load_node<S, R, F>(P, s, i, j, D.pre != 0, f, g, h);
     const Row<R> rw = make_row<R, F>(p, j);
     const S* lz = static_cast<const S*>(D.cur ? lag.B : lag.A) + P.off_fld;
     R Dr, Dz;
@@ -560,9 +519,9 @@ __device__ inline Mac<R> node_macros(const InstP& P, const InstP* Pg, const Inst
   }
   WetRule w;
   if (P.wet && !D.pre && wet_rule(P, Pg, i, j, &w))
-    wall_state<S, R, F>(P, Pg, p, s, i, j, w, f, g, h);
+    wall_state<S, R, F>(P, p, s, i, j, w, f, g, h);
   else
-    load_node<S, R, F>(P, Pg, s, i, j, D.pre != 0, f, g, h);
+    load_node<S, R, F>(P, s, i, j, D.pre != 0, f, g, h);
   const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
   // on the axis u_th = 0 and g does not enter the macros of Eqs. (16)-(17)
   return macros<R, F>(p, make_row<R, F>(p, j), axis_row, f, g, h);
@@ -708,42 +667,37 @@ long long max_tiles(const std::vector<lbaxi_desc>& d) {
   return n;
 }
 
-// Tiles of k_edge over a lattice: rows 0 and nr - 1 in chunks of 256 nodes
-// (so that each wave stores 64 aligned nodes of one row), and the end
-// columns when they are wet-node walls.
-void edge_list(const lbaxi_desc& x, int k, std::vector<Tile>* out, long long* count) {
+// Boundary nodes of a lattice and the halo workgroups (256 nodes) covering them.
+int perimeter(const lbaxi_desc& x) { return 2 * x.nz + 2 * (x.nr - 2); }
+long long halo_tiles(const std::vector<lbaxi_desc>& d) {
   long long n = 0;
-  for (int part = 0; part < 2; ++part)
-    for (int i0 = 0; i0 < x.nz; i0 += 256, ++n)
-      if (out) out->push_back(Tile{k, i0, part, 0});
-  if (wet_ends((x.fields & LBAXI_WET_WALLS) ? 1 : 0, x.west.kind))
-    for (int q0 = 0; q0 < 2 * (x.nr - 2); q0 += 256, ++n)
-      if (out) out->push_back(Tile{k, q0, 2, 0});
-  if (count) *count += n;
-}
-long long edge_tiles(const std::vector<lbaxi_desc>& d) {
-  long long n = 0;
-  for (int k = 0; k < (int)d.size(); ++k) edge_list(d[k], k, nullptr, &n);
+  for (const auto& x : d) n += (perimeter(x) + 255) / 256;
   return n;
 }
-
 // Padded rows: a 128-byte lead-in (node 0 starts a 128-byte line), nz
 // nodes and one spare slot, rounded up to 128 bytes; rows -1 and nr are the
-// ghost rows.
+// ghost rows.  After the nr + 2 rows come the ghost-column strips of the two
+// z-ends, nr + 2 slots each, rounded up to 128 bytes.
 int row_lead(const lbaxi_desc& x) { return 128 / (x.prec == LBAXI_FP64 ? 8 : 4); }
 int row_pitch(const lbaxi_desc& x) {
   const int q = row_lead(x);
   return (q + x.nz + 1 + q - 1) / q * q;
 }
-long long padded_plane(const lbaxi_desc& x) { return (long long)(x.nr + 2) * row_pitch(x); }
+int strip_len(const lbaxi_desc& x) {
+  const int q = row_lead(x);
+  return (x.nr + 2 + q - 1) / q * q;
+}
+long long padded_plane(const lbaxi_desc& x) {
+  return (long long)(x.nr + 2) * row_pitch(x) + 2LL * strip_len(x);
+}
 
-// Device workspace: parameters, three work lists (all tiles / interior
-// tiles and perimeter chunks of running lattices) with their counts,
+// Device workspace: parameters, three work lists (all tiles / tiles of
+// running lattices / halo chunks of running lattices) with their counts,
 // residual words, the time base, two padded population buffers and |u| of
 // Eq. (57).
 struct Layout {
-  size_t ip, dyn, zt, tiles_all, tiles_run, tiles_edge, counts, res, tdev, bufA, bufB, spd, lagA,
-      lagB, total;
+  size_t ip, dyn, tiles_all, tiles_run, tiles_halo, counts, res, tdev, bufA, bufB, spd, lagA, lagB,
+      total;
   long long lag_stride;  // elements between the u_z and u_r parts of a lagged buffer
   std::vector<long long> off, off_fld;
   long long buf_elems, fld_elems;
@@ -758,10 +712,9 @@ Layout layout(const std::vector<lbaxi_desc>& d) {
   size_t o = 0;
   L.ip = o; o = align_up(o + sizeof(InstP) * n, 256);
   L.dyn = o; o = align_up(o + sizeof(InstDyn) * n, 256);
-  L.zt = o; o = align_up(o + sizeof(ZEnd) * 4 * n, 256);
   L.tiles_all = o; o = align_up(o + tb, 256);
   L.tiles_run = o; o = align_up(o + tb, 256);
-  L.tiles_edge = o; o = align_up(o + sizeof(Tile) * (size_t)edge_tiles(d), 256);
+  L.tiles_halo = o; o = align_up(o + sizeof(Tile) * (size_t)halo_tiles(d), 256);
   L.counts = o; o = align_up(o + 4 * sizeof(int), 256);
   L.res = o; o = align_up(o + sizeof(unsigned long long) * n, 256);
   L.tdev = o; o = align_up(o + sizeof(long long), 256);
@@ -872,6 +825,8 @@ InstP make_inst(const lbaxi_desc& d, long long off, long long off_fld) {
   P.pitch = row_pitch(d);
   P.c0 = row_lead(d);
   P.plane = (int)padded_plane(d);
+  P.sw = (d.nr + 2) * row_pitch(d);
+  P.se = P.sw + strip_len(d);
   P.cart = (d.fields & LBAXI_CARTESIAN) ? 1 : 0;
   P.wet = (d.fields & LBAXI_WET_WALLS) ? 1 : 0;
   P.zou = (d.fields & LBAXI_ZOU_HE) ? 1 : 0;
@@ -912,81 +867,20 @@ InstP make_inst(const lbaxi_desc& d, long long off, long long off_fld) {
   return P;
 }
 
-// Z-end rule table entry of end e (0 west, 1 east), segment seg (1: rows
-// beyond r_split) of a lattice: see ZEnd.
-ZEnd zend_entry(const lbaxi_desc& d, int e, int seg) {
-  ZEnd z;
-  memset(&z, 0, sizeof z);
-  const long long pl = padded_plane(d), pitch = row_pitch(d);
-  const lbaxi_side& S = e ? d.east : d.west;
-  const bool per = S.kind == LBAXI_SIDE_PERIODIC;
-  const int kind = per ? LBAXI_SIDE_PERIODIC : (seg ? S.kind2 : S.kind);
-  const double omega = seg ? S.omega2 : S.omega, T = seg ? S.T2 : S.T;
-  const int thermal = seg ? S.thermal2 : S.thermal;
-  const int dir = e ? -1 : 1;                 // e_z of the links arriving across this end
-  const long long wrap = e ? -(d.nz - 1) : (d.nz - 1);
-  const int links[3] = {e ? 3 : 1, e ? 6 : 5, e ? 7 : 8};  // e_r = 0, +1, -1
-  const double rho0 = d.rho0;
-  for (int k = 0; k < 3; ++k) {
-    const int A = links[k], er = er9(A), ez = ez9(A);
-    z.sg[k] = 1.0;
-    if (per) {
-      z.rel[k] = (int)(A * pl - er * pitch + wrap);
-    } else if (kind == LBAXI_SIDE_FREESLIP) {
-      z.rel[k] = (int)(mz9(A) * pl - er * pitch);
-    } else {
-      z.rel[k] = (int)(opp9(A) * pl);
-      z.t0[k] = 6.0 * w9(A) * rho0 * (ez * S.u_z + er * S.u_r);
-    }
-  }
-  (void)dir;
-  const int a4 = e ? 2 : 0, o4 = opp4(a4);
-  if (d.fields & LBAXI_SWIRL) {
-    z.sg[3] = 1.0;
-    if (per) {
-      z.rel[3] = (int)((9 + a4) * pl + wrap);
-    } else {
-      z.rel[3] = (int)((9 + o4) * pl);
-      if (kind != LBAXI_SIDE_FREESLIP) {  // anti-bounce-back, rho0 u_theta,w = rho0 omega r
-        z.sg[3] = -1.0;
-        z.t0[3] = 0.5 * rho0 * omega * d.r0;
-        z.t1 = 0.5 * rho0 * omega;
-      }
-    }
-  }
-  if (d.fields & LBAXI_THERMAL) {
-    const int hb = (d.fields & LBAXI_SWIRL) ? 13 : 9;
-    z.sg[4] = 1.0;
-    if (per) {
-      z.rel[4] = (int)((hb + a4) * pl + wrap);
-    } else {
-      z.rel[4] = (int)((hb + o4) * pl);
-      if (kind == LBAXI_SIDE_WALL && thermal) {
-        z.sg[4] = -1.0;
-        z.t0[4] = 0.5 * (T - d.T_ref);
-      }
-    }
-  }
-  return z;
-}
-
 int ilog2(int x) {
   int l = 0;
   while ((1 << l) < x) ++l;
   return l;
 }
 
-// Work lists: every tile (seeding, macros, residual), the interior tiles of
-// the running lattices (k_step) and their perimeter chunks of 256 nodes
-// (k_edge).
-enum { LIST_ALL = 0, LIST_RUN = 1, LIST_EDGE = 2, NLISTS = 3 };
+enum { LIST_ALL = 0, LIST_RUN = 1, LIST_HALO = 2 };
 
 }  // namespace
 
 struct lbaxi_s {
   int n = 0, prec = 0;
   unsigned fields = 0;
-  bool any_wet = false;  // some lattice has wet-node walls
+  bool any_wet = false;  // some lattice has wet-node walls (k_wall runs)
   std::vector<lbaxi_desc> desc;
   std::vector<InstP> ip;
   hipStream_t stream = nullptr;
@@ -995,9 +889,8 @@ struct lbaxi_s {
   Layout L;
   InstP* d_ip = nullptr;
   InstDyn* d_dyn = nullptr;
-  ZEnd* d_zt = nullptr;
-  Tile* d_tiles[NLISTS] = {nullptr, nullptr, nullptr};
-  int* d_counts = nullptr;  // [LIST_ALL, LIST_RUN, LIST_EDGE]
+  Tile* d_tiles[3] = {nullptr, nullptr, nullptr};
+  int* d_counts = nullptr;  // [LIST_ALL, LIST_RUN, LIST_HALO]
   unsigned long long* d_res = nullptr;
   long long* d_t = nullptr;
   void* bufA = nullptr;
@@ -1017,8 +910,8 @@ struct lbaxi_s {
   // launch shape
   int tz = 64, tr = 4, grid = 0, xcd = 0, nt = 1;
   int K = 64;
-  std::vector<Tile> lists[NLISTS];
-  int count[NLISTS] = {0, 0, 0};
+  std::vector<Tile> lists[3];
+  int count[3] = {0, 0, 0};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   // kernel timing: event pairs around step-kernel launches
   bool prof = false;
@@ -1036,7 +929,7 @@ void drop_graphs(lbaxi_t* h) {
     }
 }
 
-// Rebuild the work lists for the current shape and statuses, upload
+// Rebuild the three work lists for the current shape and statuses, upload
 // them (synchronously: the host vectors are reused) and drop stale graphs.
 lbaxi_status build_tiles(lbaxi_t* h) {
   for (auto& v : h->lists) v.clear();
@@ -1044,14 +937,16 @@ lbaxi_status build_tiles(lbaxi_t* h) {
     const lbaxi_desc& d = h->desc[k];
     const bool run = h->status[k] == LBAXI_RUNNING;
     for (int j0 = 0; j0 < d.nr; j0 += h->tr)
-      for (int i0 = 0; i0 < d.nz; i0 += h->tz) h->lists[LIST_ALL].push_back(Tile{k, i0, j0, 0});
-    if (!run) continue;
-    for (int j0 = 1; j0 < d.nr - 1; j0 += h->tr)
-      for (int i0 = 0; i0 < d.nz; i0 += h->tz) h->lists[LIST_RUN].push_back(Tile{k, i0, j0, 0});
-    edge_list(d, k, &h->lists[LIST_EDGE], nullptr);
+      for (int i0 = 0; i0 < d.nz; i0 += h->tz) {
+        const Tile T = {k, i0, j0, 0};
+        h->lists[LIST_ALL].push_back(T);
+        if (run) h->lists[LIST_RUN].push_back(T);
+      }
+    if (run)
+      for (int p0 = 0; p0 < perimeter(d); p0 += 256) h->lists[LIST_HALO].push_back(Tile{k, p0, 0, 0});
   }
   int cnt[4] = {0, 0, 0, 0};
-  for (int q = 0; q < NLISTS; ++q) {
+  for (int q = 0; q < 3; ++q) {
     h->count[q] = cnt[q] = (int)h->lists[q].size();
     if (cnt[q])
       HIPCHK(hipMemcpyAsync(h->d_tiles[q], h->lists[q].data(), sizeof(Tile) * cnt[q],
@@ -1081,7 +976,9 @@ lbaxi_status upload_dyn(lbaxi_t* h) {
 template <typename S, typename R, int F>
 void* step_fn() { return reinterpret_cast<void*>(&k_step<S, R, F>); }
 template <typename S, typename R, int F>
-void* edge_fn() { return reinterpret_cast<void*>(&k_edge<S, R, F>); }
+void* halo_fn() { return reinterpret_cast<void*>(&k_halo<S, F & 3>); }  // no collision
+template <typename S, typename R, int F>
+void* wall_fn() { return reinterpret_cast<void*>(&k_wall<S, R, F>); }
 template <typename S, typename R, int F>
 void* seed_fn() { return reinterpret_cast<void*>(&k_seed<S, R, F>); }
 template <typename S, typename R, int F>
@@ -1139,31 +1036,49 @@ StepLaunch step_launch(lbaxi_t* h, int list, int from, long long t0, bool use_td
   a.lag_src = (const double*)(from ? h->lagB : h->lagA);
   a.lag_dst = (double*)(from ? h->lagA : h->lagB);
   a.lag_stride = h->L.lag_stride;
-  a.zt = h->d_zt;
   return L;
 }
 
-// The perimeter launch of the same step: the step's arguments over the
-// perimeter chunks of the running lattices.
-StepLaunch edge_launch(lbaxi_t* h, const StepLaunch& S) {
-  StepLaunch E = S;
-  E.fn = PICK(edge_fn, h->prec, h->fields);
-  E.block = 256;
-  E.grid = std::max(1, h->count[LIST_EDGE]);
-  E.a.tiles = h->d_tiles[LIST_EDGE];
-  E.a.ntiles = h->d_counts + LIST_EDGE;
-  return E;
+// Wet-wall launch of the same step: the step's arguments over the
+// perimeter tiles of the running lattices.
+StepLaunch wall_launch(lbaxi_t* h, const StepLaunch& S) {
+  StepLaunch W = S;
+  W.fn = PICK(wall_fn, h->prec, h->fields);
+  W.block = 256;
+  W.grid = std::max(1, h->count[LIST_HALO]);
+  W.a.tiles = h->d_tiles[LIST_HALO];
+  W.a.ntiles = h->d_counts + LIST_HALO;
+  return W;
 }
 
-// One time step of every running lattice: the interior launch, then the
-// perimeter launch (the first step after seeding reads each node's own
-// slots).
+// Halo launch filling the ghost slots of buffer `buf` (0 = A, 1 = B).
+struct HaloLaunch {
+  void* fn;
+  int grid;
+  const InstP* ip;
+  const Tile* tiles;
+  const int* ntiles;
+  void* buf;
+};
+
+HaloLaunch halo_launch(lbaxi_t* h, int buf) {
+  HaloLaunch H;
+  H.fn = PICK(halo_fn, h->prec, h->fields);
+  H.grid = std::max(1, h->count[LIST_HALO]);
+  H.ip = h->d_ip;
+  H.tiles = h->d_tiles[LIST_HALO];
+  H.ntiles = h->d_counts + LIST_HALO;
+  H.buf = buf ? h->bufB : h->bufA;
+  return H;
+}
+
+// One time step of every running lattice by direct launches: the step kernel
+// (the first step after seeding reads each node's own slots, over every
+// tile), then the halo fill of the buffer just written.
 lbaxi_status launch_step(lbaxi_t* h, int mode) {
-  StepLaunch L = step_launch(h, LIST_RUN, h->cur, h->t, false, 0,
-                             h->pre ? (mode | MODE_PRE) : mode);
-  StepLaunch E = edge_launch(h, L);
+  StepLaunch L = h->pre ? step_launch(h, LIST_ALL, h->cur, h->t, false, 0, mode | MODE_PRE)
+                        : step_launch(h, LIST_RUN, h->cur, h->t, false, 0, mode);
   void* args[] = {&L.a};
-  void* eargs[] = {&E.a};
   if (h->prof) {
     while (h->ev.size() < h->ev_used + 2) {
       hipEvent_t e;
@@ -1177,21 +1092,26 @@ lbaxi_status launch_step(lbaxi_t* h, int mode) {
     HIPCHK(hipEventRecord(h->ev[h->ev_used + 1], h->stream));
     h->ev_used += 2;
   }
-  HIPCHK(hipLaunchKernel(E.fn, dim3(E.grid), dim3(E.block), eargs, 0, h->stream));
+  if (h->any_wet && !h->pre) {
+    StepLaunch Wl = wall_launch(h, L);
+    void* wargs[] = {&Wl.a};
+    HIPCHK(hipLaunchKernel(Wl.fn, dim3(Wl.grid), dim3(Wl.block), wargs, 0, h->stream));
+  }
+  HaloLaunch H = halo_launch(h, h->cur ^ 1);
+  void* hargs[] = {&H.ip, &H.tiles, &H.ntiles, &H.buf};
+  HIPCHK(hipLaunchKernel(H.fn, dim3(H.grid), dim3(256), hargs, 0, h->stream));
   h->cur ^= 1;
   h->t += 1;
   h->pre = false;
   return LBAXI_OK;
 }
 
-// Graph of K steps starting from buffer `from`: per step an interior node
-// and a perimeter node, each depending on both nodes of the step before (the
-// two of one step are independent), then one node that advances the device
-// time base by K.
+// Graph of K steps starting from buffer `from`: step kernel, halo fill, step
+// kernel, ...; a last node advances the device time base by K.
 lbaxi_status make_graph(lbaxi_t* h, int from) {
   hipGraph_t g;
   HIPCHK(hipGraphCreate(&g, 0));
-  std::vector<hipGraphNode_t> prev, cur;
+  std::vector<hipGraphNode_t> prev;
   lbaxi_status st = LBAXI_OK;
   auto add = [&](void* fn, int grid, int block, void** args) {
     hipKernelNodeParams p;
@@ -1207,18 +1127,23 @@ lbaxi_status make_graph(lbaxi_t* h, int from) {
       st = fail(LBAXI_EDEVICE, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
       return;
     }
-    cur.push_back(node);
+    prev.assign(1, node);
   };
   for (int k = 0; k < h->K && st == LBAXI_OK; ++k) {
     const int src = from ^ (k & 1);
     StepLaunch L = step_launch(h, LIST_RUN, src, 0, true, k, 0);
-    StepLaunch E = edge_launch(h, L);
     void* args[] = {&L.a};
-    void* eargs[] = {&E.a};
-    cur.clear();
     add(L.fn, L.grid, L.block, args);
-    if (st == LBAXI_OK) add(E.fn, E.grid, E.block, eargs);
-    prev = cur;
+    if (st != LBAXI_OK) break;
+    if (h->any_wet) {
+      StepLaunch Wl = wall_launch(h, L);
+      void* wargs[] = {&Wl.a};
+      add(Wl.fn, Wl.grid, Wl.block, wargs);
+      if (st != LBAXI_OK) break;
+    }
+    HaloLaunch H = halo_launch(h, src ^ 1);
+    void* hargs[] = {&H.ip, &H.tiles, &H.ntiles, &H.buf};
+    add(H.fn, H.grid, 256, hargs);
   }
   if (st == LBAXI_OK) {
     long long* tp = h->d_t;
@@ -1253,7 +1178,7 @@ lbaxi_status check_handle(const lbaxi_t* h) {
 lbaxi_status run_steps(lbaxi_t* h, long long n) {
   if (n <= 0) return LBAXI_OK;
   lbaxi_status st;
-  if (h->count[LIST_EDGE] == 0) return LBAXI_OK;  // no running lattice
+  if (h->count[LIST_RUN] == 0) return LBAXI_OK;
   long long left = n;
   if (h->pre) {
     if ((st = launch_step(h, left == 1 ? MODE_SPEED : 0)) != LBAXI_OK) return st;
@@ -1428,10 +1353,9 @@ lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace,
   h->L = layout(h->desc);
   h->d_ip = reinterpret_cast<InstP*>(h->ws + h->L.ip);
   h->d_dyn = reinterpret_cast<InstDyn*>(h->ws + h->L.dyn);
-  h->d_zt = reinterpret_cast<ZEnd*>(h->ws + h->L.zt);
   h->d_tiles[LIST_ALL] = reinterpret_cast<Tile*>(h->ws + h->L.tiles_all);
   h->d_tiles[LIST_RUN] = reinterpret_cast<Tile*>(h->ws + h->L.tiles_run);
-  h->d_tiles[LIST_EDGE] = reinterpret_cast<Tile*>(h->ws + h->L.tiles_edge);
+  h->d_tiles[LIST_HALO] = reinterpret_cast<Tile*>(h->ws + h->L.tiles_halo);
   h->d_counts = reinterpret_cast<int*>(h->ws + h->L.counts);
   h->d_res = reinterpret_cast<unsigned long long*>(h->ws + h->L.res);
   h->d_t = reinterpret_cast<long long*>(h->ws + h->L.tdev);
@@ -1445,16 +1369,9 @@ lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace,
   h->status.assign(n, LBAXI_RUNNING);
   h->dyn.assign(n, InstDyn{0, 1, 0});
   h->inst_spd.assign(n, 0);
-  std::vector<ZEnd> zt;
-  for (int k = 0; k < n; ++k)
-    for (int e = 0; e < 2; ++e)
-      for (int seg = 0; seg < 2; ++seg) zt.push_back(zend_entry(h->desc[k], e, seg));
   hipError_t e = hipGetDevice(&h->device);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->d_ip, h->ip.data(), sizeof(InstP) * n, hipMemcpyHostToDevice,
-                       h->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(h->d_zt, zt.data(), sizeof(ZEnd) * zt.size(), hipMemcpyHostToDevice,
                        h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
@@ -1604,7 +1521,7 @@ lbaxi_status lbaxi_batch_run(lbaxi_t* h, double tol, int64_t max_steps, int64_t 
   std::vector<long long> t_start(h->n);
   for (int k = 0; k < h->n; ++k) t_start[k] = h->status[k] == LBAXI_RUNNING ? h->t : h->dyn[k].t;
   long long done = 0;
-  while (done < max_steps && h->count[LIST_EDGE] > 0) {
+  while (done < max_steps && h->count[LIST_RUN] > 0) {
     const long long n = std::min<long long>(check_every, max_steps - done);
     if ((st = run_steps(h, n)) != LBAXI_OK) return st;
     for (int k = 0; k < h->n; ++k)

@@ -32,7 +32,8 @@ struct InstP {
   int zou;    // with wet: radial wall nodes rebuild f by Zou-He
   int pitch;  // row length of a padded plane (a multiple of 128 bytes)
   int c0;     // column of node i = 0 (128 bytes into the row)
-  int plane;  // elements per padded plane: (nr + 2) rows of pitch
+  int plane;  // elements per padded plane: (nr + 2) rows of pitch, then the two strips
+  int sw, se;  // element offsets in a plane of the west / east ghost-column strips
   double r0;
   double tau, tau_g, tau_h;  // paper convention: nu = tau / 3
   double rho0, mu0, nu_g;
@@ -403,13 +404,12 @@ __device__ inline void collide(const PR<R>& p, const Row<R>& w, const Mac<R>& m,
 // ---- streaming ---------------------------------------------------------------
 // Each population plane holds rows j in [-1, nr] (the two ghost rows
 // included) of pitch elements, node (i, j) at (j + 1) * pitch + c0 + i with
-// rows starting on 128-byte boundaries so that a wave's stores are aligned;
-// the lead-in before node 0 and a spare slot after node nz - 1 hold the
-// positions i = -1 and i = nz.  An interior node pulls f_a(x) from x - e_a
-// without any test; a boundary node does the same (no address leaves the
-// plane) and then replaces what crossed a side by the boundary rules below,
-// evaluated on the post-collision values of real nodes.  Ghost positions are
-// never written and their contents never used.
+// rows starting on 128-byte boundaries so that a wave's stores are aligned,
+// then one strip per z-end holding that end's ghost column for rows -1..nr.
+// The step kernel pulls f_a(x) from x - e_a for every node without any test
+// (the end columns then re-read from the strips what crosses a z-end); the
+// ghost slots are filled after every step by the halo kernel with the
+// boundary rules below, evaluated on the post-collision values of real nodes.
 
 __device__ inline int nidx(const InstP& P, int j, int i) { return (j + 1) * P.pitch + P.c0 + i; }
 
@@ -565,10 +565,17 @@ __device__ inline ZSeg zend(const InstP& P, const InstP* Pg, bool west, int j) {
   return z;
 }
 
+// Ghost slot (element offset in a plane) of the upstream position (iu, ju)
+// outside the lattice: beyond a z-end, the west / east strip, which holds
+// the ghost column of rows -1..nr contiguously (so that filling it is a
+// coalesced write, not one element per row); else the ghost row.
+__device__ inline int ghost_slot(const InstP& P, int iu, int ju) {
+  return iu < 0 ? P.sw + ju + 1 : (iu >= P.nz ? P.se + ju + 1 : nidx(P, ju, iu));
+}
+
 // Boundary rules: the value node (i, j) receives in direction A when its
-// upstream node (i, j) - e_A lies outside the lattice, from the post-collision
-// values s of real nodes (s points at the instance's first plane).  A z-end
-// is resolved before the radial sides.
+// upstream node (i, j) - e_A lies outside the lattice.  A z-end is resolved
+// before the radial sides.  s points at the instance's first plane.
 //
 // f: moving-wall bounce-back adds 6 w_a rho0 (e_a . u_w); the axis mirrors
 // row 1; a free-slip z-end reflects e_z only.
@@ -667,38 +674,76 @@ __device__ inline double rule_h(const InstP& P, const InstP* Pg, const S* s, int
   return (double)s[A * pl + nidx(P, ju, iu)];
 }
 
-// Populations that boundary node (i, j) receives from outside the lattice:
-// every direction whose upstream node lies outside takes its rule, evaluated
-// on the post-collision values of real nodes.  A rule's value passes through
-// the storage type, as a stored population would.
-template <typename S, typename R, int F, int A>
-__device__ inline void boundary_pull(const InstP& P, const InstP* Pg, const S* s, int i, int j,
-                                     R* f, R* g, R* h) {
+// Ghost slots that boundary node (i, j) pulls from, with their values:
+// at[k] is the slot of plane k (f, g, h in storage order) or -1 where the
+// upstream node is a real one.
+template <typename S, int F, int A>
+__device__ inline void halo_gather(const InstP& P, const InstP* Pg, const S* s, int i, int j,
+                                   S* v, int* at) {
   const int pl = P.plane;
   {
     const int iu = i - ez9(A), ju = j - er9(A);
-    if (iu < 0 || iu >= P.nz || ju < 0 || ju >= P.nr) f[A] = (R)(S)rule_f<S, A>(P, Pg, s, i, j);
+    const bool out = iu < 0 || iu >= P.nz || ju < 0 || ju >= P.nr;
+    at[A] = out ? A * pl + ghost_slot(P, iu, ju) : -1;
+    if (out) v[A] = (S)rule_f<S, A>(P, Pg, s, i, j);
   }
   if constexpr (A < 4) {
     const int iu = i - ez4(A), ju = j - er4(A);
-    if (iu < 0 || iu >= P.nz || ju < 0 || ju >= P.nr) {
-      if (F & F_SWIRL) g[A] = (R)(S)rule_g<S, A>(P, Pg, s + 9 * pl, i, j);
-      if (F & F_THERMAL) {
-        constexpr int hb = (F & F_SWIRL) ? 13 : 9;
-        h[A] = (R)(S)rule_h<S, A>(P, Pg, s + hb * pl, i, j);
-      }
+    const bool out = iu < 0 || iu >= P.nz || ju < 0 || ju >= P.nr;
+    if (F & F_SWIRL) {
+      at[9 + A] = out ? (9 + A) * pl + ghost_slot(P, iu, ju) : -1;
+      if (out) v[9 + A] = (S)rule_g<S, A>(P, Pg, s + 9 * pl, i, j);
+    }
+    if (F & F_THERMAL) {
+      constexpr int hb = (F & F_SWIRL) ? 13 : 9;
+      at[hb + A] = out ? (hb + A) * pl + ghost_slot(P, iu, ju) : -1;
+      if (out) v[hb + A] = (S)rule_h<S, A>(P, Pg, s + hb * pl, i, j);
     }
   }
-  if constexpr (A + 1 < 9) boundary_pull<S, R, F, A + 1>(P, Pg, s, i, j, f, g, h);
+  if constexpr (A + 1 < 9) halo_gather<S, F, A + 1>(P, Pg, s, i, j, v, at);
 }
 
-// Populations arriving at an interior node (i, j), every upstream node
-// inside the lattice: a plain pull through the padded planes.  pre: the
-// buffer holds f^ itself (right after seeding), so the node reads its own
-// slots.
+// Fill, for boundary node (i, j), every ghost slot it pulls from.  Sources
+// are always real nodes and targets ghost slots, so every value is read
+// before the first write: the loads of a node stay in flight together
+// instead of waiting one by one behind stores to the same buffer.
+template <typename S, int F>
+__device__ inline void halo_fill(const InstP& P, const InstP* Pg, S* s, int i, int j) {
+  constexpr int NQ = 9 + ((F & F_SWIRL) ? 4 : 0) + ((F & F_THERMAL) ? 4 : 0);
+  S v[NQ];
+  int at[NQ];
+  halo_gather<S, F, 0>(P, Pg, s, i, j, v, at);
+#pragma unroll
+  for (int k = 0; k < NQ; ++k)
+    if (at[k] >= 0) s[at[k]] = v[k];
+}
+
+// Populations that node (WEST ? 0 : nz - 1, j) receives across its z-end,
+// from the ghost-column strip of that end (rows j - e_r, slot row + 1).
+template <typename S, typename R, int F, bool WEST_END>
+__device__ inline void zend_pull(const InstP& P, const S* __restrict__ s, int j, R* f, R* g, R* h) {
+  const int pl = P.plane;
+  constexpr int dir = WEST_END ? 1 : -1;  // e_z of the populations that cross it
+  const unsigned b = (unsigned)((WEST_END ? P.sw : P.se) + j + 1);
+  constexpr unsigned es = sizeof(S);
+#pragma unroll
+  for (int a = 0; a < 9; ++a)
+    if (ez9(a) == dir) f[a] = (R)ldb(s + a * pl, (b - er9(a)) * es);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+    if (ez4(a) == dir) {
+      if (F & F_SWIRL) g[a] = (R)ldb(s + (9 + a) * pl, (b - er4(a)) * es);
+      if (F & F_THERMAL) h[a] = (R)ldb(s + (((F & F_SWIRL) ? 13 : 9) + a) * pl, (b - er4(a)) * es);
+    }
+}
+
+// Populations arriving at node (i, j): a plain pull through the padded
+// planes; an end column takes what crosses its z-end from that end's strip.
+// pre: the buffer holds f^ itself (right after seeding), so the node reads
+// its own slots.
 template <typename S, typename R, int F>
-__device__ inline void plain_pull(const InstP& P, const S* __restrict__ s, int i, int j, bool pre,
-                                  R* f, R* g, R* h) {
+__device__ inline void load_node(const InstP& P, const S* __restrict__ s, int i, int j, bool pre,
+                                 R* f, R* g, R* h) {
   // Loads are written as a wave-uniform plane base plus a 32-bit byte offset
   // so that they use scalar-base addressing (one offset register per row).
   const int pl = P.plane, pt = P.pitch;
@@ -723,63 +768,12 @@ __device__ inline void plain_pull(const InstP& P, const S* __restrict__ s, int i
       if (F & F_SWIRL) g[a] = (R)ldb(sg + a * pl, q);
       if (F & F_THERMAL) h[a] = (R)ldb(sh + a * pl, q);
     }
+    // an end column takes what crosses its z-end from that end's strip
+    // (re-read after the plain pull, which keeps the interior's immediate
+    // load offsets and registers as they are)
+    if (i == 0) zend_pull<S, R, F, true>(P, s, j, f, g, h);
+    if (i == P.nz - 1) zend_pull<S, R, F, false>(P, s, j, f, g, h);
   }
-}
-
-// The z-end rules of one end of a lattice for the rows of one segment,
-// reduced to one redirected load each: the value an end-column node (i, j)
-// with 0 < j < nr - 1 receives across that end along link k is
-//     sg[k] * s[o + rel[k]] + t0[k] (+ t1 j for the swirl link),
-// o being the node's own element index.  Links k = 0, 1, 2 are the f links
-// with e_z pointing inwards and e_r = 0, +1, -1; k = 3 is the g link and
-// k = 4 the h link along e_z.  Built on the host from the side descriptions
-// (periodic wrap, moving-wall bounce-back, anti-bounce-back of g and of h at
-// a fixed temperature, e_z mirror of a free-slip segment) with the same
-// terms as rule_f / rule_g / rule_h.
-struct ZEnd {
-  int rel[5];
-  int pad;
-  double sg[5];
-  double t0[5];
-  double t1;
-};
-
-// What an end-column node of rows 1 .. nr - 2 receives across its z-end
-// (Z: the entry of its end and segment).
-template <typename S, typename R, int F>
-__device__ inline void zend_pull(const S* __restrict__ s, const ZEnd* Z, bool west, int o, int j,
-                                 R* f, R* g, R* h) {
-  const int k0 = west ? 1 : 3, k1 = west ? 5 : 6, k2 = west ? 8 : 7, kq = west ? 0 : 2;
-  const double v0 = (double)s[o + Z->rel[0]], v1 = (double)s[o + Z->rel[1]];
-  const double v2 = (double)s[o + Z->rel[2]];
-  double v3 = 0.0, v4 = 0.0;
-  if (F & F_SWIRL) v3 = (double)s[o + Z->rel[3]];
-  if (F & F_THERMAL) v4 = (double)s[o + Z->rel[4]];
-  const R r0 = (R)(S)(Z->sg[0] * v0 + Z->t0[0]);
-  const R r1 = (R)(S)(Z->sg[1] * v1 + Z->t0[1]);
-  const R r2 = (R)(S)(Z->sg[2] * v2 + Z->t0[2]);
-  // direction indices are compile-time per branch so that f, g, h stay in registers
-  if (west) { f[1] = r0; f[5] = r1; f[8] = r2; } else { f[3] = r0; f[6] = r1; f[7] = r2; }
-  (void)k0; (void)k1; (void)k2; (void)kq;
-  if (F & F_SWIRL) {
-    const R q = (R)(S)(Z->sg[3] * v3 + (Z->t0[3] + Z->t1 * (double)j));
-    if (west) g[0] = q; else g[2] = q;
-  }
-  if (F & F_THERMAL) {
-    const R q = (R)(S)(Z->sg[4] * v4 + Z->t0[4]);
-    if (west) h[0] = q; else h[2] = q;
-  }
-}
-
-// Populations arriving at any node: the plain pull (the ghost rows and the
-// lead-in / spare slot of each row keep every address inside the plane),
-// then, on a boundary node, the rules for what crosses a side.
-template <typename S, typename R, int F>
-__device__ inline void load_node(const InstP& P, const InstP* Pg, const S* __restrict__ s, int i,
-                                 int j, bool pre, R* f, R* g, R* h) {
-  plain_pull<S, R, F>(P, s, i, j, pre, f, g, h);
-  if (!pre && (i == 0 || i == P.nz - 1 || j == 0 || j == P.nr - 1))
-    boundary_pull<S, R, F, 0>(P, Pg, s, i, j, f, g, h);
 }
 
 }  // namespace lbx
