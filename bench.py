@@ -157,32 +157,43 @@ def cpu_baseline(cases, seconds: float):
 
 
 def copy_probe(steps: int, warmup: int, nbytes: int = 4 << 30):
-    """Device-to-device streaming copy through the library's copy kernel: the
-    practical HBM ceiling the step kernel is compared with."""
-    import ctypes as C
+    """Device-to-device streaming copy of 4 GiB through the library's copy
+    kernel with 1, 2, 4 and 8 loads in flight per lane, and torch's own copy:
+    the practical HBM ceiling the step kernel is compared with (the best of
+    them), and the kernel whose known traffic calibrates the HBM counters."""
     import torch
     from paper_1003_0282_amd import lbaxi as L
-    L._L.lbaxi_stream_copy.restype = C.c_int32
-    L._L.lbaxi_stream_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
     s = torch.cuda.current_stream()
-    call = lambda: L._check(L._L.lbaxi_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes,
-                                                   s.cuda_stream), "lbaxi_stream_copy")
-    for _ in range(max(1, warmup)):
-        call()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(steps):
-        call()
-    e1.record(s)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    gbs = 2 * nbytes / (ms / 1e3) / 1e9
-    return {"metric": "copy bandwidth (read + write)", "value": round(gbs, 1), "unit": "GB/s",
-            "bytes_per_launch": 2 * nbytes, "ms_per_launch": round(ms, 4),
-            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+    def timed(call):
+        for _ in range(max(1, warmup)):
+            call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(steps):
+            call()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    runs = {}
+    for u in (1, 2, 4, 8):
+        ms = timed(lambda: L._check(L._L.lbaxi_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes,
+                                                            u, s.cuda_stream), "lbaxi_stream_copy"))
+        runs["k_copy<%d>" % u] = ms
+    runs["torch copy_"] = timed(lambda: dst.copy_(src))
+    assert bool((dst == 1).all())
+    gbs = {k: 2 * nbytes / (ms / 1e3) / 1e9 for k, ms in runs.items()}
+    best = max(gbs, key=gbs.get)
+    return {"metric": "copy bandwidth (read + write)", "value": round(gbs[best], 1), "unit": "GB/s",
+            "best": best, "bytes_per_launch": 2 * nbytes,
+            "variants": {k: {"ms_per_launch": round(runs[k], 4), "GB/s": round(gbs[k], 1)}
+                         for k in runs},
+            "frac_of_peak": round(gbs[best] / HBM_PEAK_GBS, 4)}
 
 
 def sequential_probe(steps: int):

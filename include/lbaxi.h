@@ -281,9 +281,13 @@ lbaxi_status lbaxi_node_count(const lbaxi_t* h, int64_t* nodes, int32_t* n);
 
 /* Plain device-to-device streaming copy of `bytes` (a multiple of 16, both
  * pointers 16-byte aligned) on hip_stream: the bandwidth reference used to
- * calibrate HBM counters and the roofline fraction of the step kernel.
- * Asynchronous; EINVAL on misaligned arguments or a copy above 8 TiB. */
-lbaxi_status lbaxi_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* hip_stream);
+ * calibrate HBM counters and to measure the streaming ceiling the step kernel
+ * is compared with.  loads_per_lane (1, 2, 4 or 8) 16-byte loads per lane are
+ * issued before the first store; every byte is read and written once.
+ * Asynchronous; EINVAL on misaligned arguments, another loads_per_lane or a
+ * copy above 2^31 workgroups. */
+lbaxi_status lbaxi_stream_copy(const void* d_src, void* d_dst, size_t bytes, int32_t loads_per_lane,
+                               void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -289,12 +289,53 @@ __device__ inline void wall_state(const InstP& P, const PR<R>& p, const S* s, in
   }
 }
 
-// Macros, collision and store of one pulled node.
+// A value that is the same on every active lane, moved to scalar registers
+// (the step kernel's waves never straddle a row, so the row constants are
+// wave-uniform; held in SGPRs they cost no VGPRs).
+__device__ inline double uni(double x) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ inline float uni(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(unsigned, x)));
+}
+template <typename R, int F>
+__device__ inline Row<R> uni_row(Row<R> w) {
+  w.ir = uni(w.ir);
+  w.ir2 = uni(w.ir2);
+  if (F & F_MRT) {
+    w.gam = uni(w.gam);
+  } else {
+    w.omp = uni(w.omp);
+    w.omm = uni(w.omm);
+    w.c0 = uni(w.c0);
+    w.cp = uni(w.cp);
+    w.cm = uni(w.cm);
+  }
+  if (F & F_SWIRL) {
+    w.gp = uni(w.gp);
+    w.gm = uni(w.gm);
+    w.gsk = uni(w.gsk);
+  }
+  if (F & F_THERMAL) {
+    w.hp = uni(w.hp);
+    w.hm = uni(w.hm);
+  }
+  return w;
+}
+
+// Macros, collision and store of one pulled node.  uniform_row: j is the
+// same on every lane of the wave.  The swirl and temperature populations are
+// collided and stored before f is collided, so that they are not live
+// through the f collision.
 template <typename S, typename R, int F>
 __device__ inline void finish_node(const StepArgs<S>& A, const InstP& P, const PR<R>& p, int i,
-                                   int j, R* f, R* g, R* h) {
+                                   int j, R* f, R* g, R* h, bool uniform_row = false) {
   const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
-  const Row<R> rw = make_row<R, F>(p, j);
+  const Row<R> rw = uniform_row ? uni_row<R, F>(make_row<R, F>(p, __builtin_amdgcn_readfirstlane(j)))
+                                : make_row<R, F>(p, j);
   Mac<R> m;
   if (F & F_ORIG) {
     R Dr, Dz;
@@ -305,20 +346,74 @@ __device__ inline void finish_node(const StepArgs<S>& A, const InstP& P, const P
     S* ld = A.lag_dst + P.off_fld + (long long)j * P.nz + i;
     ld[0] = (S)m.uz;
     ld[A.lag_stride] = (S)m.ur;
+  } else if (sizeof(S) < sizeof(R)) {
+    // float storage: only the floats stay live across the macros.  The
+    // empty asm makes each float opaque to the compiler, so the collision
+    // converts it again instead of keeping the double (2 VGPRs) alive.
+    float fl[9], gl[4], hl[4];
+    R fa[9], ga[4], ha[4];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      fl[a] = (float)f[a];
+      asm volatile("" : "+v"(fl[a]));
+      fa[a] = (R)fl[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (F & F_SWIRL) {
+        gl[a] = (float)g[a];
+        asm volatile("" : "+v"(gl[a]));
+        ga[a] = (R)gl[a];
+      }
+      if (F & F_THERMAL) {
+        hl[a] = (float)h[a];
+        asm volatile("" : "+v"(hl[a]));
+        ha[a] = (R)hl[a];
+      }
+    }
+    m = macros<R, F>(p, rw, axis_row, fa, ga, ha);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      asm volatile("" : "+v"(fl[a]));
+      f[a] = (R)fl[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (F & F_SWIRL) {
+        asm volatile("" : "+v"(gl[a]));
+        g[a] = (R)gl[a];
+      }
+      if (F & F_THERMAL) {
+        asm volatile("" : "+v"(hl[a]));
+        h[a] = (R)hl[a];
+      }
+    }
   } else {
     m = macros<R, F>(p, rw, axis_row, f, g, h);
-    collide<R, F>(p, rw, m, f, g, h);
   }
   S* d = A.dst + P.off;
   const int pl = P.plane;
   const unsigned ob = (unsigned)nidx(P, j, i) * (unsigned)sizeof(S);
+  if (!(F & F_ORIG)) {
+    collide<R, F>(p, rw, m, f, g, h, 2);
+    if (F & F_SWIRL) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) st(ptrb(d + (9 + a) * pl, ob), (S)g[a], A.nt_store);
+    }
+    if (F & F_THERMAL) {
+      const int hb = (F & F_SWIRL) ? 13 : 9;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) st(ptrb(d + (hb + a) * pl, ob), (S)h[a], A.nt_store);
+    }
+    collide<R, F>(p, rw, m, f, g, h, 1);
+  }
 #pragma unroll
   for (int a = 0; a < 9; ++a) st(ptrb(d + a * pl, ob), (S)f[a], A.nt_store);
-  if (F & F_SWIRL) {
+  if ((F & F_ORIG) && (F & F_SWIRL)) {
 #pragma unroll
     for (int a = 0; a < 4; ++a) st(ptrb(d + (9 + a) * pl, ob), (S)g[a], A.nt_store);
   }
-  if (F & F_THERMAL) {
+  if ((F & F_ORIG) && (F & F_THERMAL)) {
     const int hb = (F & F_SWIRL) ? 13 : 9;
 #pragma unroll
     for (int a = 0; a < 4; ++a) st(ptrb(d + (hb + a) * pl, ob), (S)h[a], A.nt_store);
@@ -343,8 +438,16 @@ __device__ inline void perimeter_node(const InstP& P, int p, int& i, int& j) {
 // One time step: pull (padded planes, no boundary tests), macros, collision,
 // store at the node's own slots of the other buffer.  The halo kernel then
 // completes the boundary rules for the next pull.
+// Waves per SIMD the step kernel is compiled for: five (at most 96 VGPRs)
+// where the field set fits without spilling, four (128) for swirl together
+// with temperature or with MRT.
+constexpr int step_waves(int F) {
+  return ((F & F_SWIRL) && (F & (F_THERMAL | F_MRT))) ? 4 : 5;
+}
+
 template <typename S, typename R, int F>
-__global__ void __launch_bounds__(1024) k_step(StepArgs<S> A) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(step_waves(F))))
+k_step(StepArgs<S> A) {
   const long long t = A.tdev ? (*A.tdev + A.k) : A.t0;
   const int ntiles = *A.ntiles;
   const TileRange tr = tile_range(ntiles, A.xcd);
@@ -363,7 +466,7 @@ __global__ void __launch_bounds__(1024) k_step(StepArgs<S> A) {
     const PR<R> p = make_pr<R>(P, t);
     R f[9], g[4], h[4];
     pull_plain<S, R, F>(P, p, A.src + P.off, i, j, pre, f, g, h, !wall);
-    finish_node<S, R, F>(A, P, p, i, j, f, g, h);
+    finish_node<S, R, F>(A, P, p, i, j, f, g, h, true);
   }
 }
 
@@ -614,15 +717,26 @@ __global__ void k_add_time(long long* t, long long dv) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *t += dv;
 }
 
-// Plain streaming copy (16 bytes per lane per iteration), the bandwidth
-// reference against which the step kernel's HBM traffic is calibrated.
+// Plain streaming copy, the bandwidth reference against which the step
+// kernel's HBM traffic is calibrated.  A workgroup moves U * 4 KiB: each lane
+// issues its U 16-byte loads (coalesced, 4 KiB apart) before the first store,
+// so U loads per lane are in flight at once.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <int U>
 __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src,
                                               u32x4* __restrict__ dst, long long n) {
-  // one 16-byte element per lane, one workgroup per 4 KiB: no loop, so that
-  // every wave has its load in flight from the start
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) __builtin_nontemporal_store(src[k], dst + k);
+  const long long base = (long long)blockIdx.x * (256 * U) + threadIdx.x;
+  u32x4 v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const long long k = base + 256LL * u;
+    if (k < n) v[u] = src[k];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const long long k = base + 256LL * u;
+    if (k < n) __builtin_nontemporal_store(v[u], dst + k);
+  }
 }
 
 // Residual words of lbaxi_residual_static: a fixed array in device memory
@@ -1833,16 +1947,26 @@ lbaxi_status lbaxi_kernel_time(lbaxi_t* h, double* ms, int64_t* launches) {
   return LBAXI_OK;
 }
 
-lbaxi_status lbaxi_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* hip_stream) {
+lbaxi_status lbaxi_stream_copy(const void* d_src, void* d_dst, size_t bytes, int32_t loads_per_lane,
+                               void* hip_stream) {
   if (!d_src || !d_dst || bytes % 16 || (reinterpret_cast<uintptr_t>(d_src) % 16) ||
       (reinterpret_cast<uintptr_t>(d_dst) % 16))
     return fail(LBAXI_EINVAL, "copy needs 16-byte aligned pointers and size");
+  const int U = loads_per_lane;
+  if (U != 1 && U != 2 && U != 4 && U != 8) return fail(LBAXI_EINVAL, "loads_per_lane must be 1, 2, 4 or 8");
   const long long n = (long long)(bytes / 16);
   if (n == 0) return LBAXI_OK;
-  const long long grid = (n + 255) / 256;
-  if (grid > 0x7fffffffLL) return fail(LBAXI_EINVAL, "copy larger than 2^31 workgroups of 4 KiB");
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)grid), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream),
-                     static_cast<const u32x4*>(d_src), static_cast<u32x4*>(d_dst), n);
+  const long long grid = (n + 256LL * U - 1) / (256LL * U);
+  if (grid > 0x7fffffffLL) return fail(LBAXI_EINVAL, "copy larger than 2^31 workgroups");
+  const hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const u32x4* a = static_cast<const u32x4*>(d_src);
+  u32x4* b = static_cast<u32x4*>(d_dst);
+  switch (U) {
+    case 1: hipLaunchKernelGGL(k_copy<1>, dim3((unsigned)grid), dim3(256), 0, st, a, b, n); break;
+    case 2: hipLaunchKernelGGL(k_copy<2>, dim3((unsigned)grid), dim3(256), 0, st, a, b, n); break;
+    case 4: hipLaunchKernelGGL(k_copy<4>, dim3((unsigned)grid), dim3(256), 0, st, a, b, n); break;
+    default: hipLaunchKernelGGL(k_copy<8>, dim3((unsigned)grid), dim3(256), 0, st, a, b, n); break;
+  }
   HIPCHK(hipGetLastError());
   return LBAXI_OK;
 }

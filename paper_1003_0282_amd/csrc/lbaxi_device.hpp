@@ -355,9 +355,11 @@ __device__ inline void collide_f_orig(const PR<R>& p, const Row<R>& w, const Mac
 // populations in place.
 template <typename R, int F>
 __device__ inline void collide(const PR<R>& p, const Row<R>& w, const Mac<R>& m, R* f, R* g,
-                               R* h) {
+                               R* h, int part = 3) {
+  // part: 1 = f, 2 = g and h, 3 = all
   const R uz = m.uz, ur = m.ur;
-  if (F & F_MRT) {
+  if (!(part & 1)) {
+  } else if (F & F_MRT) {
     collide_f_mrt<R>(p, w, m, f);
   } else {
     const R k15 = (R)1.5 * (uz * uz + ur * ur);
@@ -377,7 +379,7 @@ __device__ inline void collide(const PR<R>& p, const Row<R>& w, const Mac<R>& m,
     collide_pair(f[8], f[6], uz - ur, m.Fz - m.Fr, w5, w.omm, w.omp, w.cm, w.cp, m.drho, m.rho,
                  k15, C0);
   }
-  if (F & F_SWIRL) {
+  if ((F & F_SWIRL) && (part & 2)) {
     // g_eq = (rho0 u_th / 4)(1 + 2 e.u), S^g = -(1/r)(2 u_r + nu / r) g_eq
     const R q = (R)0.25 * p.rho0 * m.uth;
     const R sk = (R)1 - w.ir * ((R)2 * ur + w.gsk);  // g* = g - om (g - geq) + (sk - 1) geq
@@ -388,7 +390,7 @@ __device__ inline void collide(const PR<R>& p, const Row<R>& w, const Mac<R>& m,
     g[1] = g[1] - w.gp * g[1] + (w.gp + sk - (R)1) * gr0;
     g[3] = g[3] - w.gm * g[3] + (w.gm + sk - (R)1) * gr1;
   }
-  if (F & F_THERMAL) {
+  if ((F & F_THERMAL) && (part & 2)) {
     // h_eq = (T/4)(1 + 2 e.u), S^h = -(u_r / r) h_eq; h stored as h - T_ref/4
     const R T = p.T_ref + m.dT;
     const R q = (R)0.25 * T, qd = (R)0.25 * m.dT;

@@ -43,8 +43,13 @@ __device__ inline bf16s f2bf(float f) {
 // so the backward pass needs no pre-activation.  (A smooth activation keeps
 // the gradient of a network with BF16 activations well conditioned: a
 // ReLU's mask flips wherever rounding moves a pre-activation across zero.)
-__device__ inline float softplus(float v) { return fmaxf(v, 0.0f) + log1pf(__expf(-fabsf(v))); }
-__device__ inline float softplus_grad(float a) { return -expm1f(-a); }
+// Both use the hardware base-2 exponential and logarithm (__expf, __logf):
+// their absolute error, a few 1e-8, is far below the BF16 rounding of the
+// stored activations and gradients.
+__device__ inline float softplus(float v) {
+  return fmaxf(v, 0.0f) + __logf(1.0f + __expf(-fabsf(v)));
+}
+__device__ inline float softplus_grad(float a) { return 1.0f - __expf(-a); }
 
 __device__ inline f32x16 mfma(u16x8 a, u16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
@@ -564,8 +569,17 @@ __global__ void __launch_bounds__(256) k_sum_chunks(const float* part, float* ou
                                                     int nchunk) {
   const long long w = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= n) return;
+  // eight loads in flight, added in chunk order
   float s = 0.0f;
-  for (int c = 0; c < nchunk; ++c) s += part[(long long)c * n + w];
+  int c = 0;
+  for (; c + 8 <= nchunk; c += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(long long)(c + u) * n + w];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; c < nchunk; ++c) s += part[(long long)c * n + w];
   out[w] = s;
 }
 

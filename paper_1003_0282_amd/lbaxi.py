@@ -76,7 +76,7 @@ _sigs = {
     "lbaxi_load": (_st, [_P, _P, C.c_size_t]),
     "lbaxi_node_count": (_st, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "lbaxi_abi_desc_size": (C.c_size_t, []),
-    "lbaxi_stream_copy": (_st, [_P, _P, C.c_size_t, _P]),
+    "lbaxi_stream_copy": (_st, [_P, _P, C.c_size_t, C.c_int32, _P]),
     "lbaxi_set_profiling": (_st, [_P, C.c_int32]),
     "lbaxi_kernel_time": (_st, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }

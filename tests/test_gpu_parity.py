@@ -57,7 +57,11 @@ def test_hagen_poiseuille_fp32_storage_floor():
     steady state that rounding is the same every step, so the slowest viscous
     mode (e-fold R^2 / (nu j01^2) ~ 1700 steps here) accumulates it: the bound
     2^-24 x 1700 ~ 1e-4 of u_max is the arithmetic's, and the float storage
-    with double arithmetic must stay well inside it."""
+    with double arithmetic must stay well inside it.  This is the one FP32
+    case held to a looser bar than 1e-5 of u_max: measured 1.2e-5 on u_z
+    (the FP32 runs of the other workloads, also at 1e5 steps, stay below
+    1e-5), so the bar here is 2e-5.  The FP64 run of this pipe is the
+    workload's own precision and meets 1e-10."""
     case = W.hagen_poiseuille()
     o = oracle_run(case, 20000)
     lat = gpu_run([case], 20000, 1)
@@ -65,7 +69,7 @@ def test_hagen_poiseuille_fp32_storage_floor():
     from _parity import errors
     e, _ = errors(case, gm, o.macros())
     print("HP FP32 storage", e)
-    assert e["uz"] < 5e-5 and e["ur"] < 1e-5, e
+    assert e["uz"] < 2e-5 and e["ur"] < 1e-5, e
 
 
 @pytest.mark.parametrize("prec", [0, 1])
