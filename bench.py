@@ -34,6 +34,10 @@ Workloads (synthetic, seeded):
   fig7       the paper's Fig. 7 run (100 x 150 rotating-lid cylinder, Re 1290,
              tau = 0.005, wet-node walls, FP64): BGK until it diverges, MRT
              to the Eq. 57 residual 1e-10, the axis maximum against Table 2
+  wheeler_refine   Table 1's Re_x = 1e3 case on 100, 141, 200 and 283 nodes
+             to the residual 1e-8, then 3 M steps on 100 x 100 with the mass
+  cavity_stall   the 256 x 384 Re 990 cylinder with halfway walls, FP64 and
+             FP32, 2 M steps: residual, where it sits, its sign pattern
 """
 from __future__ import annotations
 
@@ -342,6 +346,95 @@ def wheeler_probe():
                            / r.wall_s / 1e6, 1), "cases": per}
 
 
+def wheeler_refine_probe(long_steps: int = 3_000_000):
+    """Table 1's second case (Re_x = 1e3, Re_c = -250, wet-node walls, FP64)
+    under grid refinement, each grid from rest to the Eq. (57) residual
+    1e-8, with the stream-function extrema; then the 100 x 100 lattice run on
+    with its residual, extrema and mean density (sum r rho / sum r)."""
+    import numpy as np
+    from paper_1003_0282_amd import lbaxi as L
+    from paper_1003_0282_amd import steady as ST
+    from paper_1003_0282_amd import streamfn as SF
+    from paper_1003_0282_amd import workloads as W
+    grids = (100, 141, 200, 283)
+    cases = [W.wheeler(1000.0, -250.0, n=n) for n in grids]
+    r = ST.solve(cases, tol=1e-8, max_steps=3_000_000, check_every=2000, prec=L.FP64)
+    per, off = [], 0
+    for k, c in enumerate(cases):
+        n = c["nr"] * c["nz"]
+        lo, hi = SF.wheeler_extrema(c, r.fields["uz"][off:off + n])
+        off += n
+        per.append({"n": grids[k], "tau_s": c["tau"], "status": L.STATUS_NAMES[int(r.status[k])],
+                    "steps": int(r.steps[k]), "psi_min": round(lo, 4), "psi_max": round(hi, 4)})
+    # second-order Richardson extrapolation from the pairs (100, 200), (141, 283)
+    rich = [{"from": [a["n"], b["n"]],
+             "psi_min": round(b["psi_min"] + (b["psi_min"] - a["psi_min"]) / 3.0, 4),
+             "psi_max": round(b["psi_max"] + (b["psi_max"] - a["psi_max"]) / 3.0, 4)}
+            for a, b in ((per[0], per[2]), (per[1], per[3]))]
+    c = cases[0]
+    lat = L.Lattices([c], L.FP64)
+    lat.seed()
+    rr = np.arange(c["nr"], dtype=np.float64)[:, None]
+    run, done = [], 0
+    for target in (76_000, 300_000, 1_000_000, 2_000_000, 3_000_000):
+        if target > long_steps:
+            break
+        lat.step(target - done)
+        done = target
+        m = {k: v.double().cpu().numpy().reshape(c["nr"], c["nz"]) for k, v in lat.macros().items()}
+        lo, hi = SF.wheeler_extrema(c, m["uz"])
+        run.append({"t": done, "residual": float(lat.residual()[0]), "psi_min": round(lo, 4),
+                    "psi_max": round(hi, 4),
+                    "mean_rho": float((rr * m["rho"]).sum() / (rr.sum() * c["nz"]))})
+    lat.close()
+    return {"metric": "Wheeler benchmark Re_x = 1e3 under grid refinement (Table 1: "
+                      "psi_min -1.444, psi_max 1.128)", "value": per[-1]["psi_min"], "unit": "psi/(nu R_c)",
+            "n_gpus": 1, "higher_is_better": None, "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": "wheeler_refine", "walls": "wet-node"},
+            "grids": per, "richardson": rich, "long_run_100": run}
+
+
+def cavity_stall_probe(total: int = 2_000_000, every: int = 100_000):
+    """The 256 x 384 rotating-lid cylinder at Re 990 with halfway walls from
+    rest, FP64 and FP32 storage: every `every` steps the Eq. (57) residual,
+    the node where |u| changes most between the last two levels, and at the
+    end the signs of that change around it (a period-2 pattern is a staggered
+    mode)."""
+    import numpy as np
+    from paper_1003_0282_amd import lbaxi as L
+    from paper_1003_0282_amd import workloads as W
+    out = {}
+    for prec, name in ((L.FP64, "fp64"), (L.FP32, "fp32")):
+        c = W.cavity(256, 384, 990.0)
+        lat = L.Lattices([c], prec)
+        lat.seed()
+        nr, nz = c["nr"], c["nz"]
+        rows, done, t0 = [], 0, time.perf_counter()
+        win = None
+        while done < total:
+            lat.step(every - 1)
+            m0 = {k: v.double().cpu().numpy().reshape(nr, nz) for k, v in lat.macros().items()}
+            lat.step(1)
+            done += every
+            m1 = {k: v.double().cpu().numpy().reshape(nr, nz) for k, v in lat.macros().items()}
+            d = np.hypot(m1["uz"], m1["ur"]) - np.hypot(m0["uz"], m0["ur"])
+            j, i = np.unravel_index(np.argmax(np.abs(d)), d.shape)
+            rows.append({"t": done, "residual": float(lat.residual()[0]), "i": int(i), "j": int(j)})
+            print("cavity_stall %s t=%d residual %.3e at (i=%d, j=%d) %.0fs" % (
+                name, done, rows[-1]["residual"], i, j, time.perf_counter() - t0),
+                file=sys.stderr, flush=True)
+            win = np.sign(d[max(0, j - 2):j + 3, max(0, i - 2):i + 3]).astype(int).tolist()
+        lat.close()
+        res = [x["residual"] for x in rows]
+        out[name] = {"checks": rows, "sign_window_rows_j": win,
+                     "decay_per_check_last5": round(float((res[-1] / res[-6]) ** 0.2), 4)}
+    return {"metric": "halfway-wall cylinder residual over 2 M steps", "value": out["fp32"]["checks"][-1]["residual"],
+            "unit": "Eq. 57 residual", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "cavity_stall_256x384_re990", "walls": "halfway", "every": every},
+            "runs": out}
+
+
 def fig7_probe(budget_s: float = 240.0, max_steps: int = 40_000_000):
     """Fig. 7: the rotating-lid cylinder of Table 2 at Re = 1290 with nu =
     0.005 / 3 (tau_s = 0.505).  The BGK handle runs until its residual turns
@@ -522,6 +615,12 @@ def main():
         return
     if args.workload == "fig7":
         print(json.dumps(fig7_probe(max_steps=args.max_steps or 40_000_000)))
+        return
+    if args.workload == "wheeler_refine":
+        print(json.dumps(wheeler_refine_probe()))
+        return
+    if args.workload == "cavity_stall":
+        print(json.dumps(cavity_stall_probe()))
         return
     if args.workload == "batch256_sequential":
         print(json.dumps(sequential_probe(args.steps)))

@@ -462,7 +462,22 @@ k_step(StepArgs<S> A) {
     // wet wall nodes are rebuilt by k_wall, except on the first step after
     // seeding, where they collide their seeded state like any node
     const bool wall = P.wet && wet_rule(P, nullptr, i, j, nullptr);
-    if (wall && !pre) continue;
+    if (wall && !pre) {
+      // A z-end wall node of a row that also holds fluid nodes: store a
+      // placeholder, which the wall kernel overwrites, so that this kernel
+      // writes the row's cache lines whole (lines written partly by each of
+      // two kernels cost HBM bandwidth).
+      const bool radial = (j == P.nr - 1 && P.side[NORTH].kind == SIDE_WALL) ||
+                          (j == 0 && P.side[SOUTH].kind == SIDE_WALL);
+      if (!radial) {
+        S* d = A.dst + P.off;
+        const unsigned ob = (unsigned)nidx(P, j, i) * (unsigned)sizeof(S);
+        constexpr int Q = 9 + ((F & F_SWIRL) ? 4 : 0) + ((F & F_THERMAL) ? 4 : 0);
+#pragma unroll
+        for (int a = 0; a < Q; ++a) st(ptrb(d + a * P.plane, ob), (S)0, A.nt_store);
+      }
+      continue;
+    }
     const PR<R> p = make_pr<R>(P, t);
     R f[9], g[4], h[4];
     pull_plain<S, R, F>(P, p, A.src + P.off, i, j, pre, f, g, h, !wall);
