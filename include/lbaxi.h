@@ -239,7 +239,9 @@ lbaxi_status lbaxi_batch_run(lbaxi_t* h, double tol, int64_t max_steps, int64_t 
 lbaxi_status lbaxi_resume(lbaxi_t* h, int32_t* host_resumed);
 
 /* Launch shape of the fused step kernel: tile_z x tile_r nodes per
- * workgroup (tile_z a multiple of 64, tile_z * tile_r <= 1024), grid_blocks
+ * workgroup (tile_z a power of two >= 64, tile_z * tile_r <= 1024, or <= 512
+ * on a handle with wet-node walls, whose step kernel also rebuilds the
+ * z-end wall nodes; EINVAL otherwise), grid_blocks
  * persistent workgroups (0 = one workgroup per tile), xcd_aware = 1 gives
  * each of the 8 XCDs a contiguous band of tiles, nt_store = 1 uses
  * non-temporal stores for the populations. */

@@ -118,8 +118,9 @@ __device__ inline void pull_plain(const InstP& P, const PR<R>& p, const S* s, in
   }
   load_node<S, R, F>(P, s, i, j, pre, f, g, h);
   if ((F & F_SWIRL) && axis_row) {
+    // at the storage precision, like every population the step reads
 #pragma unroll
-    for (int a = 0; a < 4; ++a) g[a] = gn[a];
+    for (int a = 0; a < 4; ++a) g[a] = (R)(S)gn[a];
   }
 }
 
@@ -327,12 +328,15 @@ __device__ inline Row<R> uni_row(Row<R> w) {
 }
 
 // Macros, collision and store of one pulled node.  uniform_row: j is the
-// same on every lane of the wave.  The swirl and temperature populations are
+// same on every lane of the wave; stored: f, g, h hold the values as loaded
+// from storage (not a rebuilt wall node).  The swirl and temperature
+// populations are
 // collided and stored before f is collided, so that they are not live
 // through the f collision.
 template <typename S, typename R, int F>
 __device__ inline void finish_node(const StepArgs<S>& A, const InstP& P, const PR<R>& p, int i,
-                                   int j, R* f, R* g, R* h, bool uniform_row = false) {
+                                   int j, R* f, R* g, R* h, bool uniform_row = false,
+                                   bool stored = false) {
   const bool axis_row = (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
   const Row<R> rw = uniform_row ? uni_row<R, F>(make_row<R, F>(p, __builtin_amdgcn_readfirstlane(j)))
                                 : make_row<R, F>(p, j);
@@ -346,8 +350,9 @@ __device__ inline void finish_node(const StepArgs<S>& A, const InstP& P, const P
     S* ld = A.lag_dst + P.off_fld + (long long)j * P.nz + i;
     ld[0] = (S)m.uz;
     ld[A.lag_stride] = (S)m.ur;
-  } else if (sizeof(S) < sizeof(R)) {
-    // float storage: only the floats stay live across the macros.  The
+  } else if (sizeof(S) < sizeof(R) && stored) {
+    // float storage, populations as loaded: only the floats stay live
+    // across the macros.  The
     // empty asm makes each float opaque to the compiler, so the collision
     // converts it again instead of keeping the double (2 VGPRs) alive.
     float fl[9], gl[4], hl[4];
@@ -437,17 +442,31 @@ __device__ inline void perimeter_node(const InstP& P, int p, int& i, int& j) {
 
 // One time step: pull (padded planes, no boundary tests), macros, collision,
 // store at the node's own slots of the other buffer.  The halo kernel then
-// completes the boundary rules for the next pull.
+// completes the boundary rules for the next pull.  F_WETZ (handles with
+// wet-node walls): the z-end wall nodes of rows that also hold fluid nodes
+// are rebuilt here, by their own lanes, from the inner neighbour that the
+// same wave has just pulled (its lines are in the cache), so that the wall
+// kernel is left only the radial wall rows; without it they are left to the
+// wall kernel.
 // Waves per SIMD the step kernel is compiled for: five (at most 96 VGPRs)
 // where the field set fits without spilling, four (128) for swirl together
 // with temperature or with MRT.
 constexpr int step_waves(int F) {
-  return ((F & F_SWIRL) && (F & (F_THERMAL | F_MRT))) ? 4 : 5;
+  return (F & F_WETZ) ? 3 : ((F & F_SWIRL) && (F & (F_THERMAL | F_MRT))) ? 4 : 5;
 }
 
+__device__ inline bool radial_wall_row(const InstP& P, int j) {
+  return (j == P.nr - 1 && P.side[NORTH].kind == SIDE_WALL) ||
+         (j == 0 && P.side[SOUTH].kind == SIDE_WALL);
+}
+
+// Largest workgroup of the step kernel: 512 threads where the z-end wall
+// rebuild is inlined (it needs up to 168 VGPRs at three waves per SIMD).
+constexpr int step_block_max(int F) { return (F & F_WETZ) ? 512 : 1024; }
+
 template <typename S, typename R, int F>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(step_waves(F))))
-k_step(StepArgs<S> A) {
+__global__ void __launch_bounds__(step_block_max(F))
+    __attribute__((amdgpu_waves_per_eu(step_waves(F)))) k_step(StepArgs<S> A) {
   const long long t = A.tdev ? (*A.tdev + A.k) : A.t0;
   const int ntiles = *A.ntiles;
   const TileRange tr = tile_range(ntiles, A.xcd);
@@ -459,17 +478,18 @@ k_step(StepArgs<S> A) {
     const InstP P = cload(A.ip + T.inst);
     const int i = T.z0 + li, j = T.r0 + lj;
     if (i >= P.nz || j >= P.nr) continue;
-    // wet wall nodes are rebuilt by k_wall, except on the first step after
-    // seeding, where they collide their seeded state like any node
+    // wet wall nodes are rebuilt after the pull (here or by k_wall), except
+    // on the first step after seeding, where they collide their seeded state
+    // like any node
+    constexpr int FB = F & ~F_WETZ;
     const bool wall = P.wet && wet_rule(P, nullptr, i, j, nullptr);
-    if (wall && !pre) {
-      // A z-end wall node of a row that also holds fluid nodes: store a
-      // placeholder, which the wall kernel overwrites, so that this kernel
-      // writes the row's cache lines whole (lines written partly by each of
-      // two kernels cost HBM bandwidth).
-      const bool radial = (j == P.nr - 1 && P.side[NORTH].kind == SIDE_WALL) ||
-                          (j == 0 && P.side[SOUTH].kind == SIDE_WALL);
-      if (!radial) {
+    const bool rebuild = wall && !pre;
+    if (rebuild && (!(F & F_WETZ) || radial_wall_row(P, j))) {
+      // left to the wall kernel.  A z-end wall node of a row that also holds
+      // fluid nodes gets a placeholder, which the wall kernel overwrites, so
+      // that this kernel writes the row's cache lines whole (lines written
+      // partly by each of two kernels cost HBM bandwidth).
+      if (!radial_wall_row(P, j)) {
         S* d = A.dst + P.off;
         const unsigned ob = (unsigned)nidx(P, j, i) * (unsigned)sizeof(S);
         constexpr int Q = 9 + ((F & F_SWIRL) ? 4 : 0) + ((F & F_THERMAL) ? 4 : 0);
@@ -480,8 +500,14 @@ k_step(StepArgs<S> A) {
     }
     const PR<R> p = make_pr<R>(P, t);
     R f[9], g[4], h[4];
-    pull_plain<S, R, F>(P, p, A.src + P.off, i, j, pre, f, g, h, !wall);
-    finish_node<S, R, F>(A, P, p, i, j, f, g, h, true);
+    if ((F & F_WETZ) && rebuild) {
+      WetRule w;
+      wet_rule(P, A.ip + T.inst, i, j, &w);
+      wall_state<S, R, FB>(P, p, A.src + P.off, i, j, w, f, g, h);
+    } else {
+      pull_plain<S, R, FB>(P, p, A.src + P.off, i, j, pre, f, g, h, !wall);
+    }
+    finish_node<S, R, FB>(A, P, p, i, j, f, g, h, true, !(F & F_WETZ));
   }
 }
 
@@ -500,6 +526,9 @@ __global__ void __launch_bounds__(256) k_wall(StepArgs<S> A) {
   if (q >= 2 * P.nz + 2 * (P.nr - 2)) return;
   int i, j;
   perimeter_node(P, q, i, j);
+  // with MODE_WETZ the step kernel has rebuilt every wall node off the
+  // radial wall rows
+  if ((A.mode & MODE_WETZ) && !radial_wall_row(P, j)) return;
   WetRule w;
   if (!wet_rule(P, A.ip + T.inst, i, j, &w)) return;
   const long long t = A.tdev ? (*A.tdev + A.k) : A.t0;
@@ -1105,6 +1134,13 @@ lbaxi_status upload_dyn(lbaxi_t* h) {
 template <typename S, typename R, int F>
 void* step_fn() { return reinterpret_cast<void*>(&k_step<S, R, F>); }
 template <typename S, typename R, int F>
+void* step_fn_wetz() {  // the original scheme has no wet-node walls
+  if constexpr ((F & F_ORIG) != 0)
+    return step_fn<S, R, F>();
+  else
+    return reinterpret_cast<void*>(&k_step<S, R, F | F_WETZ>);
+}
+template <typename S, typename R, int F>
 void* halo_fn() { return reinterpret_cast<void*>(&k_halo<S, F & 3>); }  // no collision
 template <typename S, typename R, int F>
 void* wall_fn() { return reinterpret_cast<void*>(&k_wall<S, R, F>); }
@@ -1142,7 +1178,9 @@ struct StepLaunch {
 StepLaunch step_launch(lbaxi_t* h, int list, int from, long long t0, bool use_tdev, int k,
                        int mode) {
   StepLaunch L;
-  L.fn = PICK(step_fn, h->prec, h->fields);
+  const bool wetz = h->any_wet && !(h->fields & LBAXI_ORIGINAL);
+  L.fn = wetz ? PICK(step_fn_wetz, h->prec, h->fields) : PICK(step_fn, h->prec, h->fields);
+  if (wetz) mode |= MODE_WETZ;
   L.block = h->tz * h->tr;
   L.grid = h->grid > 0 ? std::min(h->grid, std::max(1, h->count[list]))
                        : std::max(1, h->count[list]);
@@ -1711,6 +1749,8 @@ lbaxi_status lbaxi_set_launch(lbaxi_t* h, int32_t tile_z, int32_t tile_r, int32_
   if (tile_z < 64 || (tile_z & (tile_z - 1)) || tile_r < 1 || tile_z * tile_r > 1024 ||
       grid_blocks < 0)
     return fail(LBAXI_EINVAL, "tile_z must be a power of two >= 64, tile_z*tile_r <= 1024");
+  if (h->any_wet && !(h->fields & LBAXI_ORIGINAL) && tile_z * tile_r > 512)
+    return fail(LBAXI_EINVAL, "handles with wet-node walls take tile_z*tile_r <= 512");
   h->tz = tile_z;
   h->tr = tile_r;
   h->grid = grid_blocks;

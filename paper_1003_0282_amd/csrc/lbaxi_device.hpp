@@ -17,8 +17,8 @@ namespace lbx {
 
 enum { SIDE_AXIS = 0, SIDE_WALL = 1, SIDE_PERIODIC = 2, SIDE_FREESLIP = 3 };
 enum { SOUTH = 0, NORTH = 1, WEST = 2, EAST = 3 };
-enum { F_SWIRL = 1, F_THERMAL = 2, F_MRT = 4, F_ORIG = 8 };
-enum { MODE_PRE = 1, MODE_SPEED = 2 };
+enum { F_SWIRL = 1, F_THERMAL = 2, F_MRT = 4, F_ORIG = 8, F_WETZ = 16 };
+enum { MODE_PRE = 1, MODE_SPEED = 2, MODE_WETZ = 4 };
 
 struct SideP {
   int kind, thermal, kind2, thermal2;
