@@ -1031,8 +1031,9 @@ WgShape wgrad_shape(int Ck, int co, int B, int H, int W) {
     S.cob = co / 32;
     const long long nseg = (long long)B * H * (W / WR_TW);
     const long long tiles = (long long)S.cib * S.cob;
-    // about 1024 workgroups, each at least 4 segments long
-    S.chunk = (int)std::max<long long>(4, (nseg * tiles + 1023) / 1024);
+    // about 512 workgroups, each at least 4 segments long (fewer chunks:
+    // less partial-sum traffic for the fixed-order reduction)
+    S.chunk = (int)std::max<long long>(4, (nseg * tiles + 511) / 512);
     S.gx = (nseg + S.chunk - 1) / S.chunk;
     S.gy = tiles;
   } else {
@@ -1041,9 +1042,9 @@ WgShape wgrad_shape(int Ck, int co, int B, int H, int W) {
     S.cib = (Ck + 32 * S.MB - 1) / (32 * S.MB);
     S.cob = co / (32 * S.NB);
     const long long tiles = 9LL * S.cib * S.cob;
-    // about 2048 workgroups, each at least one and at most 64 stages long
+    // about 1024 workgroups, each at least one and at most 64 stages long
     const int sp = wg_sp(S.MB, S.NB);
-    long long ch = (npix * tiles + 2047) / 2048;
+    long long ch = (npix * tiles + 1023) / 1024;
     ch = std::max<long long>(sp, std::min<long long>(64LL * sp, ch));
     S.chunk = (int)((ch + sp - 1) / sp * sp);
     S.gx = blocks(npix, S.chunk);
