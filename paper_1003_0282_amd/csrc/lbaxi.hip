@@ -102,25 +102,31 @@ __device__ inline void st(S* p, S v, int nt) {
 // populations are replaced by the non-equilibrium extrapolation of row 1
 // (Sec. IV B), computed before the node's own pull so that the two
 // population sets are never live together.
+// Swirl populations of axis node (i, 0): the non-equilibrium part of row 1
+// (Sec. IV B), g(i,0) = g(i,1) - g_eq(i,1) with row 1's macros, taken at the
+// storage precision like every population the step reads.
+template <typename S, typename R, int F>
+__device__ inline void axis_swirl(const InstP& P, const PR<R>& p, const S* s, int i, bool pre,
+                                  R* gn) {
+  R f1[9], g1[4], h1[4];
+  load_node<S, R, F>(P, s, i, 1, pre, f1, g1, h1);
+  const Mac<R> m1 = macros<R, F>(p, make_row<R, F>(p, 1), false, f1, g1, h1);
+  const R q = (R)0.25 * p.rho0 * m1.uth;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+    gn[a] = (R)(S)(g1[a] - q * ((R)1 + (R)2 * ((R)ez4(a) * m1.uz + (R)er4(a) * m1.ur)));
+}
+
 template <typename S, typename R, int F>
 __device__ inline void pull_plain(const InstP& P, const PR<R>& p, const S* s, int i, int j,
                                   bool pre, R* f, R* g, R* h, bool axis_g = true) {
   const bool axis_row = axis_g && (j == 0) && (P.side[SOUTH].kind == SIDE_AXIS);
   R gn[4];
-  if ((F & F_SWIRL) && axis_row) {
-    R f1[9], g1[4], h1[4];
-    load_node<S, R, F>(P, s, i, 1, pre, f1, g1, h1);
-    const Mac<R> m1 = macros<R, F>(p, make_row<R, F>(p, 1), false, f1, g1, h1);
-    const R q = (R)0.25 * p.rho0 * m1.uth;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-      gn[a] = g1[a] - q * ((R)1 + (R)2 * ((R)ez4(a) * m1.uz + (R)er4(a) * m1.ur));
-  }
+  if ((F & F_SWIRL) && axis_row) axis_swirl<S, R, F>(P, p, s, i, pre, gn);
   load_node<S, R, F>(P, s, i, j, pre, f, g, h);
   if ((F & F_SWIRL) && axis_row) {
-    // at the storage precision, like every population the step reads
 #pragma unroll
-    for (int a = 0; a < 4; ++a) g[a] = (R)(S)gn[a];
+    for (int a = 0; a < 4; ++a) g[a] = gn[a];
   }
 }
 
@@ -446,8 +452,8 @@ __device__ inline void perimeter_node(const InstP& P, int p, int& i, int& j) {
 // wet-node walls): the z-end wall nodes of rows that also hold fluid nodes
 // are rebuilt here, by their own lanes, from the inner neighbour that the
 // same wave has just pulled (its lines are in the cache), so that the wall
-// kernel is left only the radial wall rows; without it they are left to the
-// wall kernel.
+// kernel is left only the radial wall rows and every row off them is
+// written whole by this kernel.
 // Waves per SIMD the step kernel is compiled for: five (at most 96 VGPRs)
 // where the field set fits without spilling, four (128) for swirl together
 // with temperature or with MRT.
@@ -478,26 +484,14 @@ __global__ void __launch_bounds__(step_block_max(F))
     const InstP P = cload(A.ip + T.inst);
     const int i = T.z0 + li, j = T.r0 + lj;
     if (i >= P.nz || j >= P.nr) continue;
-    // wet wall nodes are rebuilt after the pull (here or by k_wall), except
-    // on the first step after seeding, where they collide their seeded state
-    // like any node
+    // wet wall nodes (only in the F_WETZ instance, which every handle with
+    // wet-node walls uses) are rebuilt after the pull, the z-end ones here
+    // and those of the radial wall rows by k_wall, except on the first step
+    // after seeding, where they collide their seeded state like any node
     constexpr int FB = F & ~F_WETZ;
-    const bool wall = P.wet && wet_rule(P, nullptr, i, j, nullptr);
+    const bool wall = (F & F_WETZ) && P.wet && wet_rule(P, nullptr, i, j, nullptr);
     const bool rebuild = wall && !pre;
-    if (rebuild && (!(F & F_WETZ) || radial_wall_row(P, j))) {
-      // left to the wall kernel.  A z-end wall node of a row that also holds
-      // fluid nodes gets a placeholder, which the wall kernel overwrites, so
-      // that this kernel writes the row's cache lines whole (lines written
-      // partly by each of two kernels cost HBM bandwidth).
-      if (!radial_wall_row(P, j)) {
-        S* d = A.dst + P.off;
-        const unsigned ob = (unsigned)nidx(P, j, i) * (unsigned)sizeof(S);
-        constexpr int Q = 9 + ((F & F_SWIRL) ? 4 : 0) + ((F & F_THERMAL) ? 4 : 0);
-#pragma unroll
-        for (int a = 0; a < Q; ++a) st(ptrb(d + a * P.plane, ob), (S)0, A.nt_store);
-      }
-      continue;
-    }
+    if (rebuild && radial_wall_row(P, j)) continue;
     const PR<R> p = make_pr<R>(P, t);
     R f[9], g[4], h[4];
     if ((F & F_WETZ) && rebuild) {
