@@ -241,7 +241,8 @@ lbaxi_status lbaxi_resume(lbaxi_t* h, int32_t* host_resumed);
 /* Launch shape of the fused step kernel: tile_z x tile_r nodes per
  * workgroup (tile_z a power of two >= 64, tile_z * tile_r <= 1024, or <= 512
  * on a handle with wet-node walls, whose step kernel also rebuilds the
- * z-end wall nodes; EINVAL otherwise), grid_blocks
+ * z-end wall nodes; EINVAL otherwise; default 64 x 4, or 128 x 1 on a
+ * handle with wet-node walls), grid_blocks
  * persistent workgroups (0 = one workgroup per tile), xcd_aware = 1 gives
  * each of the 8 XCDs a contiguous band of tiles, nt_store = 1 uses
  * non-temporal stores for the populations. */

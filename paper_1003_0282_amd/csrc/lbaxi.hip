@@ -1509,6 +1509,13 @@ lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace,
   h->fields = descs[0].fields;
   for (int k = 0; k < n; ++k)
     if (descs[k].fields & LBAXI_WET_WALLS) h->any_wet = true;
+  // default launch shape: 64 x 4 tiles; 128 x 1 where the step kernel's
+  // wet-wall instance runs at three waves per SIMD (20 % faster there on
+  // the 512 wet melts)
+  if (h->any_wet && !(h->fields & LBAXI_ORIGINAL)) {
+    h->tz = 128;
+    h->tr = 1;
+  }
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
   h->ws = static_cast<char*>(d_workspace);
   h->L = layout(h->desc);
