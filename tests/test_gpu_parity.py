@@ -187,6 +187,35 @@ def test_launch_shape_bitwise(launch):
         assert np.array_equal(ref[k], got[k]), k
 
 
+@pytest.mark.parametrize("launch", [(128, 1, 0, 0, 1), (64, 8, 0, 0, 0), (128, 4, 0, 0, 1),
+                                    (64, 2, 96, 1, 1)])
+def test_wet_launch_shape_bitwise(launch):
+    """Wet-node walls: the step kernel's wet instance (z-end walls rebuilt in
+    the step kernel, radial wall rows in the wall kernel) gives the same FP64
+    bits for every workgroup shape it accepts (at most 512 threads), a
+    persistent XCD-banded grid included."""
+    case = CASES["melt_wet"]()
+    fields = _fields(case, 12)
+    ref = to_np(gpu_run([case], 201, 0, [fields]).macros())
+    got = to_np(gpu_run([case], 201, 0, [fields], launch=launch).macros())
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), k
+
+
+def test_wet_handles_reject_workgroups_above_512():
+    from paper_1003_0282_amd import lbaxi as L
+    lat = L.Lattices([CASES["cavity_wet"]()], 0)
+    with pytest.raises(L.LbaxiError) as err:
+        lat.set_launch(256, 4, 0, 0, 1)
+    assert "512" in str(err.value)
+    lat.set_launch(256, 2, 0, 0, 1)
+    assert tuple(lat.get_launch()[:2]) == (256, 2)
+    lat.close()
+    dry = L.Lattices([CASES["cavity"]()], 0)
+    dry.set_launch(256, 4, 0, 0, 1)  # halfway walls: up to 1024 threads
+    dry.close()
+
+
 def test_graph_vs_direct_bitwise():
     case = CASES["pipe_periodic_force"]()
     fields = _fields(case, 12)
