@@ -211,7 +211,8 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs A) {
 // row is read from memory once per stage instead of once per tap.  The 4
 // waves form a (TW / 32) x WCH grid, each owning 32 pixels x NW blocks of 32
 // channels, and run 9 taps x 2 K-steps x NW MFMAs per stage.
-constexpr int RW_KC = 32;               // input channels per stage
+constexpr int RW_KC = 32;               // input channels per stage (two K-steps of 16)
+static_assert(RW_KC == 32, "the weight tile's fragment order assumes 32 channels per stage");
 constexpr int RW_RS = RW_KC + 8;        // LDS row stride (elements): 80 bytes
 
 template <int TW, int NT>
@@ -223,7 +224,11 @@ __global__ void __launch_bounds__(256) k_conv_row(ConvArgs A) {
   constexpr int NWT = 9 * NT * (RW_KC / 8);       // 16-byte loads of the weights
   constexpr int LPT = (NH + NWT + 255) / 256;
   __shared__ __attribute__((aligned(16))) bf16s sh[3 * HX * RW_RS];
-  __shared__ __attribute__((aligned(16))) bf16s sw[9 * NT * RW_RS];
+  // weights in the MFMA's B-fragment order, unpadded: for tap t, block jb of
+  // 32 output channels and K-step kk, lane (m, g) reads its 8 channels at
+  // ((t * NT / 32 + jb) * 2 + kk) * 512 + (32 g + m) * 8, so a wave's 64
+  // 16-byte reads are one contiguous 1 KB (no bank conflicts, no padding)
+  __shared__ __attribute__((aligned(16))) bf16s sw[9 * NT * RW_KC];
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, m = l & 31, g = l >> 5;
   const int wp = wave % WPX, wc = wave / WPX;
   const int segs = A.W / TW;
@@ -264,8 +269,11 @@ __global__ void __launch_bounds__(256) k_conv_row(ConvArgs A) {
       const int e = tid + 256 * k;
       if (e < NH)
         *reinterpret_cast<u16x8*>(sh + (e >> 2) * RW_RS + 8 * (e & 3)) = r[k];
-      else if (e < NH + NWT)
-        *reinterpret_cast<u16x8*>(sw + ((e - NH) >> 2) * RW_RS + 8 * ((e - NH) & 3)) = r[k];
+      else if (e < NH + NWT) {
+        const int f = e - NH, t = f / (NT * 4), rem = f - t * (NT * 4), nn = rem >> 2, q = rem & 3;
+        *reinterpret_cast<u16x8*>(sw + ((t * (NT / 32) + (nn >> 5)) * 2 + (q >> 1)) * 512 +
+                                  ((q & 1) * 32 + (nn & 31)) * 8) = r[k];
+      }
     }
     __syncthreads();
     if (st + 1 < S) load(st + 1);
@@ -279,7 +287,7 @@ __global__ void __launch_bounds__(256) k_conv_row(ConvArgs A) {
         const u16x8 a = *reinterpret_cast<const u16x8*>(ap + 16 * kk);
 #pragma unroll
         for (int j = 0; j < NW; ++j) {
-          const bf16s* bp = sw + (t * NT + (wc * NW + j) * 32 + m) * RW_RS + 8 * g + 16 * kk;
+          const bf16s* bp = sw + ((t * (NT / 32) + wc * NW + j) * 2 + kk) * 512 + (32 * g + m) * 8;
           acc[j] = mfma(a, *reinterpret_cast<const u16x8*>(bp), acc[j]);
         }
       }
