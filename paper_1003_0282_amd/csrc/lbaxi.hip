@@ -1509,9 +1509,11 @@ lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace,
   h->fields = descs[0].fields;
   for (int k = 0; k < n; ++k)
     if (descs[k].fields & LBAXI_WET_WALLS) h->any_wet = true;
-  // default launch shape: 64 x 4 tiles; 128 x 1 where the step kernel's
-  // wet-wall instance runs at three waves per SIMD (20 % faster there on
-  // the 512 wet melts)
+  // default launch shape: 64 x 4 tiles (one wave along z, 4 rows); 128 x 1
+  // where the step kernel's wet-wall instance runs at three waves per SIMD
+  // (20 % faster there on the 512 wet melts)
+  h->tz = 64;
+  h->tr = 4;
   if (h->any_wet && !(h->fields & LBAXI_ORIGINAL)) {
     h->tz = 128;
     h->tr = 1;
@@ -1546,8 +1548,8 @@ lbaxi_status lbaxi_create(int32_t n, const lbaxi_desc* descs, void* d_workspace,
     delete h;
     return fail(LBAXI_EDEVICE, std::string("create: ") + hipGetErrorString(e));
   }
-  // default launch shape: one wave along z, 4 rows, one workgroup per tile
-  st = lbaxi_set_launch(h, 64, 4, 0, 0, 1);
+  // default launch shape (set above): one workgroup per tile
+  st = lbaxi_set_launch(h, h->tz, h->tr, 0, 0, 1);
   if (st == LBAXI_OK) st = lbaxi_seed(h, nullptr, nullptr, nullptr, nullptr, nullptr);
   if (st != LBAXI_OK) {
     lbaxi_destroy(h);
