@@ -358,9 +358,9 @@ __device__ inline void finish_node(const StepArgs<S>& A, const InstP& P, const P
     ld[A.lag_stride] = (S)m.ur;
   } else if (sizeof(S) < sizeof(R) && stored) {
     // float storage, populations as loaded: only the floats stay live
-    // across the macros.  The
-    // empty asm makes each float opaque to the compiler, so the collision
-    // converts it again instead of keeping the double (2 VGPRs) alive.
+    // across the macros.  The empty asm makes each float opaque to the
+    // compiler, so the collision converts it again instead of keeping the
+    // double (2 VGPRs) alive.
     float fl[9], gl[4], hl[4];
     R fa[9], ga[4], ha[4];
 #pragma unroll
@@ -446,17 +446,9 @@ __device__ inline void perimeter_node(const InstP& P, int p, int& i, int& j) {
   i = nz - 1; j = 1 + p;
 }
 
-// One time step: pull (padded planes, no boundary tests), macros, collision,
-// store at the node's own slots of the other buffer.  The halo kernel then
-// completes the boundary rules for the next pull.  F_WETZ (handles with
-// wet-node walls): the z-end wall nodes of rows that also hold fluid nodes
-// are rebuilt here, by their own lanes, from the inner neighbour that the
-// same wave has just pulled (its lines are in the cache), so that the wall
-// kernel is left only the radial wall rows and every row off them is
-// written whole by this kernel.
 // Waves per SIMD the step kernel is compiled for: five (at most 96 VGPRs)
 // where the field set fits without spilling, four (128) for swirl together
-// with temperature or with MRT.
+// with temperature or with MRT, three (168) for the wet-wall instance.
 constexpr int step_waves(int F) {
   return (F & F_WETZ) ? 3 : ((F & F_SWIRL) && (F & (F_THERMAL | F_MRT))) ? 4 : 5;
 }
@@ -470,6 +462,14 @@ __device__ inline bool radial_wall_row(const InstP& P, int j) {
 // rebuild is inlined (it needs up to 168 VGPRs at three waves per SIMD).
 constexpr int step_block_max(int F) { return (F & F_WETZ) ? 512 : 1024; }
 
+// One time step: pull (padded planes, no boundary tests), macros, collision,
+// store at the node's own slots of the other buffer.  The halo kernel then
+// completes the boundary rules for the next pull.  F_WETZ (handles with
+// wet-node walls): the z-end wall nodes of rows that also hold fluid nodes
+// are rebuilt here, by their own lanes, from the inner neighbour that the
+// same wave has just pulled (its lines are in the cache), so that the wall
+// kernel is left only the radial wall rows and every row off them is
+// written whole by this kernel.
 template <typename S, typename R, int F>
 __global__ void __launch_bounds__(step_block_max(F))
     __attribute__((amdgpu_waves_per_eu(step_waves(F)))) k_step(StepArgs<S> A) {
