@@ -128,6 +128,25 @@ def test_training_is_bitwise_reproducible():
     assert np.array_equal(runs[0][1], runs[1][1])
 
 
+def test_forward_does_not_depend_on_the_batch():
+    """Each output pixel sees the same operands in the same accumulation
+    order whatever the batch size (and so whatever grid and tile shapes the
+    launch picks), so a sample's output is the same bits in a batch of 2 and
+    in a batch of 16.  The batch-2 forward is checked against the oracle
+    above."""
+    import torch
+    from paper_1003_0282_amd import lbnn
+    net, p, names, x, t, xd, td = _setup(128, 256, 2, 8, 5, seed=9)
+    big = lbnn.Net(128, 256, 8, 5, WIDTHS, max_batch=16)
+    big.set_params(net.get_params())
+    rng = np.random.default_rng(10)
+    x16 = torch.tensor(rng.standard_normal((16, 128, 256, 8)), dtype=torch.float32, device="cuda")
+    x16[5:7] = xd
+    y16 = big.forward(x16).cpu().numpy()
+    y2 = net.forward(xd).cpu().numpy()
+    assert np.array_equal(y16[5:7], y2)
+
+
 def test_training_reduces_loss():
     import torch
     net, p, names, x, t, xd, td = _setup(seed=2)
