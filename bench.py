@@ -589,7 +589,7 @@ def main():
                     help="time steps per autotuner trial (real steps: the state advances)")
     ap.add_argument("--launch", default="", help="tile_z,tile_r,grid,xcd,nt (skips autotune)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--tts-melts", type=int, default=16,
+    ap.add_argument("--tts-melts", type=int, default=128,
                     help="melts of the time-to-steady leg of the default line (0: skip)")
     ap.add_argument("--kernel-steps", type=int, default=100,
                     help="steps timed kernel by kernel for the roofline figure")
