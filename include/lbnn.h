@@ -6,7 +6,7 @@
  * kernels (BF16 MFMA with FP32 accumulation).  Its prediction seeds the
  * populations at equilibrium (lbaxi_seed, which follows Eqs. 6 and 54 of
  * Li, He, Tang, Tao, arXiv:1003.0282); the lattice Boltzmann run to the
- * Eq. (57) residual stays the judge of its error.  The network itself is not
+ * Eq. (57) residual stays the measure of its error.  The network itself is not
  * part of the paper.
  *
  * Network (tensors NHWC, H = nr rows along r, W = nz columns along z):
