@@ -212,14 +212,16 @@ def experiment(n_train=256, n_eval=16, nr=128, nz=256, re_max=1000.0, tol=1e-8,
                seed_train=2, seed_eval=1, tols=(1e-6, 3e-7, 1e-7, 3e-8, 1e-8),
                errs=(0.1, 0.03, 0.01, 0.003), out_dir=None, smooth_variants=(True,), wet=False,
                ref_tol=1e-10, ref_steps=2_000_000, ref_budget_s=None, log=print,
-               load_model_path=None, save_model_path=None):
+               load_model_path=None, save_model_path=None, gen_init_path=None):
     """Generate steady training fields with the batched solver, train the
     network on them, then solve held-out cases from rest and from the
     prediction and compare the time to each residual tolerance and to each
     distance from reference steady fields (an FP64 run to ref_tol), and the
     distance of each run's final field from that reference.  With
     load_model_path the generation and training are skipped (a model saved
-    by save_model_path is used); with n_eval = 0 the evaluation is."""
+    by save_model_path is used); with n_eval = 0 the evaluation is.  With
+    gen_init_path the training melts are solved from that model's prediction
+    rather than from rest."""
     import torch
     res = {"config": dict(n_train=n_train, n_eval=n_eval, nr=nr, nz=nz, re_max=re_max, tol=tol,
                           gen_steps=gen_steps, eval_steps=eval_steps, train_steps=train_steps,
@@ -234,7 +236,7 @@ def experiment(n_train=256, n_eval=16, nr=128, nz=256, re_max=1000.0, tol=1e-8,
     else:
         net, sc = _generate_and_train(res, n_train, nr, nz, re_max, tol, gen_steps, train_steps,
                                       batch, lr, gen_budget_s, train_budget_s, check_every,
-                                      seed_train, wet, log)
+                                      seed_train, wet, log, gen_init_path)
         if save_model_path:
             save_model(save_model_path, net, sc,
                        dict(nr=nr, nz=nz, re_max=re_max, wet=wet, seed_train=seed_train,
@@ -248,13 +250,25 @@ def experiment(n_train=256, n_eval=16, nr=128, nz=256, re_max=1000.0, tol=1e-8,
 
 
 def _generate_and_train(res, n_train, nr, nz, re_max, tol, gen_steps, train_steps, batch, lr,
-                        gen_budget_s, train_budget_s, check_every, seed_train, wet, log):
+                        gen_budget_s, train_budget_s, check_every, seed_train, wet, log,
+                        gen_init_path=None):
     import torch
     tr = W.melt_set(n_train, seed_train, nr=nr, nz=nz, re_max=re_max, wet=wet)
     rho0, T_ref = tr[0]["rho0"], tr[0]["T_ref"]
 
-    g = solve(tr, tol=tol, max_steps=gen_steps, check_every=check_every, budget_s=gen_budget_s,
-              log=log, tag="gen")
+    # the training fields are steady states of the solver; with gen_init_path
+    # the solver starts from an earlier model's prediction instead of rest
+    # (it still runs every melt to the residual tol, so the fields are its
+    # own steady states, reached in fewer steps)
+    init = None
+    if gen_init_path:
+        net0, sc0, meta0 = load_model(gen_init_path, max_batch=batch)
+        assert (meta0["nr"], meta0["nz"]) == (nr, nz), "model trained on another lattice size"
+        init = predict(net0, torch.tensor(features(tr), device="cuda"), sc0, smooth=True)
+        del net0
+    g = solve(tr, init=init, tol=tol, max_steps=gen_steps, check_every=check_every,
+              budget_s=gen_budget_s, log=log, tag="gen")
+    del init
     keep = np.flatnonzero(g.status != L.DIVERGED)
     res["generate"] = dict(wall_s=g.wall_s, converged=int((g.status == L.CONVERGED).sum()),
                            capped=int((g.status == L.CAPPED).sum()),
@@ -262,7 +276,7 @@ def _generate_and_train(res, n_train, nr, nz, re_max, tol, gen_steps, train_step
                            steps_median=float(np.median(g.steps)),
                            residual_median_kept=float(np.nanmedian(g.residual[keep])),
                            residual_max_kept=float(np.nanmax(g.residual[keep])),
-                           node_steps=float(g.steps.sum()) * nr * nz)
+                           node_steps=float(g.steps.sum()) * nr * nz, init_model=gen_init_path)
     hw = nr * nz
     sc = Scales.fit({k: np.concatenate([g.fields[k][i * hw:(i + 1) * hw] for i in keep])
                      for k in FIELDS}, rho0, T_ref)
@@ -358,6 +372,8 @@ def main(argv=None):
     ap.add_argument("--save-model", default=None, help="write the trained model (.npz) here")
     ap.add_argument("--load-model", default=None,
                     help="skip generation and training: evaluate this saved model")
+    ap.add_argument("--gen-init-model", default=None,
+                    help="solve the training melts from this saved model's prediction")
     a = ap.parse_args(argv)
     variants = tuple(v == "smooth" for v in a.variants.split(","))
     r = experiment(a.n_train, a.n_eval, a.nr, a.nz, a.re_max, a.tol, a.gen_steps, a.eval_steps,
@@ -365,7 +381,7 @@ def main(argv=None):
                    check_every=a.check_every, out_dir=a.out, smooth_variants=variants, wet=a.wet,
                    ref_tol=a.ref_tol, ref_steps=a.ref_steps, ref_budget_s=a.ref_budget,
                    log=lambda s: print(s, flush=True), load_model_path=a.load_model,
-                   save_model_path=a.save_model)
+                   save_model_path=a.save_model, gen_init_path=a.gen_init_model)
     print(json.dumps({k: r[k] for k in ("generate", "train")}))
     if a.out and "eval" not in r:
         os.makedirs(a.out, exist_ok=True)
