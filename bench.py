@@ -314,7 +314,9 @@ def time_to_steady_leg(n_melts: int, tol: float = 1e-8):
             "steps_median_warm": float(np.median(w.steps)),
             "converged_from_rest": ok(z), "converged_warm": ok(w), "lattices": n_melts,
             "end_state_difference_median": float(np.median(diff)),
-            "model": "trained on %d solver-generated fields (seed 2)" % meta.get("n_train", 0)}
+            "model": "trained on %d solver-generated steady fields (seed 2, %d reached the "
+                     "residual 1e-8)" % (meta.get("n_train", 0),
+                                         meta.get("generate", {}).get("converged", 0))}
 
 
 def wheeler_probe():
