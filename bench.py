@@ -8,7 +8,9 @@ the boundary rules, macros, collision of f, g and h as the workload has
 them), run through the C-ABI library.  The timed region is exactly K steps
 between two device synchronisations, inputs resident in HBM.  Prints one JSON
 line with MLUPS, the HBM-roofline fraction of the step kernel and the CPU
-oracle timed on a bounded sample of the same workload.
+oracle timed on a bounded sample of the same workload; the default workload's
+line also carries the time to the Eq. 57 residual 1e-8 of 128 held-out melts
+from rest and from the learned warm start (`time_to_steady`).
 
 Workloads (synthetic, seeded):
   batch256   256 rotating-lid cavities, Nr ~ U{64..512}, H/R ~ U[1,3],
