@@ -223,12 +223,16 @@ __global__ void __launch_bounds__(256) k_conv_row(ConvArgs A) {
   constexpr int NH = 3 * HX * (RW_KC / 8);        // 16-byte loads of the halo
   constexpr int NWT = 9 * NT * (RW_KC / 8);       // 16-byte loads of the weights
   constexpr int LPT = (NH + NWT + 255) / 256;
-  __shared__ __attribute__((aligned(16))) bf16s sh[3 * HX * RW_RS];
+  // halo rows sh, then the weights sw, in one buffer that the epilogue
+  // reuses for the output tile
+  constexpr int SH = 3 * HX * RW_RS;
+  __shared__ __attribute__((aligned(16))) bf16s smem[SH + 9 * NT * RW_KC];
+  bf16s* const sh = smem;
   // weights in the MFMA's B-fragment order, unpadded: for tap t, block jb of
   // 32 output channels and K-step kk, lane (m, g) reads its 8 channels at
   // ((t * NT / 32 + jb) * 2 + kk) * 512 + (32 g + m) * 8, so a wave's 64
   // 16-byte reads are one contiguous 1 KB (no bank conflicts, no padding)
-  __shared__ __attribute__((aligned(16))) bf16s sw[9 * NT * RW_KC];
+  bf16s* const sw = smem + SH;
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, m = l & 31, g = l >> 5;
   const int wp = wave % WPX, wc = wave / WPX;
   const int segs = A.W / TW;
@@ -293,20 +297,48 @@ __global__ void __launch_bounds__(256) k_conv_row(ConvArgs A) {
       }
     }
   }
-  const long long prow = (long long)rowi * A.W + x0 + 32 * wp;
+  // Epilogue through LDS: the accumulators, bias and activation applied,
+  // go to a TW x NT float tile (row stride NT + 8 floats: the two rows a
+  // store instruction writes fall on disjoint halves of the banks); then
+  // each thread takes runs of 8 channels of one pixel, applies the mask
+  // read as one 16-byte load and stores 16 bytes, so every pixel's NT
+  // channels leave as whole lines.  Same float operations per element as
+  // storing straight from the accumulators.
+  constexpr int OS = NT + 8;
+  static_assert(TW * OS * 4 <= (SH + 9 * NT * RW_KC) * 2, "output tile fits the buffer");
+  float* const so = reinterpret_cast<float*>(smem);
+  __syncthreads();  // every wave has read its last fragments of sh and sw
 #pragma unroll
   for (int j = 0; j < NW; ++j) {
-    const int col = n0 + (wc * NW + j) * 32 + m;
-    const float bias = A.bias ? A.bias[col] : 0.0f;
+    const int c = (wc * NW + j) * 32 + m;
+    const float bias = A.bias ? A.bias[n0 + c] : 0.0f;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const long long px = prow + acc_row(q, g);
       float v = acc[j][q] + bias;
       if (A.act) v = softplus(v);
-      const long long o = px * A.Cn + col;
-      if (A.mask) v *= softplus_grad(bf2f(A.mask[o]));
-      A.out[o] = f2bf(v);
+      so[(32 * wp + acc_row(q, g)) * OS + c] = v;
     }
+  }
+  __syncthreads();
+  constexpr int RUNS = NT / 8;
+  const long long pix0 = (long long)rowi * A.W + x0;
+#pragma unroll
+  for (int e = tid; e < TW * RUNS; e += 256) {
+    const int px = e / RUNS, c8 = e - px * RUNS;
+    const float* sp = so + px * OS + 8 * c8;
+    const long long o = (pix0 + px) * A.Cn + n0 + 8 * c8;
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = sp[u];
+    if (A.mask) {
+      const u16x8 mk = *reinterpret_cast<const u16x8*>(A.mask + o);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] *= softplus_grad(bf2f(mk[u]));
+    }
+    u16x8 ov;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ov[u] = f2bf(v[u]);
+    *reinterpret_cast<u16x8*>(A.out + o) = ov;
   }
 }
 
