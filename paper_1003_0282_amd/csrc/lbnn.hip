@@ -355,14 +355,18 @@ __global__ void __launch_bounds__(256) k_conv_row(ConvArgs A) {
 // many as the 256 threads can load in one round); wave w owns block
 // (w % MB, (w / MB) % NB) and the K-steps kk with kk % KS = w / (MB NB),
 // KS = 4 / (MB NB).  Each workgroup stores its partial sums in the slice
-// of its pixel chunk, part[chunk][9][Ci][Co]; k_sum_chunks then adds the
-// slices in chunk order, so the result does not depend on which workgroup
-// finishes first (no atomics: training repeats bit for bit).  x has Cx
-// channels (the padded input of the first layer); only ci < Ci are written.
+// of its pixel chunk, part[chunk] = {dW [9][Ci][Co], db [Co]}; k_sum_chunks
+// then adds the slices in chunk order, so the result does not depend on
+// which workgroup finishes first (no atomics: training repeats bit for
+// bit).  The bias gradient db[co] = sum_p gz[p][co] comes from the
+// workgroups of the centre tap and the first ci block, whose gz loads
+// cover every pixel of their chunk once: their loading threads add up what
+// they load, and the sums meet in LDS in a fixed order.  x has Cx channels
+// (the padded input of the first layer); only ci < Ci are written.
 struct WgradArgs {
   const bf16s* x;   // [B][H][W][Cx]
   const bf16s* gz;  // [B][H][W][Co]
-  float* part;      // [chunks][9][Ci][Co]
+  float* part;      // [chunks][9 Ci Co + Co]
   int B, H, W, Cx, Ci, Co, chunk;
   int cib, cob;     // ci / co tiles per tap
 };
@@ -426,6 +430,8 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs A) {
   const int lt = ldx ? tid : tid - XT;
   const int pg = lt % (WG_SP / 8), cg = lt / (WG_SP / 8);
   const int mb = wave % MB, nb = (wave / MB) % NB, ks = wave / (MB * NB);
+  const bool bias_wg = t == 4 && ci0 == 0;  // workgroup-uniform
+  float bs[8] = {};
   u16x8 r[8];
   auto load = [&](long long p0) {
     const u16x8 zero = {};
@@ -452,6 +458,12 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs A) {
   load(p_beg);
   for (long long p0 = p_beg; p0 < p_end; p0 += WG_SP) {
     __syncthreads();  // the previous stage's fragments have been read
+    if (bias_wg && ldg) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bs[e] += bf2f(r[k][e]);
+    }
     if (ldx || ldg) {
       u16x8 tr[8];
       transpose8(r, tr);
@@ -469,8 +481,25 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs A) {
       acc = mfma(a, b, acc);
     }
   }
+  float* part = A.part + (long long)cidx * (9LL * A.Ci * A.Co + A.Co);
+  if (bias_wg) {
+    // the gz loaders' column sums, pixel groups added in order
+    constexpr int PG = WG_SP / 8;
+    static_assert(sizeof(sg) >= 32 * NB * PG * sizeof(float), "bias reduction buffer");
+    float* red = reinterpret_cast<float*>(sg);
+    __syncthreads();  // every wave is done with the staged tiles
+    if (ldg) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) red[(8 * cg + e) * PG + pg] = bs[e];
+    }
+    __syncthreads();
+    if (tid < 32 * NB) {
+      float b = 0.0f;
+      for (int k = 0; k < PG; ++k) b += red[tid * PG + k];
+      part[9LL * A.Ci * A.Co + co0 + tid] = b;
+    }
+  }
   // the KS waves that split this block's K-steps meet in LDS (fixed order)
-  float* part = A.part + (long long)cidx * 9 * A.Ci * A.Co;
   const int co = co0 + 32 * nb + m;
   if (KS == 1) {
 #pragma unroll
@@ -511,7 +540,8 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs A) {
 // y over x0 .. x0 + WR_TW - 1; all nine taps then read the same staged rows,
 // the tap's x shift being an offset into the row (one 16-byte LDS read for
 // dx = 0, eight 2-byte reads otherwise).  Wave w owns the taps t = w mod 4
-// over all WR_TW / 16 K-steps; one atomic add per weight and workgroup.
+// over all WR_TW / 16 K-steps.  Partial sums per chunk of segments, the
+// bias gradient from the workgroups of the first ci block, as in k_wgrad.
 constexpr int WR_TW = 128;                 // pixels per row segment
 constexpr int WR_XS = WR_TW + 16 + 8;      // x row: 8-pixel pads each side + 8 (152 el.)
 constexpr int WR_GS = WR_TW + 8;           // g row stride (136 elements)
@@ -533,6 +563,9 @@ __global__ void __launch_bounds__(256) k_wgrad_row(WgradArgs A) {
   f32x16 acc[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) acc[k] = f32x16{};
+  static_assert(NXB < 256 && NGB <= 256 && NXB + NGB <= 512, "two load rounds");
+  const bool bias_wg = ci0 == 0;  // workgroup-uniform
+  float bs[8] = {};
   const u16x8 zero = {};
   for (long long sgi = s_beg; sgi < s_end; ++sgi) {
     const int seg = (int)(sgi % segs);
@@ -562,6 +595,12 @@ __global__ void __launch_bounds__(256) k_wgrad_row(WgradArgs A) {
 #pragma unroll
         for (int k = 0; k < 8; ++k)
           v[k] = *reinterpret_cast<const u16x8*>(A.gz + (p + k) * A.Co + co0 + 8 * cg);
+        if (bias_wg) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bs[e] += bf2f(v[k][e]);
+        }
         transpose8(v, tv);
 #pragma unroll
         for (int j = 0; j < 8; ++j)
@@ -589,7 +628,27 @@ __global__ void __launch_bounds__(256) k_wgrad_row(WgradArgs A) {
       }
     }
   }
-  float* part = A.part + (long long)cidx * 9 * A.Ci * A.Co;
+  float* part = A.part + (long long)cidx * (9LL * A.Ci * A.Co + A.Co);
+  if (bias_wg) {
+    // thread tid loaded gz block b = tid or tid + 256 (if in the gz range);
+    // its column sums meet in LDS, pixel groups added in order
+    constexpr int PG = WR_TW / 8;
+    static_assert(sizeof(sg) >= 32 * PG * sizeof(float), "bias reduction buffer");
+    float* red = reinterpret_cast<float*>(sg);
+    __syncthreads();  // every wave is done with the staged tiles
+    const int b = tid >= NXB ? tid : tid + 256;
+    if (b < NXB + NGB) {
+      const int f = b - NXB, xg = f >> 2, cg = f & 3;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) red[(8 * cg + e) * PG + xg] = bs[e];
+    }
+    __syncthreads();
+    if (tid < 32) {
+      float bsum = 0.0f;
+      for (int k = 0; k < PG; ++k) bsum += red[tid * PG + k];
+      part[9LL * A.Ci * A.Co + co0 + tid] = bsum;
+    }
+  }
   const int co = co0 + m;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -603,24 +662,44 @@ __global__ void __launch_bounds__(256) k_wgrad_row(WgradArgs A) {
   }
 }
 
-// out[w] = sum over chunks c = 0, 1, ... of part[c][w], in that order: the
-// second, fixed-order pass of every parameter-gradient reduction.
+// out[w] = sum over chunks of part[c][w] in a fixed order: the second pass
+// of every parameter-gradient reduction.  The chunks are cut into G
+// contiguous runs (a workgroup covers 256 / G elements); thread (run,
+// element) adds its run in chunk order with eight loads in flight, then the
+// G run sums are added in run order.  Several runs keep the dependent chain
+// of loads short where there are many chunks and few elements.
+template <int G>
 __global__ void __launch_bounds__(256) k_sum_chunks(const float* part, float* out, long long n,
                                                     int nchunk) {
-  const long long w = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= n) return;
-  // eight loads in flight, added in chunk order
+  constexpr int E = 256 / G;
+  __shared__ float red[256];
+  const int e = threadIdx.x % E, run = threadIdx.x / E;
+  const long long w = (long long)blockIdx.x * E + e;
+  const int len = (nchunk + G - 1) / G;
+  const int c1 = min(nchunk, (run + 1) * len);
   float s = 0.0f;
-  int c = 0;
-  for (; c + 8 <= nchunk; c += 8) {
-    float v[8];
+  if (w < n) {
+    int c = run * len;
+    for (; c + 8 <= c1; c += 8) {
+      float v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = part[(long long)(c + u) * n + w];
+      for (int u = 0; u < 8; ++u) v[u] = part[(long long)(c + u) * n + w];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s += v[u];
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < c1; ++c) s += part[(long long)c * n + w];
   }
-  for (; c < nchunk; ++c) s += part[(long long)c * n + w];
-  out[w] = s;
+  if (G == 1) {
+    if (w < n) out[w] = s;
+    return;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (run == 0 && w < n) {
+    float t = red[e];
+    for (int k = 1; k < G; ++k) t += red[k * E + e];
+    out[w] = t;
+  }
 }
 
 // The same for FP64 partial sums reduced to one value by one workgroup:
@@ -637,50 +716,6 @@ __global__ void __launch_bounds__(256) k_sum_chunks_d(const double* part, double
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = red[0];
-}
-
-// Bias gradient part[chunk][c] = sum over a chunk of pixels of gz[p][c].
-// Thread t owns channels 8 (t % G) .. + 7 (G = C / 8, one 16-byte load per
-// pixel) and every (256 / G)-th pixel of the chunk, with four independent
-// partial sums per channel so that four loads are in flight; the partial
-// sums meet in LDS in a fixed order and k_sum_chunks adds the chunks.  The
-// chunk holds 64 (256 / G) pixels (64 loads per thread).  C <= 256, a
-// multiple of 8.
-__global__ void __launch_bounds__(256) k_bgrad(const bf16s* gz, float* part, long long npix, int C) {
-  __shared__ float red[256 * 8];
-  const int G = C / 8, nq = 256 / G;
-  const int cg = threadIdx.x % G, q = threadIdx.x / G;
-  const long long chunk = 64LL * nq;
-  const long long p0 = (long long)blockIdx.x * chunk;
-  const long long p1 = std::min<long long>(p0 + chunk, npix);
-  float s[4][8] = {};
-  if (q < nq) {
-    long long p = p0 + q;
-    for (; p + 3 * nq < p1; p += 4 * nq) {
-      u16x8 v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        v[u] = *reinterpret_cast<const u16x8*>(gz + (p + u * nq) * C + 8 * cg);
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) s[u][e] += bf2f(v[u][e]);
-    }
-    for (; p < p1; p += nq) {
-      const u16x8 v = *reinterpret_cast<const u16x8*>(gz + p * C + 8 * cg);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) s[0][e] += bf2f(v[e]);
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < 8; ++e) red[threadIdx.x * 8 + e] = (s[0][e] + s[1][e]) + (s[2][e] + s[3][e]);
-  __syncthreads();
-  if (threadIdx.x < C) {
-    const int c = threadIdx.x, g = c / 8, e = c % 8;
-    float t = 0.0f;
-    for (int k = 0; k < nq; ++k) t += red[(k * G + g) * 8 + e];
-    part[(long long)blockIdx.x * C + c] = t;
-  }
 }
 
 // ---- U-Net glue --------------------------------------------------------------
@@ -862,8 +897,8 @@ __global__ void __launch_bounds__(256) k_head_back(const bf16s* d0, const float*
 }
 
 // Head backward, parameter side: dWh[c][k] = sum_p d0[p][c] gy[p][k] and
-// dbh[k] = sum_p gy[p][k].  As in k_bgrad, thread t owns channels
-// 8 (t % G) .. + 7 (one 16-byte load of d0 per pixel) and every (256 / G)-th
+// dbh[k] = sum_p gy[p][k].  Thread t owns channels 8 (t % G) .. + 7
+// (G = C / 8, one 16-byte load of d0 per pixel) and every (256 / G)-th
 // pixel of a chunk of 64 (256 / G) pixels, accumulating 8 x K products in
 // registers; the partial sums meet in LDS in a fixed order and the chunk's
 // C K + K sums go to part[chunk] (dWh then dbh), which k_sum_chunks adds.
@@ -925,8 +960,21 @@ __global__ void k_cast_w(const float* W, bf16s* wf, bf16s* wb, int ci, int Ck, i
   wf[((long long)t * co + o) * Ck + c] = v;
 }
 
+// The convolution weights' place in the parameter vector and their BF16
+// copies, for the Adam step to refresh the copies as it updates.
+constexpr int MAXCONV = 14;
+struct WCopies {
+  long long off[MAXCONV];  // first weight of convolution q ([9][ci][co])
+  int ci[MAXCONV], Ck[MAXCONV], co[MAXCONV];
+  bf16s* wf[MAXCONV];
+  bf16s* wb[MAXCONV];
+};
+
+// Adam step of every parameter.  A convolution weight is also written to
+// its BF16 copies (the value k_cast_w would write), so a step needs no cast
+// pass; the zero-padded input channels of the copies are left as they are.
 __global__ void k_adam(float* p, const float* g, float* m, float* v, long long n, float lr,
-                       float b1, float b2, float eps, float c1, float c2) {
+                       float b1, float b2, float eps, float c1, float c2, WCopies W) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const float gk = g[k];
@@ -934,7 +982,28 @@ __global__ void k_adam(float* p, const float* g, float* m, float* v, long long n
   const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
   m[k] = mk;
   v[k] = vk;
-  p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+  const float pk = p[k] - lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+  p[k] = pk;
+  // which convolution's weights k is, if any (constant indices only)
+  long long rel = -1;
+  int ci = 1, Ck = 1, co = 1;
+  bf16s *wf = nullptr, *wb = nullptr;
+#pragma unroll
+  for (int q = 0; q < MAXCONV; ++q)
+    if (k >= W.off[q] && k < W.off[q] + 9LL * W.ci[q] * W.co[q]) {
+      rel = k - W.off[q];
+      ci = W.ci[q];
+      Ck = W.Ck[q];
+      co = W.co[q];
+      wf = W.wf[q];
+      wb = W.wb[q];
+    }
+  if (rel >= 0) {
+    const int o = (int)(rel % co), c = (int)((rel / co) % ci), t = (int)(rel / ((long long)co * ci));
+    const bf16s b = f2bf(pk);
+    wb[((long long)t * Ck + c) * co + o] = b;
+    wf[((long long)t * co + o) * Ck + c] = b;
+  }
 }
 
 __global__ void k_zero(float* p, long long n) {
@@ -1032,6 +1101,7 @@ struct Conv {
 };
 
 enum { E0A, E0B, E1A, E1B, E2A, E2B, E3A, E3B, D2A, D2B, D1A, D1B, D0A, D0B, NCONV };
+static_assert(NCONV == MAXCONV, "one weight-copy entry per convolution");
 
 struct Plan {
   lbnn_desc d;
@@ -1093,8 +1163,8 @@ WgShape wgrad_shape(int Ck, int co, int B, int H, int W) {
   return S;
 }
 
-// Chunks of the bias gradient and of the head's parameter gradient.
-long long bgrad_chunks(long long npix, int C) { return blocks(npix, 64 * (256 / (C / 8))); }
+// Pixel chunks of the head's parameter gradient.
+long long head_chunks(long long npix, int C) { return blocks(npix, 64 * (256 / (C / 8))); }
 
 bool plan(const lbnn_desc& d, Plan& P) {
   P.d = d;
@@ -1165,10 +1235,9 @@ bool plan(const lbnn_desc& d, Plan& P) {
       const Conv& c = P.cv[k];
       const int l = conv_level(k);
       const WgShape S = wgrad_shape(c.Ck, c.co, b, d.H >> l, d.W >> l);
-      part = std::max(part, (size_t)S.gx * 9 * c.ci * c.co);
-      part = std::max(part, (size_t)bgrad_chunks((long long)b * npix_lvl(d, l), c.co) * c.co);
+      part = std::max(part, (size_t)S.gx * (9 * c.ci * c.co + c.co));
     }
-    part = std::max(part, (size_t)bgrad_chunks((long long)b * npix_lvl(d, 0), c0) *
+    part = std::max(part, (size_t)head_chunks((long long)b * npix_lvl(d, 0), c0) *
                               ((size_t)c0 * d.c_out + d.c_out));
   }
   P.part = o; o = al(o + 4 * part);
@@ -1290,11 +1359,21 @@ lbaxi_status conv(lbnn_t* h, const Conv& c, const bf16s* in, bf16s* out, int lvl
   return LBAXI_OK;
 }
 
-// Sum of the per-chunk partials part[nchunk][n] into out[n] (chunk order).
+// Sum of the per-chunk partials part[nchunk][n] into out[n] (fixed order).
+// Runs per element: doubled while each run keeps at least 8 chunks and the
+// grid stays under 1024 workgroups, at most 16.
 lbaxi_status sum_chunks(lbnn_t* h, float* out, long long n, long long nchunk) {
-  hipLaunchKernelGGL(k_sum_chunks, dim3(blocks(n)), dim3(256), 0, h->stream,
-                     h->at<float>(h->P.part), out, n, (int)nchunk);
-  NCHK(hipGetLastError());
+  int G = 1;
+  while (G < 16 && nchunk / (2 * G) >= 8 && blocks(n, 256 / G) < 1024) G *= 2;
+  void* fn = G == 16 ? (void*)&k_sum_chunks<16>
+             : G == 8 ? (void*)&k_sum_chunks<8>
+             : G == 4 ? (void*)&k_sum_chunks<4>
+             : G == 2 ? (void*)&k_sum_chunks<2>
+                      : (void*)&k_sum_chunks<1>;
+  const float* part = h->at<float>(h->P.part);
+  int nc = (int)nchunk;
+  void* args[] = {&part, &out, &n, &nc};
+  NCHK(hipLaunchKernel(fn, dim3((unsigned)blocks(n, 256 / G)), dim3(256), args, 0, h->stream));
   return LBAXI_OK;
 }
 
@@ -1326,13 +1405,8 @@ lbaxi_status wgrad(lbnn_t* h, const Conv& c, const bf16s* x, const bf16s* gz, in
   }
   void* args[] = {&A};
   NCHK(hipLaunchKernel(fn, grid, dim3(256), args, 0, h->stream));
-  lbaxi_status s;
-  if ((s = sum_chunks(h, h->grads() + c.off_W, 9LL * c.ci * c.co, S.gx)) != LBAXI_OK) return s;
-  const long long nb = bgrad_chunks(npix, c.co);
-  hipLaunchKernelGGL(k_bgrad, dim3((unsigned)nb), dim3(256), 0, h->stream, gz,
-                     h->at<float>(h->P.part), npix, c.co);
-  NCHK(hipGetLastError());
-  return sum_chunks(h, h->grads() + c.off_b, c.co, nb);
+  // dW then db: contiguous in the parameter vector as in each chunk's slice
+  return sum_chunks(h, h->grads() + c.off_W, 9LL * c.ci * c.co + c.co, S.gx);
 }
 
 }  // namespace
@@ -1479,7 +1553,7 @@ lbaxi_status lbnn_backward(lbnn_t* h, const float* d_target, float* d_grads, dou
   hipLaunchKernelGGL(k_head_back, dim3(blocks(np0)), dim3(256), 0, h->stream, h->act(P.d_b[0]),
                      h->at<float>(P.gy), h->params() + P.off_hW, h->act(P.gbig1[0]), np0, c0,
                      P.d.c_out);
-  const long long nh = bgrad_chunks(np0, c0);
+  const long long nh = head_chunks(np0, c0);
   hipLaunchKernelGGL(k_head_wgrad, dim3((unsigned)nh), dim3(256), 0, h->stream, h->act(P.d_b[0]),
                      h->at<float>(P.gy), h->at<float>(P.part), np0, c0, P.d.c_out);
   NCHK(hipGetLastError());
@@ -1549,11 +1623,22 @@ lbaxi_status lbnn_adam(lbnn_t* h, float lr, float b1, float b2, float eps) {
   if (!h) return nfail(LBAXI_EINVAL, "NULL handle");
   h->step += 1;
   const float c1 = 1.0f - powf(b1, (float)h->step), c2 = 1.0f - powf(b2, (float)h->step);
+  WCopies W;
+  for (int q = 0; q < NCONV; ++q) {
+    const Conv& c = h->P.cv[q];
+    W.off[q] = c.off_W;
+    W.ci[q] = c.ci;
+    W.Ck[q] = c.Ck;
+    W.co[q] = c.co;
+    W.wf[q] = h->at<bf16s>(c.wf);
+    W.wb[q] = h->at<bf16s>(c.wb);
+  }
   hipLaunchKernelGGL(k_adam, dim3(blocks(h->P.nparam)), dim3(256), 0, h->stream, h->params(),
                      h->grads(), h->at<float>(h->P.m1), h->at<float>(h->P.m2), h->P.nparam, lr, b1,
-                     b2, eps, c1, c2);
+                     b2, eps, c1, c2, W);
   NCHK(hipGetLastError());
-  h->wdirty = true;
+  // copies that were current stay current (the step wrote them); copies out
+  // of date (parameters set since the last cast) are cast before next use
   return LBAXI_OK;
 }
 

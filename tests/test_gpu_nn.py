@@ -147,6 +147,24 @@ def test_forward_does_not_depend_on_the_batch():
     assert np.array_equal(y16[5:7], y2)
 
 
+def test_adam_keeps_the_bf16_weight_copies_current():
+    """The Adam step also writes each updated convolution weight to its BF16
+    copies (forward and adjoint order): after training steps the network's
+    forward equals, bit for bit, that of a network given the same
+    parameters, whose copies are cast from them.  Five input channels make
+    the first layer's padded channels part of the check."""
+    from paper_1003_0282_amd import lbnn
+    net, p, names, x, t, xd, td = _setup(40, 72, 3, 5, 5, seed=11)
+    y0 = net.forward(xd).cpu().numpy()
+    for _ in range(3):
+        net.train_step(xd, td, 1e-2)
+    fresh = lbnn.Net(40, 72, 5, 5, WIDTHS, max_batch=3)
+    fresh.set_params(net.get_params())
+    y1 = net.forward(xd).cpu().numpy()
+    assert not np.array_equal(y0, y1)
+    assert np.array_equal(y1, fresh.forward(xd).cpu().numpy())
+
+
 def test_training_reduces_loss():
     import torch
     net, p, names, x, t, xd, td = _setup(seed=2)
