@@ -97,16 +97,24 @@ def bytes_per_update(case, prec):
 
 
 def kernel_hash() -> str:
-    """Hash of the solver's device code: lbaxi_device.hpp and the kernel part
-    of lbaxi.hip (everything before its host-runtime section), which is what
-    the HBM counters of a launch shape depend on."""
+    """Hash of what the HBM counters of a launch shape depend on: the solver's
+    device code (lbaxi_device.hpp and the kernel part of lbaxi.hip, everything
+    before its host-runtime section) and the host functions that lay the
+    populations out in memory (from the layout's description to the
+    workspace's)."""
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_1003_0282_amd", "csrc")
     for f in sorted(os.listdir(src)):
         if f.startswith("lbaxi"):
             text = open(os.path.join(src, f), "rb").read()
             cut = text.find(b"\n// host runtime\n")
-            h.update(text if cut < 0 else text[:cut])
+            if cut < 0:
+                h.update(text)
+                continue
+            h.update(text[:cut])
+            a = text.find(b"\n// Row-blocked layout", cut)
+            b = text.find(b"\n// Device workspace", a + 1)
+            h.update(text[cut:] if a < 0 or b < 0 else text[a:b])
     return h.hexdigest()[:16]
 
 

@@ -163,7 +163,11 @@ const char* lbaxi_strerror(lbaxi_status s);
 
 /* Device workspace needed by a batch of n descriptors (n = 1: one lattice).
  * Sec. III A: state is two population buffers (ping-pong) plus one speed
- * field per lattice for Eq. (57). */
+ * field per lattice for Eq. (57).  A buffer holds each lattice's populations
+ * in row blocks (the padded rows of all Q populations of one lattice row,
+ * one after the other, for rows -1..nr, then two blocks of z-end ghost
+ * columns); one lattice's populations may take at most 4 GiB (32-bit byte
+ * offsets inside a lattice), EINVAL beyond. */
 lbaxi_status lbaxi_workspace_bytes(int32_t n, const lbaxi_desc* descs, size_t* bytes);
 
 /* Create a handle over n lattices (all the same prec, the same SWIRL and
@@ -171,7 +175,8 @@ lbaxi_status lbaxi_workspace_bytes(int32_t n, const lbaxi_desc* descs, size_t* b
  * WET_WALLS may differ between lattices), carving
  * d_workspace (>= lbaxi_workspace_bytes, 256-byte aligned) and enqueuing on
  * hip_stream (a hipStream_t; NULL = the null stream).  Validates every
- * descriptor: EINVAL for bad sizes or side combinations (axis only as south
+ * descriptor: EINVAL for bad sizes (a lattice above 4 GiB of populations
+ * included) or side combinations (axis only as south
  * with r0 = 0, periodic only on both z-ends together, free slip only on
  * z-ends), ERANGE when some relaxation rate (1 + tau e_r / r)/(tau + 1/2) of
  * f (BGK), g or h, or an MRT rate, leaves (0, 2).  The lattices start at rest (lbaxi_seed with NULL

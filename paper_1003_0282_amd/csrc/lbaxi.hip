@@ -826,22 +826,28 @@ long long halo_tiles(const std::vector<lbaxi_desc>& d) {
   for (const auto& x : d) n += (perimeter(x) + 255) / 256;
   return n;
 }
-// Padded rows: a 128-byte lead-in (node 0 starts a 128-byte line), nz
-// nodes and one spare slot, rounded up to 128 bytes; rows -1 and nr are the
-// ghost rows.  After the nr + 2 rows come the ghost-column strips of the two
-// z-ends, nr + 2 slots each, rounded up to 128 bytes.
+// Row-blocked layout of one lattice's populations.  A padded row of one
+// population has a 128-byte lead-in (node 0 starts a 128-byte line), nz
+// nodes and one spare slot, rounded up to 128 bytes (and to at least the
+// length of a ghost-column strip).  The padded rows of all populations for
+// one lattice row follow each other (row block), and row blocks follow in
+// row order: block 0 holds ghost row -1, block j + 1 node row j, block nr + 1
+// ghost row nr.  Two more blocks hold the ghost-column strips of the west
+// and the east z-end (rows -1..nr of each population, contiguous).  So the
+// plane stride is one padded row and the row stride one row block: the
+// populations a wave pulls for a tile lie in three nearby row blocks rather
+// than in Q planes a lattice apart.
 int row_lead(const lbaxi_desc& x) { return 128 / (x.prec == LBAXI_FP64 ? 8 : 4); }
-int row_pitch(const lbaxi_desc& x) {
-  const int q = row_lead(x);
-  return (q + x.nz + 1 + q - 1) / q * q;
-}
 int strip_len(const lbaxi_desc& x) {
   const int q = row_lead(x);
   return (x.nr + 2 + q - 1) / q * q;
 }
-long long padded_plane(const lbaxi_desc& x) {
-  return (long long)(x.nr + 2) * row_pitch(x) + 2LL * strip_len(x);
+int row_pitch(const lbaxi_desc& x) {
+  const int q = row_lead(x);
+  return std::max((q + x.nz + 1 + q - 1) / q * q, strip_len(x));
 }
+long long row_block(const lbaxi_desc& x) { return (long long)n_planes(x.fields) * row_pitch(x); }
+long long lattice_elems(const lbaxi_desc& x) { return (long long)(x.nr + 4) * row_block(x); }
 
 // Device workspace: parameters, three work lists (all tiles / tiles of
 // running lattices / halo chunks of running lattices) with their counts,
@@ -859,7 +865,6 @@ Layout layout(const std::vector<lbaxi_desc>& d) {
   Layout L;
   const int n = (int)d.size();
   const size_t es = elem_size(d[0].prec);
-  const int np = n_planes(d[0].fields);
   const size_t tb = sizeof(Tile) * (size_t)max_tiles(d);
   size_t o = 0;
   L.ip = o; o = align_up(o + sizeof(InstP) * n, 256);
@@ -874,7 +879,7 @@ Layout layout(const std::vector<lbaxi_desc>& d) {
   for (const auto& x : d) {
     L.off.push_back(e);
     L.off_fld.push_back(fe);
-    e += align_up((size_t)np * padded_plane(x), 64);
+    e += align_up((size_t)lattice_elems(x), 64);
     fe += (long long)x.nz * x.nr;
   }
   L.buf_elems = e;
@@ -904,8 +909,9 @@ lbaxi_status validate(const lbaxi_desc& d, int k) {
     return fail(s, b);
   };
   if (d.nz < 2 || d.nr < 2) return bad(LBAXI_EINVAL, "nz and nr must be >= 2");
-  if ((long long)n_planes(d.fields) * padded_plane(d) >= (1LL << 31))
-    return bad(LBAXI_EINVAL, "lattice too large for 32-bit in-lattice offsets");
+  // loads and stores address a lattice by a 32-bit byte offset from a population base
+  if (lattice_elems(d) * (long long)elem_size(d.prec) >= (1LL << 32))
+    return bad(LBAXI_EINVAL, "lattice too large for 32-bit in-lattice byte offsets");
   if (d.prec != LBAXI_FP64 && d.prec != LBAXI_FP32 && d.prec != LBAXI_FP32_FAST)
     return bad(LBAXI_EINVAL, "bad prec");
   if (d.fields & ~127u) return bad(LBAXI_EINVAL, "unknown field bits");
@@ -974,11 +980,11 @@ InstP make_inst(const lbaxi_desc& d, long long off, long long off_fld) {
   memset(&P, 0, sizeof P);
   P.nz = d.nz;
   P.nr = d.nr;
-  P.pitch = row_pitch(d);
+  P.pitch = (int)row_block(d);  // row stride
   P.c0 = row_lead(d);
-  P.plane = (int)padded_plane(d);
-  P.sw = (d.nr + 2) * row_pitch(d);
-  P.se = P.sw + strip_len(d);
+  P.plane = row_pitch(d);        // population (plane) stride
+  P.sw = (d.nr + 2) * P.pitch;   // strip blocks after the ghost row nr
+  P.se = P.sw + P.pitch;
   P.cart = (d.fields & LBAXI_CARTESIAN) ? 1 : 0;
   P.wet = (d.fields & LBAXI_WET_WALLS) ? 1 : 0;
   P.zou = (d.fields & LBAXI_ZOU_HE) ? 1 : 0;
@@ -1880,8 +1886,8 @@ lbaxi_status lbaxi_save(lbaxi_t* h, void* host_buf, size_t bytes) {
   char* p = static_cast<char*>(host_buf);
   SaveHeader H;
   memset(&H, 0, sizeof H);
-  memcpy(H.magic, "LBAXISV2", 8);
-  H.version = 2;
+  memcpy(H.magic, "LBAXISV3", 8);  // V3: row-blocked population layout
+  H.version = 3;
   H.n = h->n;
   H.prec = h->prec;
   H.fields = h->fields;
@@ -1899,11 +1905,10 @@ lbaxi_status lbaxi_save(lbaxi_t* h, void* host_buf, size_t bytes) {
   memcpy(p, h->inst_spd.data(), h->n);
   p += h->n;
   // every lattice's own current buffer, instance by instance
-  const int np = n_planes(h->fields);
   for (int k = 0; k < h->n; ++k) {
     const char* src =
         static_cast<const char*>(h->dyn[k].cur ? h->bufB : h->bufA) + es * h->L.off[k];
-    const size_t nb = es * (size_t)np * padded_plane(h->desc[k]);
+    const size_t nb = es * (size_t)lattice_elems(h->desc[k]);
     HIPCHK(hipMemcpyAsync(p + es * h->L.off[k], src, nb, hipMemcpyDeviceToHost, h->stream));
   }
   p += es * (size_t)h->L.buf_elems;
@@ -1933,7 +1938,7 @@ lbaxi_status lbaxi_load(lbaxi_t* h, const void* host_buf, size_t bytes) {
   const char* p = static_cast<const char*>(host_buf);
   SaveHeader H;
   memcpy(&H, p, sizeof H);
-  if (memcmp(H.magic, "LBAXISV2", 8) || H.n != h->n || H.prec != h->prec ||
+  if (memcmp(H.magic, "LBAXISV3", 8) || H.n != h->n || H.prec != h->prec ||
       H.fields != h->fields || H.desc_hash != desc_hash(h->desc))
     return fail(LBAXI_EINVAL, "checkpoint does not match this handle");
   p += sizeof H;
@@ -1944,10 +1949,9 @@ lbaxi_status lbaxi_load(lbaxi_t* h, const void* host_buf, size_t bytes) {
   memcpy(h->inst_spd.data(), p, h->n);
   p += h->n;
   const size_t es = elem_size(h->prec);
-  const int np = n_planes(h->fields);
   for (int k = 0; k < h->n; ++k) {
     char* dst = static_cast<char*>(h->dyn[k].cur ? h->bufB : h->bufA) + es * h->L.off[k];
-    const size_t nb = es * (size_t)np * padded_plane(h->desc[k]);
+    const size_t nb = es * (size_t)lattice_elems(h->desc[k]);
     HIPCHK(hipMemcpyAsync(dst, p + es * h->L.off[k], nb, hipMemcpyHostToDevice, h->stream));
   }
   p += es * (size_t)h->L.buf_elems;

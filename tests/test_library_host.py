@@ -131,11 +131,13 @@ def test_workspace_grows_with_batch(L):
 
 
 def test_largest_lattice_accepted(L):
-    """In-lattice offsets are 32-bit: a lattice whose population planes reach
-    2^31 elements is refused, one just below is accepted (FP32, f only)."""
-    ok = W.base_case(14000, 16384, 0.8, a0=1e-7)
-    too_big = W.base_case(15000, 16384, 0.8, a0=1e-7)
+    """In-lattice byte offsets are 32-bit: a lattice whose populations (nr + 4
+    row blocks of 9 padded rows of 16448 floats at nz = 16384) reach 4 GiB is
+    refused, one just below is accepted (FP32, f only)."""
+    ok = W.base_case(16384, 7200, 0.8, a0=1e-7)      # 7204 * 9 * 16448 * 4 B < 2^32
+    too_big = W.base_case(16384, 7300, 0.8, a0=1e-7)  # 7304 * 9 * 16448 * 4 B > 2^32
     assert _status(L, [ok], prec=1) == 0
     assert _status(L, [too_big], prec=1) == -1
-    # the bound counts elements, not bytes: refused in FP64 as well
-    assert _status(L, [too_big], prec=0) == -1
+    # the bound counts bytes: the accepted FP32 lattice is refused in FP64
+    assert _status(L, [ok], prec=0) == -1
+    assert _status(L, [W.base_case(16384, 3600, 0.8, a0=1e-7)], prec=0) == 0
