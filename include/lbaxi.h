@@ -259,6 +259,15 @@ lbaxi_status lbaxi_get_launch(const lbaxi_t* h, int32_t* cfg5);
  * graphs (every step is a direct launch).  Default 64. */
 lbaxi_status lbaxi_set_graph_steps(lbaxi_t* h, int32_t k);
 
+/* Wet-node walls of small handles (on = 1, the default): for a handle with
+ * LBAXI_WET_WALLS lattices whose running lattices have at most 16 x 256
+ * perimeter nodes in all, the wall-node rebuild (Sec. IV B's
+ * non-equilibrium extrapolation) runs in the step kernel's launch, as
+ * further workgroups, instead of a launch of its own: one launch fewer per
+ * step.  on = 0 keeps the separate launch.  Bitwise the same results
+ * either way; no effect on other handles.  EINVAL for other values. */
+lbaxi_status lbaxi_set_fused_walls(lbaxi_t* h, int32_t on);
+
 /* Autotuner: times each candidate launch shape over steps_per_trial real
  * time steps (the steps count: the state advances) and keeps the fastest;
  * cfg5_out (may be NULL) receives it.  Synchronises the stream. */

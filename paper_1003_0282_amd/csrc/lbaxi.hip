@@ -470,6 +470,39 @@ constexpr int step_block_max(int F) { return (F & F_WETZ) ? 512 : 1024; }
 // same wave has just pulled (its lines are in the cache), so that the wall
 // kernel is left only the radial wall rows and every row off them is
 // written whole by this kernel.
+// One node (i, j) of a step tile: pull (or, for a wet z-end wall node, the
+// rebuild), macros, collision, store.
+template <typename S, typename R, int F>
+__device__ __forceinline__ void step_node(const StepArgs<S>& A, const Tile& T, const InstP& P,
+                                          long long t, bool pre, int i, int j) {
+  // wet wall nodes (only in the F_WETZ instance, which every handle with
+  // wet-node walls uses) are rebuilt after the pull, the z-end ones here
+  // and those of the radial wall rows by k_wall, except on the first step
+  // after seeding, where they collide their seeded state like any node
+  constexpr int FB = F & ~F_WETZ;
+  const bool wall = (F & F_WETZ) && P.wet && wet_rule(P, nullptr, i, j, nullptr);
+  const bool rebuild = wall && !pre;
+  if (rebuild && radial_wall_row(P, j)) return;
+  const PR<R> p = make_pr<R>(P, t);
+  R f[9], g[4], h[4];
+  if ((F & F_WETZ) && rebuild) {
+    WetRule w;
+    wet_rule(P, A.ip + T.inst, i, j, &w);
+    wall_state<S, R, FB>(P, p, A.src + P.off, i, j, w, f, g, h);
+  } else {
+    pull_plain<S, R, FB>(P, p, A.src + P.off, i, j, pre, f, g, h, !wall);
+  }
+  finish_node<S, R, FB>(A, P, p, i, j, f, g, h, true, !(F & F_WETZ));
+}
+
+// One time step: pull (padded planes, no boundary tests), macros, collision,
+// store at the node's own slots of the other buffer.  The halo kernel then
+// completes the boundary rules for the next pull.  F_WETZ (handles with
+// wet-node walls): the z-end wall nodes of rows that also hold fluid nodes
+// are rebuilt here, by their own lanes, from the inner neighbour that the
+// same wave has just pulled (its lines are in the cache), so that the wall
+// kernel is left only the radial wall rows and every row off them is
+// written whole by this kernel.
 template <typename S, typename R, int F>
 __global__ void __launch_bounds__(step_block_max(F))
     __attribute__((amdgpu_waves_per_eu(step_waves(F)))) k_step(StepArgs<S> A) {
@@ -484,10 +517,8 @@ __global__ void __launch_bounds__(step_block_max(F))
     const InstP P = cload(A.ip + T.inst);
     const int i = T.z0 + li, j = T.r0 + lj;
     if (i >= P.nz || j >= P.nr) continue;
-    // wet wall nodes (only in the F_WETZ instance, which every handle with
-    // wet-node walls uses) are rebuilt after the pull, the z-end ones here
-    // and those of the radial wall rows by k_wall, except on the first step
-    // after seeding, where they collide their seeded state like any node
+    // the body of step_node, written out: called from here, that function
+    // compiled to a different (longer) instruction schedule of this loop
     constexpr int FB = F & ~F_WETZ;
     const bool wall = (F & F_WETZ) && P.wet && wet_rule(P, nullptr, i, j, nullptr);
     const bool rebuild = wall && !pre;
@@ -510,13 +541,8 @@ __global__ void __launch_bounds__(step_block_max(F))
 // neighbour, then macros, collision and store like k_step.  Reads the same
 // source buffer as k_step and writes other nodes of the same destination.
 template <typename S, typename R, int F>
-__global__ void __launch_bounds__(256) k_wall(StepArgs<S> A) {
-  const int ti = blockIdx.x;
-  if (ti >= *A.ntiles) return;
-  const Tile T = cload(A.tiles + ti);
-  const InstP P = cload(A.ip + T.inst);
-  if (!P.wet) return;
-  const int q = T.z0 + threadIdx.x;
+__device__ __forceinline__ void wall_node(const StepArgs<S>& A, const Tile& T, const InstP& P,
+                                          int q) {
   if (q >= 2 * P.nz + 2 * (P.nr - 2)) return;
   int i, j;
   perimeter_node(P, q, i, j);
@@ -532,8 +558,27 @@ __global__ void __launch_bounds__(256) k_wall(StepArgs<S> A) {
   finish_node<S, R, F>(A, P, p, i, j, f, g, h);
 }
 
+template <typename S, typename R, int F>
+__global__ void __launch_bounds__(256) k_wall(StepArgs<S> A) {
+  const int ti = blockIdx.x;
+  if (ti >= *A.ntiles) return;
+  const Tile T = cload(A.tiles + ti);
+  const InstP P = cload(A.ip + T.inst);
+  if (!P.wet) return;
+  wall_node<S, R, F>(A, T, P, T.z0 + threadIdx.x);
+}
+
 // Ghost-slot fill after a step: tiles here are {instance, first perimeter
 // node, 0, 0}, one thread per perimeter node.
+template <typename S, int F>
+__device__ __forceinline__ void halo_node(const InstP* ip, const Tile& T, const InstP& P, S* buf,
+                                          int p) {
+  if (p >= 2 * P.nz + 2 * (P.nr - 2)) return;
+  int i, j;
+  perimeter_node(P, p, i, j);
+  halo_fill<S, F>(P, ip + T.inst, buf + P.off, i, j);
+}
+
 template <typename S, int F>
 __global__ void __launch_bounds__(256) k_halo(const InstP* ip, const Tile* tiles,
                                               const int* ntiles, S* buf) {
@@ -541,11 +586,44 @@ __global__ void __launch_bounds__(256) k_halo(const InstP* ip, const Tile* tiles
   if (ti >= *ntiles) return;
   const Tile T = cload(tiles + ti);
   const InstP P = cload(ip + T.inst);
-  const int p = T.z0 + threadIdx.x;
-  if (p >= 2 * P.nz + 2 * (P.nr - 2)) return;
-  int i, j;
-  perimeter_node(P, p, i, j);
-  halo_fill<S, F>(P, ip + T.inst, buf + P.off, i, j);
+  halo_node<S, F>(ip, T, P, buf, T.z0 + threadIdx.x);
+}
+
+// The wall part of a step taken in the step's own launch.
+struct WallPart {
+  const Tile* htiles;  // perimeter tiles of the running lattices
+  const int* nh;       // their count
+  int ns;              // workgroups of the step part (one per tile of the step's list)
+};
+
+// Step and wet-wall work of a time step in one launch, for handles with
+// wet-node walls and few lattices, where each kernel of a step is a short
+// chain of dependent loads and the step costs about the sum of its kernels.
+// Workgroups [0, ns) do what k_step does for one tile each, the others what
+// k_wall does for one perimeter tile each: both read only the source buffer
+// and write disjoint nodes of the destination, so the two parts need no
+// order between them.  The ghost slots are filled by k_halo afterwards, as
+// after the separate kernels.  Same arithmetic per node.
+template <typename S, typename R, int F>
+__global__ void __launch_bounds__(step_block_max(F)) k_step_wall(StepArgs<S> A, WallPart B) {
+  constexpr int FB = F & ~F_WETZ;
+  const int b = blockIdx.x;
+  if (b < B.ns) {
+    if (b >= *A.ntiles) return;
+    const long long t = A.tdev ? (*A.tdev + A.k) : A.t0;
+    const Tile T = cload(A.tiles + b);
+    const InstP P = cload(A.ip + T.inst);
+    const int tz = 1 << A.tzlog;
+    const int i = T.z0 + (threadIdx.x & (tz - 1)), j = T.r0 + (threadIdx.x >> A.tzlog);
+    if (i < P.nz && j < P.nr) step_node<S, R, F>(A, T, P, t, A.mode & MODE_PRE, i, j);
+  } else {
+    const int w = b - B.ns;
+    if (w >= *B.nh) return;
+    const Tile T = cload(B.htiles + w);
+    const InstP P = cload(A.ip + T.inst);
+    if (!P.wet) return;
+    for (int q = threadIdx.x; q < 256; q += blockDim.x) wall_node<S, R, FB>(A, T, P, T.z0 + q);
+  }
 }
 
 // Equilibrium seeding: f^ = f_eq - S/2 (S of the collision model), g = g_eq,
@@ -1068,6 +1146,7 @@ struct lbaxi_s {
   // launch shape
   int tz = 64, tr = 4, grid = 0, xcd = 0, nt = 1;
   int K = 64;
+  int fuse = 1;  // wall part in the step's launch (k_step_wall) where the handle is small
   std::vector<Tile> lists[3];
   int count[3] = {0, 0, 0};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -1139,6 +1218,13 @@ void* step_fn_wetz() {  // the original scheme has no wet-node walls
     return step_fn<S, R, F>();
   else
     return reinterpret_cast<void*>(&k_step<S, R, F | F_WETZ>);
+}
+template <typename S, typename R, int F>
+void* step_wall_fn() {  // instances with wet-node walls only (the original scheme has none)
+  if constexpr ((F & F_ORIG) != 0)
+    return nullptr;
+  else
+    return reinterpret_cast<void*>(&k_step_wall<S, R, F | F_WETZ>);
 }
 template <typename S, typename R, int F>
 void* halo_fn() { return reinterpret_cast<void*>(&k_halo<S, F & 3>); }  // no collision
@@ -1239,6 +1325,36 @@ HaloLaunch halo_launch(lbaxi_t* h, int buf) {
   return H;
 }
 
+// Handles with wet-node walls and at most this many perimeter tiles run the
+// wall part of each step in the step's launch (k_step_wall).
+constexpr int FUSE_MAX_HALO_TILES = 16;
+
+bool fuse_walls(const lbaxi_t* h) {
+  return h->fuse && h->any_wet && !(h->fields & LBAXI_ORIGINAL) &&
+         h->count[LIST_HALO] <= FUSE_MAX_HALO_TILES;
+}
+
+// Step and wall parts as one launch: one workgroup per tile of the step's
+// list (whatever the grid option), then one per perimeter tile.
+struct StepWallLaunch {
+  void* fn;
+  int grid, block;
+  StepArgs<double> a;
+  WallPart b;
+};
+
+StepWallLaunch step_wall_launch(lbaxi_t* h, const StepLaunch& L, int list) {
+  StepWallLaunch O;
+  O.fn = PICK(step_wall_fn, h->prec, h->fields);
+  O.block = L.block;
+  O.a = L.a;
+  O.b.htiles = h->d_tiles[LIST_HALO];
+  O.b.nh = h->d_counts + LIST_HALO;
+  O.b.ns = std::max(1, h->count[list]);
+  O.grid = O.b.ns + std::max(1, h->count[LIST_HALO]);
+  return O;
+}
+
 // One time step of every running lattice by direct launches: the step kernel
 // (the first step after seeding reads each node's own slots, over every
 // tile), then the halo fill of the buffer just written.
@@ -1254,12 +1370,19 @@ lbaxi_status launch_step(lbaxi_t* h, int mode) {
     }
     HIPCHK(hipEventRecord(h->ev[h->ev_used], h->stream));
   }
-  HIPCHK(hipLaunchKernel(L.fn, dim3(L.grid), dim3(L.block), args, 0, h->stream));
+  const bool fused = !h->pre && fuse_walls(h);
+  if (fused) {
+    StepWallLaunch O = step_wall_launch(h, L, LIST_RUN);
+    void* oargs[] = {&O.a, &O.b};
+    HIPCHK(hipLaunchKernel(O.fn, dim3(O.grid), dim3(O.block), oargs, 0, h->stream));
+  } else {
+    HIPCHK(hipLaunchKernel(L.fn, dim3(L.grid), dim3(L.block), args, 0, h->stream));
+  }
   if (h->prof) {
     HIPCHK(hipEventRecord(h->ev[h->ev_used + 1], h->stream));
     h->ev_used += 2;
   }
-  if (h->any_wet && !h->pre) {
+  if (h->any_wet && !h->pre && !fused) {
     StepLaunch Wl = wall_launch(h, L);
     void* wargs[] = {&Wl.a};
     HIPCHK(hipLaunchKernel(Wl.fn, dim3(Wl.grid), dim3(Wl.block), wargs, 0, h->stream));
@@ -1299,10 +1422,16 @@ lbaxi_status make_graph(lbaxi_t* h, int from) {
   for (int k = 0; k < h->K && st == LBAXI_OK; ++k) {
     const int src = from ^ (k & 1);
     StepLaunch L = step_launch(h, LIST_RUN, src, 0, true, k, 0);
-    void* args[] = {&L.a};
-    add(L.fn, L.grid, L.block, args);
+    if (fuse_walls(h)) {
+      StepWallLaunch O = step_wall_launch(h, L, LIST_RUN);
+      void* oargs[] = {&O.a, &O.b};
+      add(O.fn, O.grid, O.block, oargs);
+    } else {
+      void* args[] = {&L.a};
+      add(L.fn, L.grid, L.block, args);
+    }
     if (st != LBAXI_OK) break;
-    if (h->any_wet) {
+    if (h->any_wet && !fuse_walls(h)) {
       StepLaunch Wl = wall_launch(h, L);
       void* wargs[] = {&Wl.a};
       add(Wl.fn, Wl.grid, Wl.block, wargs);
@@ -1777,6 +1906,15 @@ lbaxi_status lbaxi_get_launch(const lbaxi_t* h, int32_t* cfg5) {
   cfg5[2] = h->grid;
   cfg5[3] = h->xcd;
   cfg5[4] = h->nt;
+  return LBAXI_OK;
+}
+
+lbaxi_status lbaxi_set_fused_walls(lbaxi_t* h, int32_t on) {
+  lbaxi_status st = check_handle(h);
+  if (st != LBAXI_OK) return st;
+  if (on != 0 && on != 1) return fail(LBAXI_EINVAL, "set_fused_walls: on must be 0 or 1");
+  h->fuse = on;
+  drop_graphs(h);
   return LBAXI_OK;
 }
 

@@ -70,6 +70,7 @@ _sigs = {
     "lbaxi_set_launch": (_st, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "lbaxi_get_launch": (_st, [_P, C.POINTER(C.c_int32)]),
     "lbaxi_set_graph_steps": (_st, [_P, C.c_int32]),
+    "lbaxi_set_fused_walls": (_st, [_P, C.c_int32]),
     "lbaxi_autotune": (_st, [_P, C.c_int32, C.POINTER(C.c_int32)]),
     "lbaxi_state_bytes": (_st, [_P, C.POINTER(C.c_size_t)]),
     "lbaxi_save": (_st, [_P, _P, C.c_size_t]),
@@ -293,6 +294,9 @@ class Lattices:
 
     def set_graph_steps(self, k: int):
         _check(_L.lbaxi_set_graph_steps(self.h, int(k)), "lbaxi_set_graph_steps")
+
+    def set_fused_walls(self, on: bool):
+        _check(_L.lbaxi_set_fused_walls(self.h, 1 if on else 0), "lbaxi_set_fused_walls")
 
     def autotune(self, steps_per_trial: int = 8):
         c = (C.c_int32 * 5)()

@@ -126,6 +126,36 @@ CASES = {
 }
 
 
+FUSED_WALL_CASES = {k: CASES[k] for k in CASES if k.endswith("_wet")}
+FUSED_WALL_CASES.update(melt_wet_mrt=lambda: dict(CASES["melt_wet"](), mrt=True),
+                        annulus_wet_mrt=lambda: dict(CASES["annulus_wet"](), mrt=True),
+                        cavity=CASES["cavity"])
+
+
+@pytest.mark.parametrize("name", sorted(FUSED_WALL_CASES))
+def test_fused_walls_bitwise(name):
+    """Small handles with wet-node walls rebuild the radial wall rows in the
+    step kernel's launch (further workgroups) instead of a wall kernel of
+    their own: the same FP64 bits either way, over direct launches and graph
+    replays (301 steps with 16-step graphs).  A halfway-wall case checks that
+    the switch leaves other handles alone."""
+    import torch
+    from paper_1003_0282_amd import lbaxi as L
+    case = FUSED_WALL_CASES[name]()
+    fields = _fields(case, 5)
+    out = []
+    for fused in (False, True):
+        lat = L.Lattices([case], 0)
+        lat.set_fused_walls(fused)
+        lat.set_graph_steps(16)
+        lat.seed(**{k: torch.as_tensor(np.asarray(v).reshape(-1)) for k, v in fields.items()})
+        lat.step(301)
+        out.append(to_np(lat.macros()))
+        lat.close()
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("prec", [0, 1])
 def test_random_state_cases(name, prec):
