@@ -215,14 +215,31 @@ constexpr int RW_KC = 32;               // input channels per stage (two K-steps
 static_assert(RW_KC == 32, "the weight tile's fragment order assumes 32 channels per stage");
 constexpr int RW_RS = RW_KC + 8;        // LDS row stride (elements): 80 bytes
 
+// Which 16-byte piece of the weight tile load f (0 <= f < 9 NT 4) moves:
+// tap t, output channel nn, 8-channel chunk q.  Within each run of 64 loads
+// (one wave) q is the slowest index, so the 16 lanes that an LDS write
+// serves together store 16 channels' chunks side by side (256 contiguous
+// bytes) rather than four chunks 512 bytes apart on the same banks; a
+// wave's 64 global reads still cover the same 16 whole weight rows.
+template <int NT>
+__device__ inline void wtile_part(int f, int& t, int& nn, int& q) {
+  static_assert(NT % 16 == 0, "runs of 64 loads cover 16 whole output channels");
+  t = f / (NT * 4);
+  const int rem = f - t * (NT * 4), lo = rem & 63;
+  q = lo >> 4;
+  nn = (rem >> 6) * 16 + (lo & 15);
+}
+
 template <int TW, int NT>
 __global__ void __launch_bounds__(256) k_conv_row(ConvArgs A) {
   constexpr int WPX = TW / 32, WCH = 4 / WPX, NW = NT / (32 * WCH);
   static_assert(WPX * WCH == 4 && NW * 32 * WCH == NT, "wave grid");
   constexpr int HX = TW + 2;                      // halo row length (pixels)
   constexpr int NH = 3 * HX * (RW_KC / 8);        // 16-byte loads of the halo
+  // the weight loads start on a wave boundary (a multiple of 64 threads)
+  constexpr int NHP = (NH + 63) / 64 * 64;
   constexpr int NWT = 9 * NT * (RW_KC / 8);       // 16-byte loads of the weights
-  constexpr int LPT = (NH + NWT + 255) / 256;
+  constexpr int LPT = (NHP + NWT + 255) / 256;
   // halo rows sh, then the weights sw, in one buffer that the epilogue
   // reuses for the output tile
   constexpr int SH = 3 * HX * RW_RS;
@@ -254,8 +271,9 @@ __global__ void __launch_bounds__(256) k_conv_row(ConvArgs A) {
         if (c < A.Ck && yy >= 0 && yy < A.H && xx >= 0 && xx < A.W)
           r[k] = *reinterpret_cast<const u16x8*>(
               A.in + (((long long)n * A.H + yy) * A.W + xx) * A.Ck + c);
-      } else if (e < NH + NWT) {
-        const int f = e - NH, t = f / (NT * 4), rem = f - t * (NT * 4), nn = rem >> 2, q = rem & 3;
+      } else if (e >= NHP && e < NHP + NWT) {
+        int t, nn, q;
+        wtile_part<NT>(e - NHP, t, nn, q);
         const int c = c0 + 8 * q;
         if (c < A.Ck)
           r[k] = *reinterpret_cast<const u16x8*>(A.wt + ((long long)t * A.Cn + n0 + nn) * A.Ck + c);
@@ -273,8 +291,9 @@ __global__ void __launch_bounds__(256) k_conv_row(ConvArgs A) {
       const int e = tid + 256 * k;
       if (e < NH)
         *reinterpret_cast<u16x8*>(sh + (e >> 2) * RW_RS + 8 * (e & 3)) = r[k];
-      else if (e < NH + NWT) {
-        const int f = e - NH, t = f / (NT * 4), rem = f - t * (NT * 4), nn = rem >> 2, q = rem & 3;
+      else if (e >= NHP && e < NHP + NWT) {
+        int t, nn, q;
+        wtile_part<NT>(e - NHP, t, nn, q);
         *reinterpret_cast<u16x8*>(sw + ((t * (NT / 32) + (nn >> 5)) * 2 + (q >> 1)) * 512 +
                                   ((q & 1) * 32 + (nn & 31)) * 8) = r[k];
       }
