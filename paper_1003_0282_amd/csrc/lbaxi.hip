@@ -987,6 +987,9 @@ lbaxi_status validate(const lbaxi_desc& d, int k) {
     return fail(s, b);
   };
   if (d.nz < 2 || d.nr < 2) return bad(LBAXI_EINVAL, "nz and nr must be >= 2");
+  // bounds that keep the size arithmetic below in range (any lattice near
+  // them is refused by the 4 GiB bound anyway)
+  if (d.nz > (1 << 24) || d.nr > (1 << 24)) return bad(LBAXI_EINVAL, "nz and nr must be <= 2^24");
   // loads and stores address a lattice by a 32-bit byte offset from a population base
   if (lattice_elems(d) * (long long)elem_size(d.prec) >= (1LL << 32))
     return bad(LBAXI_EINVAL, "lattice too large for 32-bit in-lattice byte offsets");
