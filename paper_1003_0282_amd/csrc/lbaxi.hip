@@ -462,14 +462,6 @@ __device__ inline bool radial_wall_row(const InstP& P, int j) {
 // rebuild is inlined (it needs up to 168 VGPRs at three waves per SIMD).
 constexpr int step_block_max(int F) { return (F & F_WETZ) ? 512 : 1024; }
 
-// One time step: pull (padded planes, no boundary tests), macros, collision,
-// store at the node's own slots of the other buffer.  The halo kernel then
-// completes the boundary rules for the next pull.  F_WETZ (handles with
-// wet-node walls): the z-end wall nodes of rows that also hold fluid nodes
-// are rebuilt here, by their own lanes, from the inner neighbour that the
-// same wave has just pulled (its lines are in the cache), so that the wall
-// kernel is left only the radial wall rows and every row off them is
-// written whole by this kernel.
 // One node (i, j) of a step tile: pull (or, for a wet z-end wall node, the
 // rebuild), macros, collision, store.
 template <typename S, typename R, int F>
@@ -495,7 +487,7 @@ __device__ __forceinline__ void step_node(const StepArgs<S>& A, const Tile& T, c
   finish_node<S, R, FB>(A, P, p, i, j, f, g, h, true, !(F & F_WETZ));
 }
 
-// One time step: pull (padded planes, no boundary tests), macros, collision,
+// One time step: pull (padded rows, no boundary tests), macros, collision,
 // store at the node's own slots of the other buffer.  The halo kernel then
 // completes the boundary rules for the next pull.  F_WETZ (handles with
 // wet-node walls): the z-end wall nodes of rows that also hold fluid nodes

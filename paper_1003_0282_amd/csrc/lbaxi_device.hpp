@@ -30,17 +30,17 @@ struct InstP {
   int nz, nr, cart;
   int wet;    // wall sides are wet-node walls (wall through the outer node row)
   int zou;    // with wet: radial wall nodes rebuild f by Zou-He
-  int pitch;  // row length of a padded plane (a multiple of 128 bytes)
-  int c0;     // column of node i = 0 (128 bytes into the row)
-  int plane;  // elements per padded plane: (nr + 2) rows of pitch, then the two strips
-  int sw, se;  // element offsets in a plane of the west / east ghost-column strips
+  int pitch;  // row stride: from a node to the node one row up (one row block)
+  int c0;     // column of node i = 0 (128 bytes into a padded row)
+  int plane;  // population stride: from population a to a + 1 of a node (one padded row)
+  int sw, se;  // offsets of population 0's west / east ghost-column strips
   double r0;
   double tau, tau_g, tau_h;  // paper convention: nu = tau / 3
   double rho0, mu0, nu_g;
   double om0, omg0, omh0;  // 1 / (tau + 1/2) of f, g, h (om0 is the MRT s_v)
   double s_e, s_eps, s_q;  // MRT rates of the e, epsilon and q moments
   double a0, period, phase, gbeta, T_ref;
-  long long off;      // element offset of the instance's population planes
+  long long off;      // element offset of the instance's populations
   long long off_fld;  // element offset of its packed [nr][nz] fields
   SideP side[4];
 };
@@ -404,10 +404,12 @@ __device__ inline void collide(const PR<R>& p, const Row<R>& w, const Mac<R>& m,
 }
 
 // ---- streaming ---------------------------------------------------------------
-// Each population plane holds rows j in [-1, nr] (the two ghost rows
-// included) of pitch elements, node (i, j) at (j + 1) * pitch + c0 + i with
-// rows starting on 128-byte boundaries so that a wave's stores are aligned,
-// then one strip per z-end holding that end's ghost column for rows -1..nr.
+// Population a of node (i, j), rows j in [-1, nr] (the two ghost rows
+// included), is at a * plane + (j + 1) * pitch + c0 + i, every padded row
+// starting on a 128-byte boundary so that a wave's stores are aligned; the
+// host lays the populations out in row blocks (plane = one padded row,
+// pitch = Q of them), then per z-end one strip holding that end's ghost
+// column for rows -1..nr (population a's at a * plane + sw or se).
 // The step kernel pulls f_a(x) from x - e_a for every node without any test
 // (the end columns then re-read from the strips what crosses a z-end); the
 // ghost slots are filled after every step by the halo kernel with the
@@ -415,7 +417,8 @@ __device__ inline void collide(const PR<R>& p, const Row<R>& w, const Mac<R>& m,
 
 __device__ inline int nidx(const InstP& P, int j, int i) { return (j + 1) * P.pitch + P.c0 + i; }
 
-// Element at byte offset boff from a plane base (boff < 4 GiB: a plane).
+// Element at byte offset boff from a population base (boff < 4 GiB: the
+// host refuses lattices whose populations reach 4 GiB).
 template <typename S>
 __device__ inline S ldb(const S* base, unsigned boff) {
   return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + boff);
@@ -567,7 +570,7 @@ __device__ inline ZSeg zend(const InstP& P, const InstP* Pg, bool west, int j) {
   return z;
 }
 
-// Ghost slot (element offset in a plane) of the upstream position (iu, ju)
+// Ghost slot (element offset from its population's base) of the upstream position (iu, ju)
 // outside the lattice: beyond a z-end, the west / east strip, which holds
 // the ghost column of rows -1..nr contiguously (so that filling it is a
 // coalesced write, not one element per row); else the ghost row.
@@ -577,7 +580,7 @@ __device__ inline int ghost_slot(const InstP& P, int iu, int ju) {
 
 // Boundary rules: the value node (i, j) receives in direction A when its
 // upstream node (i, j) - e_A lies outside the lattice.  A z-end is resolved
-// before the radial sides.  s points at the instance's first plane.
+// before the radial sides.  s points at the instance's population 0.
 //
 // f: moving-wall bounce-back adds 6 w_a rho0 (e_a . u_w); the axis mirrors
 // row 1; a free-slip z-end reflects e_z only.
@@ -677,7 +680,7 @@ __device__ inline double rule_h(const InstP& P, const InstP* Pg, const S* s, int
 }
 
 // Ghost slots that boundary node (i, j) pulls from, with their values:
-// at[k] is the slot of plane k (f, g, h in storage order) or -1 where the
+// at[k] is the slot of population k (f, g, h in storage order) or -1 where the
 // upstream node is a real one.
 template <typename S, int F, int A>
 __device__ inline void halo_gather(const InstP& P, const InstP* Pg, const S* s, int i, int j,
@@ -740,13 +743,13 @@ __device__ inline void zend_pull(const InstP& P, const S* __restrict__ s, int j,
 }
 
 // Populations arriving at node (i, j): a plain pull through the padded
-// planes; an end column takes what crosses its z-end from that end's strip.
+// rows; an end column takes what crosses its z-end from that end's strip.
 // pre: the buffer holds f^ itself (right after seeding), so the node reads
 // its own slots.
 template <typename S, typename R, int F>
 __device__ inline void load_node(const InstP& P, const S* __restrict__ s, int i, int j, bool pre,
                                  R* f, R* g, R* h) {
-  // Loads are written as a wave-uniform plane base plus a 32-bit byte offset
+  // Loads are written as a wave-uniform population base plus a 32-bit byte offset
   // so that they use scalar-base addressing (one offset register per row).
   const int pl = P.plane, pt = P.pitch;
   const unsigned o = (unsigned)nidx(P, j, i);
