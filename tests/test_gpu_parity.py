@@ -156,6 +156,36 @@ def test_fused_walls_bitwise(name):
         assert np.array_equal(out[0][k], out[1][k]), k
 
 
+def test_fused_walls_mixed_batch_bitwise():
+    """A small batch mixing wet-node and halfway lattices (and swirl with
+    temperature): the wall part in the step's launch skips the halfway
+    lattices' perimeter tiles and gives the same FP64 bits as the separate
+    wall kernel, per lattice."""
+    import torch
+    from paper_1003_0282_amd import lbaxi as L
+    cases = [CASES["annulus_wet"](), CASES["annulus_thermal"](),
+             dict(CASES["narrow_nz3_freeslip"]()), CASES["split_top_axis"]()]
+    cases[2]["wet"] = True
+    fields = [_fields(c, 11 + k) for k, c in enumerate(cases)]
+    out = []
+    for fused in (False, True):
+        lat = L.Lattices(cases, 0)
+        lat.set_fused_walls(fused)
+        lat.set_graph_steps(16)
+        packed = {}
+        for key in ("uz", "ur", "uth", "T", "rho"):
+            if all(key in f for f in fields):
+                packed[key] = torch.cat([torch.as_tensor(np.asarray(f[key]).reshape(-1))
+                                         for f in fields])
+        lat.seed(**packed)
+        lat.step(257)
+        out.append([{k: v.double().cpu().numpy() for k, v in m.items()} for m in lat.macros_list()])
+        lat.close()
+    for k in range(len(cases)):
+        for key in out[0][k]:
+            assert np.array_equal(out[0][k][key], out[1][k][key]), (k, key)
+
+
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("prec", [0, 1])
 def test_random_state_cases(name, prec):
