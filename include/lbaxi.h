@@ -104,7 +104,13 @@ enum {
   LBAXI_WET_WALLS = 8u,
   LBAXI_MRT = 16u,
   LBAXI_ORIGINAL = 32u,
-  LBAXI_ZOU_HE = 64u
+  LBAXI_ZOU_HE = 64u,
+  /* Memory layout of this lattice's populations: each population's rows
+   * contiguous (planes) instead of the default row blocks (the rows of all
+   * populations of one lattice row side by side, which the step kernel
+   * streams faster).  Same results bit for bit.  A lattice whose row
+   * blocks would take 4 GiB or more is stored as planes anyway. */
+  LBAXI_PLANES = 128u
 };
 enum {
   LBAXI_SIDE_AXIS = 0,     /* south side only, r0 = 0: specular axis */
@@ -137,7 +143,7 @@ typedef struct {
   int32_t nz, nr;   /* nodes along z and r, each >= 2 */
   double r0;        /* radius of node row 0; 0 with an axis south side */
   int32_t prec;     /* LBAXI_FP64 / _FP32 / _FP32_FAST (same for a whole batch) */
-  uint32_t fields;  /* LBAXI_SWIRL | _THERMAL | _CARTESIAN | _WET_WALLS | _MRT | _ORIGINAL
+  uint32_t fields;  /* LBAXI_SWIRL | _THERMAL | _CARTESIAN | _WET_WALLS | _MRT | _ORIGINAL | _PLANES
                        | _ZOU_HE */
   double tau;       /* tau_s of f */
   double tau_g;     /* tau_s of g, 0 -> paper default */
@@ -166,8 +172,9 @@ const char* lbaxi_strerror(lbaxi_status s);
  * field per lattice for Eq. (57).  A buffer holds each lattice's populations
  * in row blocks (the padded rows of all Q populations of one lattice row,
  * one after the other, for rows -1..nr, then two blocks of z-end ghost
- * columns); one lattice's populations may take at most 4 GiB (32-bit byte
- * offsets inside a lattice), EINVAL beyond. */
+ * columns), or, with LBAXI_PLANES and for lattices whose row blocks would
+ * take 4 GiB or more, in planes (each population's rows contiguous); one
+ * lattice may hold fewer than 2^31 population elements, EINVAL beyond. */
 lbaxi_status lbaxi_workspace_bytes(int32_t n, const lbaxi_desc* descs, size_t* bytes);
 
 /* Create a handle over n lattices (all the same prec, the same SWIRL and
@@ -175,8 +182,8 @@ lbaxi_status lbaxi_workspace_bytes(int32_t n, const lbaxi_desc* descs, size_t* b
  * WET_WALLS may differ between lattices), carving
  * d_workspace (>= lbaxi_workspace_bytes, 256-byte aligned) and enqueuing on
  * hip_stream (a hipStream_t; NULL = the null stream).  Validates every
- * descriptor: EINVAL for bad sizes (a lattice above 4 GiB of populations
- * included) or side combinations (axis only as south
+ * descriptor: EINVAL for bad sizes (2^31 population elements or more in
+ * one lattice included) or side combinations (axis only as south
  * with r0 = 0, periodic only on both z-ends together, free slip only on
  * z-ends), ERANGE when some relaxation rate (1 + tau e_r / r)/(tau + 1/2) of
  * f (BGK), g or h, or an MRT rate, leaves (0, 2).  The lattices start at rest (lbaxi_seed with NULL

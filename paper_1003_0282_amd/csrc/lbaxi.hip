@@ -907,17 +907,51 @@ long long halo_tiles(const std::vector<lbaxi_desc>& d) {
 // plane stride is one padded row and the row stride one row block: the
 // populations a wave pulls for a tile lie in three nearby row blocks rather
 // than in Q planes a lattice apart.
+//
+// Plane layout (LBAXI_PLANES, and every lattice whose row blocks would take
+// 4 GiB or more): each population's padded rows -1..nr follow each other
+// (one plane), then that population's west and east strips; the plane
+// stride is a whole plane and the row stride one padded row.  Byte offsets
+// then stay inside one population's plane, so such a lattice may hold up to
+// 2^31 population elements.  The kernels see only the strides and strip
+// offsets and run either layout unchanged.
 int row_lead(const lbaxi_desc& x) { return 128 / (x.prec == LBAXI_FP64 ? 8 : 4); }
 int strip_len(const lbaxi_desc& x) {
   const int q = row_lead(x);
   return (x.nr + 2 + q - 1) / q * q;
 }
-int row_pitch(const lbaxi_desc& x) {
+int padded_row(const lbaxi_desc& x) {
   const int q = row_lead(x);
-  return std::max((q + x.nz + 1 + q - 1) / q * q, strip_len(x));
+  return (q + x.nz + 1 + q - 1) / q * q;
 }
-long long row_block(const lbaxi_desc& x) { return (long long)n_planes(x.fields) * row_pitch(x); }
-long long lattice_elems(const lbaxi_desc& x) { return (long long)(x.nr + 4) * row_block(x); }
+
+struct PopLayout {
+  long long plane, pitch, sw, se, total;  // elements (strides, strip offsets, lattice size)
+};
+
+PopLayout pop_layout(const lbaxi_desc& x) {
+  PopLayout L;
+  const long long np = n_planes(x.fields), sl = strip_len(x);
+  const long long rb = std::max<long long>(padded_row(x), sl);  // row-block padded row
+  const bool planes = (x.fields & LBAXI_PLANES) ||
+                      (x.nr + 4) * np * rb * (long long)elem_size(x.prec) >= (1LL << 32);
+  if (planes) {
+    const long long rp = padded_row(x);
+    L.pitch = rp;
+    L.sw = (x.nr + 2) * rp;
+    L.se = L.sw + sl;
+    L.plane = L.sw + 2 * sl;
+    L.total = np * L.plane;
+  } else {
+    L.plane = rb;
+    L.pitch = np * rb;
+    L.sw = (x.nr + 2) * L.pitch;
+    L.se = L.sw + L.pitch;
+    L.total = (x.nr + 4) * L.pitch;
+  }
+  return L;
+}
+long long lattice_elems(const lbaxi_desc& x) { return pop_layout(x).total; }
 
 // Device workspace: parameters, three work lists (all tiles / tiles of
 // running lattices / halo chunks of running lattices) with their counts,
@@ -982,12 +1016,13 @@ lbaxi_status validate(const lbaxi_desc& d, int k) {
   // bounds that keep the size arithmetic below in range (any lattice near
   // them is refused by the 4 GiB bound anyway)
   if (d.nz > (1 << 24) || d.nr > (1 << 24)) return bad(LBAXI_EINVAL, "nz and nr must be <= 2^24");
-  // loads and stores address a lattice by a 32-bit byte offset from a population base
-  if (lattice_elems(d) * (long long)elem_size(d.prec) >= (1LL << 32))
-    return bad(LBAXI_EINVAL, "lattice too large for 32-bit in-lattice byte offsets");
   if (d.prec != LBAXI_FP64 && d.prec != LBAXI_FP32 && d.prec != LBAXI_FP32_FAST)
     return bad(LBAXI_EINVAL, "bad prec");
-  if (d.fields & ~127u) return bad(LBAXI_EINVAL, "unknown field bits");
+  if (d.fields & ~255u) return bad(LBAXI_EINVAL, "unknown field bits");
+  // element indices inside a lattice are 32-bit (byte offsets stay inside a
+  // population's plane, or, in row blocks, below 4 GiB by construction)
+  if (lattice_elems(d) >= (1LL << 31))
+    return bad(LBAXI_EINVAL, "lattice too large: 2^31 population elements or more");
   if ((d.fields & LBAXI_ZOU_HE) &&
       (!(d.fields & LBAXI_WET_WALLS) || d.west.kind != LBAXI_SIDE_PERIODIC ||
        (d.south.kind == LBAXI_SIDE_WALL && d.south.u_r != 0.0) || d.north.u_r != 0.0))
@@ -1053,11 +1088,12 @@ InstP make_inst(const lbaxi_desc& d, long long off, long long off_fld) {
   memset(&P, 0, sizeof P);
   P.nz = d.nz;
   P.nr = d.nr;
-  P.pitch = (int)row_block(d);  // row stride
+  const PopLayout PL = pop_layout(d);
+  P.pitch = (int)PL.pitch;  // row stride
   P.c0 = row_lead(d);
-  P.plane = row_pitch(d);        // population (plane) stride
-  P.sw = (d.nr + 2) * P.pitch;   // strip blocks after the ghost row nr
-  P.se = P.sw + P.pitch;
+  P.plane = (int)PL.plane;  // population (plane) stride
+  P.sw = (int)PL.sw;        // population 0's ghost-column strips
+  P.se = (int)PL.se;
   P.cart = (d.fields & LBAXI_CARTESIAN) ? 1 : 0;
   P.wet = (d.fields & LBAXI_WET_WALLS) ? 1 : 0;
   P.zou = (d.fields & LBAXI_ZOU_HE) ? 1 : 0;

@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
                       "(the HIP library has no CPU fallback)")
 
 FP64, FP32, FP32_FAST = 0, 1, 2
-SWIRL, THERMAL, CARTESIAN, WET_WALLS, MRT, ORIGINAL, ZOU_HE = 1, 2, 4, 8, 16, 32, 64
+SWIRL, THERMAL, CARTESIAN, WET_WALLS, MRT, ORIGINAL, ZOU_HE, PLANES = 1, 2, 4, 8, 16, 32, 64, 128
 SIDE = {"axis": 0, "wall": 1, "periodic": 2, "freeslip": 3}
 RUNNING, CONVERGED, DIVERGED, CAPPED = 0, 1, 2, 3
 STATUS_NAMES = {RUNNING: "running", CONVERGED: "converged", DIVERGED: "diverged",
@@ -129,7 +129,7 @@ def make_desc(case: dict, prec: int) -> Desc:
                 | (CARTESIAN if case.get("cartesian") else 0)
                 | (WET_WALLS if case.get("wet") else 0) | (MRT if case.get("mrt") else 0)
                 | (ORIGINAL if case.get("original") else 0)
-                | (ZOU_HE if case.get("zou_he") else 0))
+                | (ZOU_HE if case.get("zou_he") else 0) | (PLANES if case.get("planes") else 0))
     d.tau = float(case["tau"])
     d.tau_g = float(case.get("tau_g", 0.0))
     d.tau_h = float(case.get("tau_h", 0.0))

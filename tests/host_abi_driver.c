@@ -64,7 +64,8 @@ int main(void) {
   char name[96];
   const uint32_t field_sets[] = {0, LBAXI_SWIRL, LBAXI_SWIRL | LBAXI_THERMAL, LBAXI_MRT,
                                  LBAXI_SWIRL | LBAXI_MRT, LBAXI_ORIGINAL, LBAXI_WET_WALLS,
-                                 LBAXI_WET_WALLS | LBAXI_SWIRL | LBAXI_THERMAL, LBAXI_CARTESIAN};
+                                 LBAXI_WET_WALLS | LBAXI_SWIRL | LBAXI_THERMAL, LBAXI_CARTESIAN,
+                                 LBAXI_PLANES, LBAXI_PLANES | LBAXI_SWIRL | LBAXI_THERMAL};
   for (int p = 0; p < 3; ++p)
     for (unsigned k = 0; k < sizeof field_sets / sizeof field_sets[0]; ++k) {
       lbaxi_desc d = pipe_desc(37 + 5 * (int)k, 21 + p, p, field_sets[k]);
@@ -78,11 +79,20 @@ int main(void) {
     batch[k] = pipe_desc(rnd(2, 3 * nr + 2), nr, LBAXI_FP32, LBAXI_SWIRL);
   }
   expect("workspace of 64 uneven lattices", lbaxi_workspace_bytes(64, batch, &b), 1);
-  /* the largest lattice whose populations fit 32-bit byte offsets, and one above */
+  /* row blocks below 4 GiB, planes above it, and the 2^31-element bound */
   lbaxi_desc big = pipe_desc(16384, 7200, LBAXI_FP32, 0);
-  expect("workspace 16384 x 7200 FP32 (just below 4 GiB)", lbaxi_workspace_bytes(1, &big, &b), 1);
+  expect("workspace 16384 x 7200 FP32 (row blocks)", lbaxi_workspace_bytes(1, &big, &b), 1);
   big.nr = 7300;
-  expect("workspace 16384 x 7300 FP32 (above 4 GiB)", lbaxi_workspace_bytes(1, &big, &b), 0);
+  expect("workspace 16384 x 7300 FP32 (planes)", lbaxi_workspace_bytes(1, &big, &b), 1);
+  big.fields = LBAXI_PLANES;
+  expect("workspace 16384 x 7300 FP32, planes asked", lbaxi_workspace_bytes(1, &big, &b), 1);
+  big.nr = 14000;
+  big.fields = 0;
+  expect("workspace 16384 x 14000 FP64 (below 2^31)", (big.prec = LBAXI_FP64,
+         lbaxi_workspace_bytes(1, &big, &b)), 1);
+  big.nr = 14600;
+  expect("workspace 16384 x 14600 FP64 (above 2^31)", lbaxi_workspace_bytes(1, &big, &b), 0);
+  big.prec = LBAXI_FP32;
   big.nr = 1 << 30;
   expect("workspace nr = 2^30", lbaxi_workspace_bytes(1, &big, &b), 0);
   big.nr = 7200;
@@ -93,7 +103,7 @@ int main(void) {
   expect("nz = 1", lbaxi_workspace_bytes(1, &d, &b), 0);
   d = pipe_desc(8, 8, 7, 0);
   expect("unknown precision", lbaxi_workspace_bytes(1, &d, &b), 0);
-  d = pipe_desc(8, 8, LBAXI_FP64, 1u << 20);
+  d = pipe_desc(8, 8, LBAXI_FP64, 1u << 8);
   expect("unknown field bit", lbaxi_workspace_bytes(1, &d, &b), 0);
   d = pipe_desc(8, 8, LBAXI_FP64, 0);
   d.r0 = 2.0;

@@ -186,6 +186,39 @@ def test_fused_walls_mixed_batch_bitwise():
             assert np.array_equal(out[0][k][key], out[1][k][key]), (k, key)
 
 
+PLANE_CASES = {k: CASES[k] for k in ("cavity", "melt_wet", "annulus_wet", "split_top_axis",
+                                      "narrow_nz3_wet", "pipe_periodic_force", "planar")}
+PLANE_CASES.update(melt_mrt=lambda: dict(CASES["melt"](), mrt=True),
+                   pipe_original=lambda: dict(CASES["pipe_periodic_force"](), original=True))
+
+
+@pytest.mark.parametrize("name", sorted(PLANE_CASES))
+def test_plane_layout_bitwise(name):
+    """The kernels see only the population and row strides: a lattice stored
+    as planes (LBAXI_PLANES) gives the same FP64 bits as in row blocks, over
+    direct launches, graph replays and checkpoint-free 301-step runs."""
+    case = PLANE_CASES[name]()
+    fields = _fields(case, 9)
+    a = to_np(gpu_run([case], 301, 0, [fields], graph=16).macros())
+    b = to_np(gpu_run([dict(case, planes=True)], 301, 0, [fields], graph=16).macros())
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_plane_layout_mixed_batch_bitwise():
+    """One batch with lattices in both layouts: each lattice's FP64 bits
+    equal those of the all-row-block batch."""
+    cases = [CASES["cavity"](), W.cavity(20, 133, 250.0), W.cavity(64, 65, 900.0)]
+    fields = [_fields(c, 20 + k) for k, c in enumerate(cases)]
+    ref = gpu_run(cases, 211, 0, fields).macros_list()
+    mixed = [cases[0], dict(cases[1], planes=True), cases[2]]
+    got = gpu_run(mixed, 211, 0, fields).macros_list()
+    for k in range(len(cases)):
+        for key in ref[k]:
+            assert np.array_equal(ref[k][key].double().cpu().numpy(),
+                                  got[k][key].double().cpu().numpy()), (k, key)
+
+
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("prec", [0, 1])
 def test_random_state_cases(name, prec):

@@ -131,13 +131,33 @@ def test_workspace_grows_with_batch(L):
 
 
 def test_largest_lattice_accepted(L):
-    """In-lattice byte offsets are 32-bit: a lattice whose populations (nr + 4
-    row blocks of 9 padded rows of 16448 floats at nz = 16384) reach 4 GiB is
-    refused, one just below is accepted (FP32, f only)."""
-    ok = W.base_case(16384, 7200, 0.8, a0=1e-7)      # 7204 * 9 * 16448 * 4 B < 2^32
-    too_big = W.base_case(16384, 7300, 0.8, a0=1e-7)  # 7304 * 9 * 16448 * 4 B > 2^32
+    """Element indices inside a lattice are 32-bit: a lattice of 2^31
+    population elements or more is refused, one just below is accepted (it
+    is stored as planes, since its row blocks would pass 4 GiB).  At
+    nz = 16384 a padded row holds 16448 floats or 16416 doubles; f only."""
+    ok = W.base_case(16384, 14000, 0.8, a0=1e-7)       # 9 planes of 14002 rows + strips < 2^31
+    too_big = W.base_case(16384, 14600, 0.8, a0=1e-7)  # 9 * 14602 * 16448 > 2^31
     assert _status(L, [ok], prec=1) == 0
     assert _status(L, [too_big], prec=1) == -1
-    # the bound counts bytes: the accepted FP32 lattice is refused in FP64
-    assert _status(L, [ok], prec=0) == -1
-    assert _status(L, [W.base_case(16384, 3600, 0.8, a0=1e-7)], prec=0) == 0
+    # the bound counts elements, not bytes: the same in FP64
+    assert _status(L, [ok], prec=0) == 0
+    assert _status(L, [too_big], prec=0) == -1
+
+
+def test_layout_sizes(L):
+    """Row blocks take nr + 4 blocks of Q padded rows; planes Q planes of
+    nr + 2 padded rows and two strips; a lattice whose row blocks would pass
+    4 GiB takes the plane layout by itself."""
+    small = W.base_case(100, 50, 0.8)
+    rb = L.workspace_bytes([small], 1)
+    pl = L.workspace_bytes([dict(small, planes=True)], 1)
+    # rows of 100 floats pad to 160 (lead-in 32, 101 slots, 128-byte
+    # rounding), strips of 52 to 64: row blocks 54 x 9 x 160 elements,
+    # planes 9 x (52 x 160 + 2 x 64); two buffers, each 64-element aligned
+    # within 256-byte aligned workspace slices
+    d = (54 * 9 * 160 - 9 * (52 * 160 + 2 * 64)) * 4 * 2
+    assert abs((rb - pl) - d) <= 2 * 256, (rb, pl, d)
+    big = W.base_case(16384, 7300, 0.8)
+    assert L.workspace_bytes([big], 1) == L.workspace_bytes([dict(big, planes=True)], 1)
+    mid = W.base_case(16384, 7200, 0.8)  # row blocks fit below 4 GiB
+    assert L.workspace_bytes([mid], 1) != L.workspace_bytes([dict(mid, planes=True)], 1)
