@@ -36,3 +36,29 @@ def test_bytes_per_update():
     assert bench.bytes_per_update(dict(pipe, original=True), 0) == 176
     assert bench.bytes_per_update(W.cavity(16, 24, 100.0), 1) == 104
     assert bench.bytes_per_update(W.melt(10.0, 10.0, 1e3), 1) == 136
+
+
+def test_traffic_key_covers_device_code_and_layout(tmp_path, monkeypatch):
+    """The key of the traffic files changes with the solver's device code and
+    with the host code that lays the populations out, and not with the rest
+    of the host runtime (the counters depend only on the first two)."""
+    src = os.path.join(ROOT, "paper_1003_0282_amd", "csrc")
+    text = {f: open(os.path.join(src, f)).read() for f in os.listdir(src) if f.startswith("lbaxi")}
+    hip = text["lbaxi.hip"]
+    assert "\n// host runtime\n" in hip
+    cut = hip.index("\n// host runtime\n")
+    a = hip.index("\n// Row-blocked layout", cut)
+    b = hip.index("\n// Device workspace", a)
+    pkg = tmp_path / "paper_1003_0282_amd" / "csrc"
+    pkg.mkdir(parents=True)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+
+    def key(h):
+        for f, t in text.items():
+            (pkg / f).write_text(h if f == "lbaxi.hip" else t)
+        return bench.kernel_hash()
+
+    base = key(hip)
+    assert key(hip[:cut // 2] + " " + hip[cut // 2:]) != base          # device code
+    assert key(hip[:(a + b) // 2] + " " + hip[(a + b) // 2:]) != base  # layout
+    assert key(hip[:b + 40] + " " + hip[b + 40:]) == base              # rest of the host runtime
